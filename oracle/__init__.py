@@ -1,0 +1,156 @@
+"""Test infrastructure: the CPU oracle for the 15 non-induced orbit counts.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the HIP library
+(``paper_2606_29651_amd``) and never imports it.
+
+Contents
+  * ``brute``          -- definition-level brute force in pure Python (tiny graphs).
+  * ``niorca_ref.c``   -- plain C: the definition by connected-set enumeration
+                          (``enum_count``) and the paper's three-stage method
+                          (``stage1``/``stage2``/``stage3``/``count``), plus
+                          ``orbits_at`` for selected vertices of large graphs.
+  * ``build()``        -- compiles ``niorca_ref.c`` with gcc into
+                          ``oracle/libniorca_ref.so``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "niorca_ref.c")
+_LIB = os.path.join(_HERE, "libniorca_ref.so")
+_lib = None
+
+F_NAMES = ["f12_14", "f10_13", "f13_14", "f11_13", "f5_8", "f6_9", "f9_12", "f4_8", "f8_12"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle (gcc -O2 -fopenmp) and return the library path."""
+    global _lib
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
+               "-Wno-unused-function", "-o", tmp, _SRC]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+        _lib = None
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        lib.oref_enum_count.argtypes = [i32, P, P, P]
+        lib.oref_stage1.argtypes = [i32, P, P, P]
+        lib.oref_stage2.argtypes = [i32, P, P, P]
+        lib.oref_stage3.argtypes = [i32, P, P, P, P, P, P]
+        lib.oref_count.argtypes = [i32, P, P, P]
+        lib.oref_orbits_at.argtypes = [i32, P, P, i32, P, P, P, P]
+        lib.oref_set_threads.argtypes = [ctypes.c_int]
+        lib.oref_num_threads.restype = ctypes.c_int
+        for name in ("oref_enum_count", "oref_stage1", "oref_stage2", "oref_stage3",
+                     "oref_count", "oref_orbits_at"):
+            getattr(lib, name).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _csr(row_ptr, col):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    n = rp.shape[0] - 1
+    if n < 0 or rp[-1] != cl.shape[0]:
+        raise ValueError("malformed CSR")
+    return n, rp, cl
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+def set_threads(t: int) -> None:
+    _load().oref_set_threads(int(t))
+
+
+def num_threads() -> int:
+    return int(_load().oref_num_threads())
+
+
+def enum_count(row_ptr, col) -> np.ndarray:
+    """psi int64[n, 15] by enumerating every connected vertex set (the definition)."""
+    n, rp, cl = _csr(row_ptr, col)
+    psi = np.zeros((max(n, 0), 15), dtype=np.int64)
+    _check(_load().oref_enum_count(n, _ptr(rp), _ptr(cl), _ptr(psi)), "enum_count")
+    return psi
+
+
+def stage1(row_ptr, col) -> np.ndarray:
+    """Per-CSR-slot triangle counts t(e), int32[2m] (Algorithm 1)."""
+    n, rp, cl = _csr(row_ptr, col)
+    tri = np.zeros(cl.shape[0], dtype=np.int32)
+    _check(_load().oref_stage1(n, _ptr(rp), _ptr(cl), _ptr(tri)), "stage1")
+    return tri
+
+
+def stage2(row_ptr, col) -> np.ndarray:
+    """Per-vertex 4-clique counts, int64[n] (Algorithm 2)."""
+    n, rp, cl = _csr(row_ptr, col)
+    k4 = np.zeros(n, dtype=np.int64)
+    _check(_load().oref_stage2(n, _ptr(rp), _ptr(cl), _ptr(k4)), "stage2")
+    return k4
+
+
+def stage3(row_ptr, col, tri, k4, want_fvars: bool = False):
+    """psi int64[n, 15] (and f-variables int64[n, 9]) from Stage I/II results."""
+    n, rp, cl = _csr(row_ptr, col)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    k4 = np.ascontiguousarray(k4, dtype=np.int64)
+    psi = np.zeros((n, 15), dtype=np.int64)
+    fv = np.zeros((n, 9), dtype=np.int64) if want_fvars else None
+    _check(_load().oref_stage3(n, _ptr(rp), _ptr(cl), _ptr(tri), _ptr(k4), _ptr(psi),
+                               _ptr(fv) if fv is not None else None), "stage3")
+    return (psi, fv) if want_fvars else psi
+
+
+def count(row_ptr, col) -> np.ndarray:
+    """psi int64[n, 15] by the paper's three stages."""
+    n, rp, cl = _csr(row_ptr, col)
+    psi = np.zeros((n, 15), dtype=np.int64)
+    _check(_load().oref_count(n, _ptr(rp), _ptr(cl), _ptr(psi)), "count")
+    return psi
+
+
+def count_with_intermediates(row_ptr, col):
+    """(psi, tri, k4, fvars) of the paper's three stages."""
+    tri = stage1(row_ptr, col)
+    k4 = stage2(row_ptr, col)
+    psi, fv = stage3(row_ptr, col, tri, k4, want_fvars=True)
+    return psi, tri, k4, fv
+
+
+def orbits_at(row_ptr, col, xs, want_fvars: bool = False):
+    """psi int64[len(xs), 15] for selected vertices of a (possibly large) graph."""
+    n, rp, cl = _csr(row_ptr, col)
+    xs = np.ascontiguousarray(xs, dtype=np.int32)
+    psi = np.zeros((xs.shape[0], 15), dtype=np.int64)
+    fv = np.zeros((xs.shape[0], 9), dtype=np.int64) if want_fvars else None
+    scratch = np.zeros(max(cl.shape[0], 1), dtype=np.int32)
+    _check(_load().oref_orbits_at(n, _ptr(rp), _ptr(cl), xs.shape[0], _ptr(xs), _ptr(psi),
+                                  _ptr(fv) if fv is not None else None, _ptr(scratch)),
+           "orbits_at")
+    return (psi, fv) if want_fvars else psi

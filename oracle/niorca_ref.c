@@ -1,0 +1,584 @@
+/*
+ * Test infrastructure: the CPU oracle for per-vertex non-induced orbit counts.
+ *
+ * Only the test suite, the smoke check and the bench's CPU-baseline leg may load
+ * this file's library.  It is not part of the product path, includes no header
+ * of the HIP library and shares no code with it.
+ *
+ * Two independent formulations live here:
+ *
+ *  1. oref_enum_*  -- the definition (Section 3, Definitions 3-5): every
+ *     connected vertex set S, |S| = 2..4, is enumerated once (each set is grown
+ *     from its smallest vertex through vertices larger than it), and every edge
+ *     subset of E[S] that connects S is one non-induced occurrence, classified by
+ *     (edge count, degree sequence) into the 15 orbits.  Exact and plain, usable on
+ *     sparse graphs of a few thousand vertices and on small dense graphs.
+ *
+ *  2. oref_stage1/2/3, oref_count, oref_orbits_at -- the paper's three-stage
+ *     method: Stage I per-edge triangle counts (Algorithm 1), Stage II K4 counts
+ *     (Algorithm 2), Stage III f-variable probing over the four substructures of
+ *     Table 1 followed by the non-induced equations of Section 5 and the Appendix.
+ *
+ * Readings taken where the text is silent, ambiguous or garbled (each one is
+ * checked against formulation 1 and Python brute force by the tests):
+ *   - Algorithm 2: the neigh buffer is emptied for every (x, y) pair, the id
+ *     tests are strict (y > x, z > y) and the pair loop starts after i, so each
+ *     4-clique is found once, from its smallest vertex.
+ *   - psi_1, psi_2, psi_3 are the non-induced 3-vertex counts found while probing:
+ *     psi_1 sums d(y)-1 over neighbours y, psi_2 counts neighbour pairs, psi_3
+ *     counts triangles at x.
+ *   - Per occurrence terms of the f-variables (Table 1; the figure of the four
+ *     substructures is missing):
+ *       Triangle 1 (triangle {x,y,z} seen once, y > z):
+ *           f12_14 += t(yz) - 1;  f10_13 += (d(y)-1-t(yz)) + (d(z)-1-t(yz))
+ *       Triangle 2 (each triangle at x once):
+ *           f13_14 += (t(xy)-1) + (t(xz)-1)
+ *           f11_13 += (d(x)-1-t(xy)) + (d(x)-1-t(xz))
+ *       Two-Star (unordered {y,z} in N(x), y and z not adjacent):
+ *           f5_8 += (d(y)-1-t(xy)) + (d(z)-1-t(xz))
+ *       Path (y in N(x), z in N(y), z != x, z not in N(x)):
+ *           f6_9 += d(y)-2-t(xy)      (the triangles excluded are those on e_xy;
+ *                                      reading them on e_yz breaks psi_6)
+ *           f9_12 += t(yz);  f4_8 += d(z)-1-t(yz);  f8_12 += common[z]-1
+ *     where common[z] = |N(x) and N(z)| for z outside N(x) and z != x, counted
+ *     over every y (no ordering).
+ *   - Every halving in the equations is exact: the numerator is checked to be
+ *     even and the call fails with ORACLE_EODD otherwise.
+ *
+ * Numbers are int64 throughout.  Graphs are simple, symmetric CSR with each row
+ * sorted ascending (row_ptr int64[n+1], col int32[row_ptr[n]]).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef int64_t i64;
+typedef int32_t i32;
+
+enum { ORACLE_OK = 0, ORACLE_EINVAL = -1, ORACLE_ENOMEM = -2, ORACLE_EODD = -3 };
+
+/* f-variable order used by every function here (Table 1 order). */
+enum { F12_14 = 0, F10_13, F13_14, F11_13, F5_8, F6_9, F9_12, F4_8, F8_12, NFV };
+
+int oref_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oref_set_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
+/* Slot of b in the sorted row of a, or -1. */
+static i64 slot_of(const i64 *rp, const i32 *col, i32 a, i32 b)
+{
+    i64 lo = rp[a], hi = rp[a + 1];
+    while (lo < hi) {
+        i64 mid = lo + (hi - lo) / 2;
+        if (col[mid] < b) lo = mid + 1; else hi = mid;
+    }
+    return (lo < rp[a + 1] && col[lo] == b) ? lo : -1;
+}
+
+static i64 deg_of(const i64 *rp, i32 v) { return rp[v + 1] - rp[v]; }
+
+/* ------------------------------------------------------------------------- */
+/* Formulation 1: the definition, by enumerating connected vertex sets.       */
+/* ------------------------------------------------------------------------- */
+
+/* Orbit of each vertex of a connected occurrence on k vertices with edge mask
+ * over the pairs of S (pair p = (pi[p], pj[p])).  Returns 0 on success. */
+static const int PI4[6] = {0, 0, 0, 1, 1, 2};
+static const int PJ4[6] = {1, 2, 3, 2, 3, 3};
+
+static int occurrence_orbits(int k, int npairs, const int *pi, const int *pj,
+                             unsigned mask, int orb[4])
+{
+    int deg[4] = {0, 0, 0, 0};
+    int ne = 0;
+    for (int p = 0; p < npairs; p++)
+        if (mask >> p & 1u) { deg[pi[p]]++; deg[pj[p]]++; ne++; }
+    for (int v = 0; v < k; v++) if (deg[v] == 0) return -1;
+    /* connectivity by repeated relaxation */
+    int seen = 1, grew = 1;
+    while (grew) {
+        grew = 0;
+        for (int p = 0; p < npairs; p++) {
+            if (!(mask >> p & 1u)) continue;
+            int a = pi[p], b = pj[p];
+            if ((seen >> a & 1) != (seen >> b & 1)) { seen |= (1 << a) | (1 << b); grew = 1; }
+        }
+    }
+    if (seen != (1 << k) - 1) return -1;
+    if (k == 2) { orb[0] = orb[1] = 0; return 0; }
+    if (k == 3) {
+        for (int v = 0; v < 3; v++) orb[v] = (ne == 3) ? 3 : (deg[v] == 1 ? 1 : 2);
+        return 0;
+    }
+    int maxd = 0;
+    for (int v = 0; v < 4; v++) if (deg[v] > maxd) maxd = deg[v];
+    for (int v = 0; v < 4; v++) {
+        int d = deg[v];
+        switch (ne) {
+        case 3:
+            if (maxd == 3) orb[v] = (d == 3) ? 7 : 6;          /* 3-star */
+            else orb[v] = (d == 1) ? 4 : 5;                    /* 4-path */
+            break;
+        case 4:
+            if (maxd == 2) orb[v] = 8;                         /* 4-cycle */
+            else orb[v] = (d == 1) ? 9 : (d == 2 ? 10 : 11);   /* tailed triangle */
+            break;
+        case 5: orb[v] = (d == 2) ? 12 : 13; break;           /* diamond */
+        case 6: orb[v] = 14; break;                            /* 4-clique */
+        default: return -1;
+        }
+    }
+    return 0;
+}
+
+static void credit_set(const i64 *rp, const i32 *col, int k, const i32 *S, i64 *psi)
+{
+    static const int PI3[3] = {0, 0, 1}, PJ3[3] = {1, 2, 2};
+    const int *pi = (k == 4) ? PI4 : PI3, *pj = (k == 4) ? PJ4 : PJ3;
+    int npairs = k * (k - 1) / 2;
+    unsigned present = 0;
+    for (int p = 0; p < npairs; p++)
+        if (slot_of(rp, col, S[pi[p]], S[pj[p]]) >= 0) present |= 1u << p;
+    /* every subset of the present pairs */
+    for (unsigned sub = present;; sub = (sub - 1) & present) {
+        int orb[4];
+        if (sub && occurrence_orbits(k, npairs, pi, pj, sub, orb) == 0)
+            for (int v = 0; v < k; v++) {
+#pragma omp atomic
+                psi[(i64)S[v] * 15 + orb[v]] += 1;
+            }
+        if (sub == 0) break;
+    }
+}
+
+/* Grow connected sets from their smallest vertex: every vertex added is larger
+ * than S[0] and adjacent to the set; a set is reported once because extension
+ * candidates are only neighbours of the newest vertex that are not adjacent to
+ * any earlier member (the exclusive-neighbourhood rule), as in ESU. */
+static int in_set(const i32 *S, int k, i32 v) { for (int i = 0; i < k; i++) if (S[i] == v) return 1; return 0; }
+
+static int adjacent_to_set(const i64 *rp, const i32 *col, const i32 *S, int k, i32 v)
+{
+    for (int i = 0; i < k; i++) if (slot_of(rp, col, S[i], v) >= 0) return 1;
+    return 0;
+}
+
+static void extend(const i64 *rp, const i32 *col, i32 *S, int k, i32 *ext, int next, i64 *psi,
+                   i32 *buf, i64 bufcap)
+{
+    credit_set(rp, col, k, S, psi);
+    if (k == 4) return;
+    /* ext[0..next) is the current extension set */
+    for (int i = 0; i < next; i++) {
+        i32 w = ext[i];
+        /* new extension: remaining ext after w, plus exclusive neighbours of w */
+        int nn = 0;
+        i32 *ne = buf;
+        for (int j = i + 1; j < next; j++) ne[nn++] = ext[j];
+        for (i64 s = rp[w]; s < rp[w + 1]; s++) {
+            i32 u = col[s];
+            if (u <= S[0] || in_set(S, k, u) || u == w) continue;
+            if (adjacent_to_set(rp, col, S, k, u)) continue;
+            int dup = 0;
+            for (int j = 0; j < nn; j++) if (ne[j] == u) { dup = 1; break; }
+            if (!dup) {
+                if (nn >= bufcap) return; /* cannot happen: cap sized by caller */
+                ne[nn++] = u;
+            }
+        }
+        S[k] = w;
+        extend(rp, col, S, k + 1, ne, nn, psi, buf + nn, bufcap - nn);
+    }
+}
+
+/* psi int64[n*15] (zeroed here).  Enumerates each connected vertex set once. */
+int oref_enum_count(i32 n, const i64 *rp, const i32 *col, i64 *psi)
+{
+    if (n < 0 || (n > 0 && (!rp || !col)) || !psi) return ORACLE_EINVAL;
+    memset(psi, 0, sizeof(i64) * 15 * (size_t)n);
+    i64 dmax = 0;
+    for (i32 v = 0; v < n; v++) if (deg_of(rp, v) > dmax) dmax = deg_of(rp, v);
+    i64 cap = 4 * (3 * dmax + 4);
+    int err = 0;
+#pragma omp parallel
+    {
+        i32 *buf = (i32 *)malloc(sizeof(i32) * (size_t)cap);
+        if (!buf) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (i32 v = 0; v < n; v++) {
+                i32 S[4];
+                S[0] = v;
+                int nn = 0;
+                for (i64 s = rp[v]; s < rp[v + 1]; s++) if (col[s] > v) buf[nn++] = col[s];
+                extend(rp, col, S, 1, buf, nn, psi, buf + nn, cap - nn);
+            }
+            free(buf);
+        }
+    }
+    return err ? ORACLE_ENOMEM : ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Formulation 2: the paper's three stages.                                    */
+/* ------------------------------------------------------------------------- */
+
+/* Stage I (Algorithm 1): the i-th edge (x, y), x < y, taken in CSR order, gets
+ * tri = |N(x) and N(y)| by a sorted merge.  The value is stored in both CSR slots
+ * of the edge (tri int32[row_ptr[n]]) so later stages can read it from either end. */
+int oref_stage1(i32 n, const i64 *rp, const i32 *col, i32 *tri)
+{
+    if (n < 0 || (n > 0 && (!rp || !col)) || (n > 0 && rp[n] > 0 && !tri)) return ORACLE_EINVAL;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (i32 x = 0; x < n; x++) {
+        for (i64 s = rp[x]; s < rp[x + 1]; s++) {
+            i32 y = col[s];
+            if (y < x) continue;
+            i64 i = rp[x], j = rp[y];
+            i32 c = 0;
+            while (i < rp[x + 1] && j < rp[y + 1]) {
+                if (col[i] < col[j]) i++;
+                else if (col[i] > col[j]) j++;
+                else { c++; i++; j++; }
+            }
+            tri[s] = c;
+            tri[slot_of(rp, col, y, x)] = c;
+        }
+    }
+    return ORACLE_OK;
+}
+
+/* Stage II (Algorithm 2): for x, every neighbour y > x, the neighbours z > y of y
+ * that are also neighbours of x go to neigh (emptied for every y); every adjacent
+ * pair z < z' of neigh closes a 4-clique {x, y, z, z'} and all four get +1. */
+int oref_stage2(i32 n, const i64 *rp, const i32 *col, i64 *K4)
+{
+    if (n < 0 || (n > 0 && (!rp || !col || !K4))) return ORACLE_EINVAL;
+    if (n == 0) return ORACLE_OK;
+    memset(K4, 0, sizeof(i64) * (size_t)n);
+    i64 dmax = 0;
+    for (i32 v = 0; v < n; v++) if (deg_of(rp, v) > dmax) dmax = deg_of(rp, v);
+    int err = 0;
+#pragma omp parallel
+    {
+        unsigned char *inx = (unsigned char *)calloc((size_t)n, 1);
+        i32 *neigh = (i32 *)malloc(sizeof(i32) * (size_t)(dmax + 1));
+        if (!inx || !neigh) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (i32 x = 0; x < n; x++) {
+                for (i64 s = rp[x]; s < rp[x + 1]; s++) inx[col[s]] = 1;
+                for (i64 s = rp[x]; s < rp[x + 1]; s++) {
+                    i32 y = col[s];
+                    if (y <= x) continue;
+                    i64 len = 0;
+                    for (i64 r = rp[y]; r < rp[y + 1]; r++) {
+                        i32 z = col[r];
+                        if (z > y && inx[z]) neigh[len++] = z;
+                    }
+                    for (i64 i = 0; i < len; i++)
+                        for (i64 j = i + 1; j < len; j++)
+                            if (slot_of(rp, col, neigh[i], neigh[j]) >= 0) {
+#pragma omp atomic
+                                K4[x] += 1;
+#pragma omp atomic
+                                K4[y] += 1;
+#pragma omp atomic
+                                K4[neigh[i]] += 1;
+#pragma omp atomic
+                                K4[neigh[j]] += 1;
+                            }
+                }
+                for (i64 s = rp[x]; s < rp[x + 1]; s++) inx[col[s]] = 0;
+            }
+        }
+        free(inx);
+        free(neigh);
+    }
+    return err ? ORACLE_ENOMEM : ORACLE_OK;
+}
+
+/* Per-thread scratch for Stage III. */
+typedef struct {
+    i32 *tx;        /* tx[z] = t(x, z) for z in N(x), -1 elsewhere */
+    unsigned char *iny; /* neighbour marks of the current y (two-star test) */
+    i64 *common;    /* common[z] for z outside N(x) */
+    i32 *touched;   /* vertices with common[z] != 0 */
+} scratch_t;
+
+static int scratch_init(scratch_t *sc, i32 n, i64 dmax)
+{
+    sc->tx = (i32 *)malloc(sizeof(i32) * (size_t)(n ? n : 1));
+    sc->iny = (unsigned char *)calloc((size_t)(n ? n : 1), 1);
+    sc->common = (i64 *)calloc((size_t)(n ? n : 1), sizeof(i64));
+    sc->touched = (i32 *)malloc(sizeof(i32) * (size_t)(n ? n : 1));
+    (void)dmax;
+    if (!sc->tx || !sc->iny || !sc->common || !sc->touched) return -1;
+    for (i32 v = 0; v < n; v++) sc->tx[v] = -1;
+    return 0;
+}
+
+static void scratch_free(scratch_t *sc)
+{
+    free(sc->tx); free(sc->iny); free(sc->common); free(sc->touched);
+}
+
+static i64 choose2(i64 a) { return a * (a - 1) / 2; }
+static i64 choose3(i64 a) { return a * (a - 1) * (a - 2) / 6; }
+
+/* Stage III for one vertex x: probe the four substructures (Table 1), then solve
+ * the equations (Section 5, Appendix).  tri is indexed by CSR slot and must be
+ * valid in row x and in every row y with y in N(x).  Writes psi[15] and f[9]. */
+static int stage3_vertex(const i64 *rp, const i32 *col, const i32 *tri, i64 k4x,
+                         i32 x, scratch_t *sc, i64 *psi, i64 *f)
+{
+    i64 dx = deg_of(rp, x);
+    i64 fv[NFV];
+    memset(fv, 0, sizeof fv);
+    i64 psi1 = 0, pairs = 0, triangles = 0;
+
+    for (i64 s = rp[x]; s < rp[x + 1]; s++) sc->tx[col[s]] = tri[s];
+
+    /* 3-vertex counts and the two triangle substructures. */
+    for (i64 s = rp[x]; s < rp[x + 1]; s++) {
+        i32 y = col[s];
+        i64 dy = deg_of(rp, y), txy = tri[s];
+        psi1 += dy - 1;
+        for (i64 r = rp[y]; r < rp[y + 1]; r++) {
+            i32 z = col[r];
+            if (z >= y || sc->tx[z] < 0) continue;   /* triangle {x,y,z}, y > z */
+            i64 dz = deg_of(rp, z), tyz = tri[r], txz = sc->tx[z];
+            triangles++;
+            /* Triangle 1 */
+            fv[F12_14] += tyz - 1;
+            fv[F10_13] += (dy - 1 - tyz) + (dz - 1 - tyz);
+            /* Triangle 2 */
+            fv[F13_14] += (txy - 1) + (txz - 1);
+            fv[F11_13] += (dx - 1 - txy) + (dx - 1 - txz);
+        }
+    }
+
+    /* Two-Star: unordered pairs of neighbours of x. */
+    for (i64 s = rp[x]; s < rp[x + 1]; s++) {
+        i32 y = col[s];
+        i64 dy = deg_of(rp, y), txy = tri[s];
+        for (i64 r = rp[y]; r < rp[y + 1]; r++) sc->iny[col[r]] = 1;
+        for (i64 q = s + 1; q < rp[x + 1]; q++) {
+            i32 z = col[q];
+            pairs++;
+            if (sc->iny[z]) continue;
+            i64 dz = deg_of(rp, z), txz = tri[q];
+            fv[F5_8] += (dy - 1 - txy) + (dz - 1 - txz);
+        }
+        for (i64 r = rp[y]; r < rp[y + 1]; r++) sc->iny[col[r]] = 0;
+    }
+
+    /* Path x - y - z with z outside N(x): first fill common[], then the sums. */
+    i64 ntouched = 0;
+    for (i64 s = rp[x]; s < rp[x + 1]; s++) {
+        i32 y = col[s];
+        for (i64 r = rp[y]; r < rp[y + 1]; r++) {
+            i32 z = col[r];
+            if (z == x || sc->tx[z] >= 0) continue;
+            if (sc->common[z]++ == 0) sc->touched[ntouched++] = z;
+        }
+    }
+    for (i64 s = rp[x]; s < rp[x + 1]; s++) {
+        i32 y = col[s];
+        i64 dy = deg_of(rp, y), txy = tri[s];
+        for (i64 r = rp[y]; r < rp[y + 1]; r++) {
+            i32 z = col[r];
+            if (z == x || sc->tx[z] >= 0) continue;
+            i64 dz = deg_of(rp, z), tyz = tri[r];
+            fv[F6_9] += dy - 2 - txy;
+            fv[F9_12] += tyz;
+            fv[F4_8] += dz - 1 - tyz;
+            fv[F8_12] += sc->common[z] - 1;
+        }
+    }
+    for (i64 i = 0; i < ntouched; i++) sc->common[sc->touched[i]] = 0;
+    for (i64 s = rp[x]; s < rp[x + 1]; s++) sc->tx[col[s]] = -1;
+
+    /* Equations (Section 5 and Appendix).  Halvings must be exact. */
+    i64 h13 = fv[F13_14], h11 = fv[F11_13] + fv[F13_14], h9 = fv[F9_12];
+    i64 h8 = fv[F13_14] + fv[F8_12], h6 = fv[F6_9] - fv[F13_14];
+    if ((h13 | h11 | h9 | h8 | h6) & 1) return ORACLE_EODD;
+    psi[0] = dx;
+    psi[1] = psi1;
+    psi[2] = pairs;
+    psi[3] = triangles;
+    psi[4] = 2 * fv[F12_14] + fv[F4_8] + fv[F10_13] + fv[F9_12];
+    psi[5] = 2 * fv[F12_14] + fv[F5_8] + fv[F10_13] + fv[F11_13];
+    psi[6] = h6 / 2 + fv[F10_13] + 2 * fv[F12_14];
+    psi[7] = choose3(dx);
+    psi[8] = h8 / 2;
+    psi[9] = fv[F12_14] + h9 / 2;
+    psi[10] = fv[F10_13] + 2 * fv[F12_14];
+    psi[11] = h11 / 2;
+    psi[12] = fv[F12_14];
+    psi[13] = h13 / 2;
+    psi[14] = k4x;
+    (void)choose2;
+    if (f) memcpy(f, fv, sizeof fv);
+    return ORACLE_OK;
+}
+
+/* Stage III over all vertices.  psi int64[n*15]; fvars int64[n*9] or NULL. */
+int oref_stage3(i32 n, const i64 *rp, const i32 *col, const i32 *tri, const i64 *K4,
+                i64 *psi, i64 *fvars)
+{
+    if (n < 0 || (n > 0 && (!rp || !col || !K4 || !psi))) return ORACLE_EINVAL;
+    if (n == 0) return ORACLE_OK;
+    if (rp[n] > 0 && !tri) return ORACLE_EINVAL;
+    int err = 0;
+#pragma omp parallel
+    {
+        scratch_t sc;
+        if (scratch_init(&sc, n, 0) != 0) {
+#pragma omp atomic write
+            err = ORACLE_ENOMEM;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (i32 x = 0; x < n; x++) {
+                int e = stage3_vertex(rp, col, tri, K4[x], x, &sc, psi + (i64)x * 15,
+                                      fvars ? fvars + (i64)x * NFV : NULL);
+                if (e) {
+#pragma omp atomic write
+                    err = e;
+                }
+            }
+        }
+        scratch_free(&sc);
+    }
+    return err;
+}
+
+/* The three stages in order (Algorithm 1). */
+int oref_count(i32 n, const i64 *rp, const i32 *col, i64 *psi)
+{
+    if (n < 0 || (n > 0 && (!rp || !col || !psi))) return ORACLE_EINVAL;
+    if (n == 0) return ORACLE_OK;
+    i64 nnz = rp[n];
+    i32 *tri = (i32 *)malloc(sizeof(i32) * (size_t)(nnz ? nnz : 1));
+    i64 *K4 = (i64 *)malloc(sizeof(i64) * (size_t)n);
+    if (!tri || !K4) { free(tri); free(K4); return ORACLE_ENOMEM; }
+    int e = oref_stage1(n, rp, col, tri);
+    if (!e) e = oref_stage2(n, rp, col, K4);
+    if (!e) e = oref_stage3(n, rp, col, tri, K4, psi, NULL);
+    free(tri);
+    free(K4);
+    return e;
+}
+
+/* Orbit counts of selected vertices only, for graphs too large for the full
+ * oracle.  Stage I values are computed for the rows the probes read (row x and the
+ * rows of its neighbours) by counting common neighbours with a mark array; psi_14
+ * is the number of triangles inside N(x), i.e. the 4-cliques containing x (the
+ * definition, since Algorithm 2 attributes globally).  xs int32[nq];
+ * psi int64[nq*15]; fvars int64[nq*9] or NULL; tri_scratch int32[row_ptr[n]]
+ * (caller-owned, contents overwritten). */
+int oref_orbits_at(i32 n, const i64 *rp, const i32 *col, i32 nq, const i32 *xs,
+                   i64 *psi, i64 *fvars, i32 *tri_scratch)
+{
+    if (n < 0 || nq < 0 || (nq > 0 && (!rp || !col || !xs || !psi || !tri_scratch)))
+        return ORACLE_EINVAL;
+    for (i32 q = 0; q < nq; q++) if (xs[q] < 0 || xs[q] >= n) return ORACLE_EINVAL;
+    if (nq == 0) return ORACLE_OK;
+    /* rows whose Stage I values are needed */
+    unsigned char *need = (unsigned char *)calloc((size_t)n, 1);
+    if (!need) return ORACLE_ENOMEM;
+    for (i32 q = 0; q < nq; q++) {
+        i32 x = xs[q];
+        need[x] = 1;
+        for (i64 s = rp[x]; s < rp[x + 1]; s++) need[col[s]] = 1;
+    }
+    i32 *rows = (i32 *)malloc(sizeof(i32) * (size_t)n);
+    if (!rows) { free(need); return ORACLE_ENOMEM; }
+    i64 nrows = 0;
+    for (i32 v = 0; v < n; v++) if (need[v]) rows[nrows++] = v;
+    int err = 0;
+#pragma omp parallel
+    {
+        unsigned char *mark = (unsigned char *)calloc((size_t)n, 1);
+        if (!mark) {
+#pragma omp atomic write
+            err = ORACLE_ENOMEM;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (i64 i = 0; i < nrows; i++) {
+                i32 y = rows[i];
+                for (i64 r = rp[y]; r < rp[y + 1]; r++) mark[col[r]] = 1;
+                for (i64 r = rp[y]; r < rp[y + 1]; r++) {
+                    i32 z = col[r];
+                    i32 c = 0;
+                    for (i64 u = rp[z]; u < rp[z + 1]; u++) c += mark[col[u]];
+                    tri_scratch[r] = c;
+                }
+                for (i64 r = rp[y]; r < rp[y + 1]; r++) mark[col[r]] = 0;
+            }
+        }
+        free(mark);
+    }
+    free(rows);
+    free(need);
+    if (err) return err;
+#pragma omp parallel
+    {
+        scratch_t sc;
+        if (scratch_init(&sc, n, 0) != 0) {
+#pragma omp atomic write
+            err = ORACLE_ENOMEM;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (i32 q = 0; q < nq; q++) {
+                i32 x = xs[q];
+                /* 4-cliques containing x: triangles y < z < w inside N(x) */
+                for (i64 s = rp[x]; s < rp[x + 1]; s++) sc.tx[col[s]] = 1;
+                i64 k4 = 0;
+                for (i64 s = rp[x]; s < rp[x + 1]; s++) {
+                    i32 y = col[s];
+                    for (i64 r = rp[y]; r < rp[y + 1]; r++) sc.iny[col[r]] = 1;
+                    for (i64 r = rp[y]; r < rp[y + 1]; r++) {
+                        i32 z = col[r];
+                        if (z <= y || sc.tx[z] < 0) continue;
+                        for (i64 u = rp[z]; u < rp[z + 1]; u++) {
+                            i32 w = col[u];
+                            if (w > z && sc.tx[w] >= 0 && sc.iny[w]) k4++;
+                        }
+                    }
+                    for (i64 r = rp[y]; r < rp[y + 1]; r++) sc.iny[col[r]] = 0;
+                }
+                for (i64 s = rp[x]; s < rp[x + 1]; s++) sc.tx[col[s]] = -1;
+                int e = stage3_vertex(rp, col, tri_scratch, k4, x, &sc, psi + (i64)q * 15,
+                                      fvars ? fvars + (i64)q * NFV : NULL);
+                if (e) {
+#pragma omp atomic write
+                    err = e;
+                }
+            }
+        }
+        scratch_free(&sc);
+    }
+    return err;
+}
