@@ -1,0 +1,166 @@
+/*
+ * niorca.h -- C ABI of the MI355X (gfx950) library that counts, for every vertex
+ * of an undirected simple graph, the 15 orbits of the non-induced connected
+ * graphlets on 2 to 4 vertices.
+ *
+ * What is computed (Section 3, Definitions 3-5; Section 5): psi_k(x) is the number
+ * of pairs (S, E') with S a set of 2..4 vertices containing x, E' a subset of the
+ * edges of G inside S such that (S, E') is connected, and x in orbit k of (S, E').
+ * Orbits: 0 edge end; 1, 2 end and middle of a 3-path; 3 triangle; 4, 5 end and
+ * inner vertex of a 4-path; 6, 7 leaf and centre of a 3-star; 8 4-cycle; 9, 10,
+ * 11 tail, degree-2 and degree-3 vertex of a tailed triangle; 12, 13 degree-2 and
+ * degree-3 vertex of a diamond; 14 4-clique.
+ *
+ * Method (Algorithm 1): Stage I per-edge triangle counts, Stage II per-vertex
+ * 4-clique counts (Algorithm 2 in spirit, run on a degree-ordered orientation),
+ * Stage III the nine f-variables of Table 1 and the non-induced equations of
+ * Section 5 and the Appendix, all in int64.
+ *
+ * Conventions shared by every entry point
+ *   - Graph: CSR in DEVICE memory.  row_ptr is int64[n+1] with row_ptr[0] = 0 and
+ *     row_ptr[n] = nnz; col is int32[nnz]; row v lists N(v) sorted ascending, with
+ *     no self-loop, no duplicate, and (u in N(v)) <=> (v in N(u)).  nnz = 2|E|.
+ *     The library never modifies the graph and keeps no pointer after a call.
+ *   - Outputs are DEVICE buffers owned by the caller, written completely.
+ *   - stream: a hipStream_t passed as void*; NULL means the null stream.  Work is
+ *     enqueued on it; entry points return once the work is enqueued (they wait on
+ *     the stream only where stated).  The caller synchronises before reading.
+ *   - A context is single-threaded: calls on one context must not overlap in time
+ *     (they share its workspace).  Different contexts are independent.
+ *   - Errors: every entry point returns a niorca_status; on failure nothing has
+ *     been enqueued unless stated, and niorca_last_error() describes the cause.
+ */
+#ifndef NIORCA_H
+#define NIORCA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    NIORCA_OK = 0,
+    NIORCA_EINVAL = 1,      /* bad argument: NULL pointer, negative or odd size, unknown flag */
+    NIORCA_ENOTSIMPLE = 2,  /* NIORCA_VALIDATE found an unsorted/asymmetric/looped/duplicated CSR */
+    NIORCA_EOVERFLOW = 3,   /* some count could exceed int64 for this degree sequence */
+    NIORCA_ENOMEM = 4,      /* device workspace allocation failed or exceeded the cap */
+    NIORCA_EDEVICE = 5,     /* a HIP runtime call failed */
+    NIORCA_ENOTIMPL = 6,    /* a size beyond the supported range (e.g. nnz >= 2^31) */
+    NIORCA_EINTERNAL = 7    /* a device-side consistency check failed */
+} niorca_status;
+
+/* Flags (bitmask). */
+#define NIORCA_VALIDATE   0x1u  /* check the CSR precondition on the device; waits on the stream */
+#define NIORCA_BIN_DEGREE 0x2u  /* work classes from degree thresholds */
+#define NIORCA_BIN_MLP    0x4u  /* work classes from the loaded cost model (niorca_set_cost_model) */
+#define NIORCA_COUNTERS   0x8u  /* record per-vertex work counters (niorca_work_counters) */
+#define NIORCA_TIMING     0x10u /* record HIP events between stages (niorca_stage_times) */
+
+typedef struct niorca_ctx niorca_ctx;
+
+/* Create a context on HIP device `device`; it owns a grow-only device workspace.
+ * Returns EINVAL for a NULL ctx pointer, EDEVICE if the device cannot be set. */
+niorca_status niorca_create(niorca_ctx **ctx, int device);
+
+/* Release the context and its workspace (waits for the device).  NULL-safe. */
+void niorca_destroy(niorca_ctx *ctx);
+
+/* Message for the last failure on this context ("" if none).  The pointer stays
+ * valid until the next call on the context. */
+const char *niorca_last_error(const niorca_ctx *ctx);
+
+/* Cap on the workspace in bytes (0 = no cap).  Calls needing more fail with ENOMEM. */
+niorca_status niorca_set_workspace_limit(niorca_ctx *ctx, uint64_t bytes);
+
+/* Workspace bytes currently held by the context. */
+uint64_t niorca_workspace_bytes(const niorca_ctx *ctx);
+
+/* Tuning knobs of the work classes (they change which kernel shape handles a vertex,
+ * never a count).  Names and ranges:
+ *   "tri_wave"  1..64    vertices with |N+| up to this use one wave (Stage I/II, tau)
+ *   "tri_block" 1..512   ... up to this one workgroup with LDS; above, global scratch
+ *   "ql_wave"   0..256   4-cycle wedges (largest vertex light) up to this: wave hash
+ *   "ql_block"  0..4096  ... up to this: workgroup hash; above: global counters
+ *   "qh_wave"   0..256   4-cycle wedges opposite a heavy largest vertex: wave hash
+ *   "qh_block"  0..4096  ... workgroup hash; above: dense LDS counters
+ *   "heavy_k"   0..32768 how many top-ranked vertices form the heavy range
+ * Returns EINVAL for an unknown name or a value out of range. */
+niorca_status niorca_set_param(niorca_ctx *ctx, const char *name, int64_t value);
+
+/* The 15 orbit counts of every vertex (Algorithm 1, Section 5, Appendix).
+ *   n        number of vertices, 0 <= n < 2^31 (n = 0 is a no-op returning OK)
+ *   nnz      row_ptr[n] = 2|E|, even, < 2^31
+ *   row_ptr  device int64[n+1]; col device int32[nnz] (see conventions)
+ *   out      device int64[n*15], row-major: out[x*15 + k] = psi_k(x)
+ *   flags    NIORCA_* bits
+ * Waits once on `stream` to read a few graph statistics (degree maximum, work
+ * class sizes) that size the launches and the overflow check; everything after
+ * that is enqueued without waiting. */
+niorca_status niorca_count(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
+                           const int32_t *col, int64_t *out, void *stream, uint32_t flags);
+
+/* Many small graphs in one call.  Graph g owns vertices vtx_off[g]..vtx_off[g+1]-1
+ * of a packed CSR whose row_ptr is global (int64[total_n+1]) and whose column ids
+ * are LOCAL to the graph (0..n_g-1).  out is int64[total_n*15].  vtx_off is a
+ * HOST int64[num_graphs+1] array (the packing is known to the host).  All graphs
+ * are counted by one persistent launch per stage; with NIORCA_GRAPH_CAPTURE the
+ * launch sequence is captured once per shape into a hipGraph and replayed. */
+#define NIORCA_GRAPH_CAPTURE 0x100u
+niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graphs, const int64_t *vtx_off,
+                                   const int64_t *row_ptr, const int32_t *col, int64_t *out,
+                                   void *stream, uint32_t flags);
+
+/* ---- Introspection: intermediate results of the last stages, same conventions ---- */
+
+/* Stage I: tri[s] = |N(x) and N(y)| for the edge in input CSR slot s (Algorithm 1,
+ * the tri array indexed by edge).  tri is device int32[nnz]. */
+niorca_status niorca_edge_triangles(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
+                                    const int32_t *col, int32_t *tri, void *stream);
+
+/* Stage II: k4[x] = number of 4-cliques containing x (Algorithm 2).  device int64[n]. */
+niorca_status niorca_k4(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
+                        const int32_t *col, int64_t *k4, void *stream);
+
+/* Stage III-a: the nine f-variables of Table 1 per vertex, device int64[n*9] in the
+ * order f12_14, f10_13, f13_14, f11_13, f5_8, f6_9, f9_12, f4_8, f8_12. */
+niorca_status niorca_fvars(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
+                           const int32_t *col, int64_t *fvars, void *stream);
+
+/* Durations in ms, measured with HIP events on the call's stream, of the stages of
+ * the last niorca_count made with NIORCA_TIMING; waits for that call to finish.
+ *   0 degrees, rank sort, relabelled rows         1 statistics wait and setup
+ *   2 N+ sort, mirror slots, work classes          3 zeroing of the accumulators
+ *   4 Stage I + Stage II (probe kernels)           5 neighbour sums
+ *   6 tau (probe kernels)                          7 4-cycles (light and heavy kernels)
+ *   8 equations and output
+ * ms must hold NIORCA_NUM_STAGES floats. */
+#define NIORCA_NUM_STAGES 9
+niorca_status niorca_stage_times(niorca_ctx *ctx, float *ms, int32_t count);
+
+/* Number of per-vertex work counters written by niorca_work_counters. */
+#define NIORCA_NUM_COUNTERS 6
+/* Per-vertex work measured by the last niorca_count made with NIORCA_COUNTERS:
+ * device int64[n*NIORCA_NUM_COUNTERS], in input vertex order:
+ *   0 triangle probes (Stage I, x as lowest vertex), 1 triangles found there,
+ *   2 clique bitset words scanned, 3 4-cycle wedges with x as the largest vertex,
+ *   4 4-cycle wedges with x as the opposite vertex of a heavy largest vertex,
+ *   5 neighbour-sum slots read.
+ * Fails with EINVAL if the last count did not record counters or n differs. */
+niorca_status niorca_work_counters(niorca_ctx *ctx, int32_t n, int64_t *counters, void *stream);
+
+/* Cost model for NIORCA_BIN_MLP: an FP32 MLP 6 -> 32 -> 32 -> 1 (ReLU hidden layers)
+ * predicting log2(1 + work) of a vertex from its features.  weights is a HOST
+ * float array in the order W1[32][6], b1[32], W2[32][32], b2[32], W3[1][32], b3[1]
+ * (1313 floats), plus feature normalisation mean[6], inv_std[6] (12 floats):
+ * 1325 floats in total.  Thresholds (log2 work) split the thread / wave / block
+ * classes.  Copied into the context. */
+#define NIORCA_MLP_PARAMS 1325
+niorca_status niorca_set_cost_model(niorca_ctx *ctx, const float *weights, int32_t count,
+                                    float thr_wave, float thr_block);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NIORCA_H */

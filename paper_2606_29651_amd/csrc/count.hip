@@ -1,0 +1,795 @@
+// Counting kernels on the relabelled, degree-oriented graph.
+//
+//   probe (TRI)  Stage I and Stage II: for every vertex u, the triangles with u as
+//                lowest vertex are found by probing each N+(v), v in N+(u), against
+//                an LDS hash of N+(u); every hit adds 1 to the three edges' t.  The
+//                hits also form the graph H_u induced on N+(u), kept as an LDS
+//                bitset; the 4-cliques with u lowest are the triangles of H_u
+//                (Algorithm 2 counts each 4-clique once from a fixed vertex too).
+//   probe (TAU)  after Stage I: tau(x) = sum over triangles at x of t(opposite edge).
+//   sums         neighbour sums over the full row of x of t, t^2, t d(a), d(a), d(a)^2.
+//   q (LIGHT)    4-cycles whose largest vertex u lies below h0, grouped by u:
+//                cnt[w] = #v in N-(u) adjacent to w, w < u.
+//   q (HEAVY)    4-cycles whose largest vertex u lies in [h0, n), grouped by the
+//                vertex w opposite u: cnt[u] = #v in N(w) with u in N+(v), u > w.
+//                Each 4-cycle is counted once, by (largest vertex, its opposite).
+//   solve        the nine f-variables from those sums and the non-induced equations
+//                (Section 5 and the Appendix), written in input vertex order.
+#include "common.hpp"
+#include "kernels.hpp"
+
+template <int NT>
+__device__ __forceinline__ void item_sync() {
+    if constexpr (NT == WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        __syncthreads();
+    }
+}
+
+// Sum over the NT threads of one item; red must hold NT/WAVE entries.
+template <int NT>
+__device__ __forceinline__ i64 item_sum(i64 v, i64 *red, int tid) {
+    v = wave_sum64(v);
+    if constexpr (NT == WAVE) {
+        return v;
+    } else {
+        if (lane_id() == 0) red[tid / WAVE] = v;
+        __syncthreads();
+        i64 s = 0;
+        for (int k = 0; k < NT / WAVE; k++) s += red[k];
+        __syncthreads();
+        return s;
+    }
+}
+
+// In-place inclusive prefix over a[1..len] (a[0] = 0 set here), NT threads.
+template <int NT>
+__device__ __forceinline__ void item_scan(i32 *a, int len, int tid, i32 *red32) {
+    if (tid == 0) a[0] = 0;
+    i32 carry = 0;
+    for (int c = 0; c < len; c += NT) {
+        int i = c + tid;
+        i32 v = i < len ? a[i + 1] : 0;
+        i32 x = wave_incl_sum(v);
+        if constexpr (NT == WAVE) {
+            if (i < len) a[i + 1] = carry + x;
+            carry += __shfl(x, WAVE - 1, WAVE);
+        } else {
+            int w = tid / WAVE;
+            if (lane_id() == WAVE - 1) red32[w] = x;
+            __syncthreads();
+            i32 before = 0, all = 0;
+            for (int k = 0; k < NT / WAVE; k++) {
+                if (k < w) before += red32[k];
+                all += red32[k];
+            }
+            if (i < len) a[i + 1] = carry + before + x;
+            carry += all;
+            __syncthreads();
+        }
+    }
+    item_sync<NT>();
+}
+
+// ---------------------------------------------------------------------------
+// Classification into work lists (wave-aggregated appends).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void list_push(bool take, int c, i32 y, const ListPtrs &lists, GraphStats *st) {
+    u64 m = __ballot(take);
+    if (!m) return;
+    int leader = __ffsll((long long)m) - 1;
+    i32 base = 0;
+    if (lane_id() == leader) base = atomicAdd(&st->cnt[c], __popcll(m));
+    base = __shfl(base, leader, WAVE);
+    if (take) lists.l[c][base + __popcll(m & lanemask_lt())] = y;
+}
+
+__global__ void k_classify(DevGraph g, const i64 *__restrict__ wlight, const i64 *__restrict__ wheavy,
+                           ListPtrs lists, GraphStats *__restrict__ st, Thresholds th) {
+    i32 idx = blockIdx.x * blockDim.x + threadIdx.x;
+    i32 y = g.n - 1 - idx;  // hubs first
+    bool valid = y >= 0;
+    i32 du = 0, d = 0, dm = 0;
+    i64 wl = 0, wh = 0;
+    if (valid) {
+        i32 b = g.nrp[y], sp = g.nsplit[y], e = g.nrp[y + 1];
+        du = e - sp;
+        d = e - b;
+        dm = sp - b;
+        wl = wlight[y];
+        wh = wheavy[y];
+    }
+    list_push(valid && du >= 2 && du <= th.tri_wave, WC_TRI_WAVE, y, lists, st);
+    list_push(valid && du >= 2 && du > th.tri_wave && du <= th.tri_block, WC_TRI_BLOCK, y, lists, st);
+    list_push(valid && du >= 2 && du > th.tri_block, WC_TRI_LARGE, y, lists, st);
+    bool qlw = valid && wl > 0 && wl <= th.ql_wave;
+    bool qlb = valid && wl > th.ql_wave && wl <= th.ql_block;
+    bool qlg = valid && wl > th.ql_block;
+    list_push(qlw, WC_QL_WAVE, y, lists, st);
+    list_push(qlb, WC_QL_BLOCK, y, lists, st);
+    list_push(qlg, WC_QL_GLOBAL, y, lists, st);
+    bool qhw = valid && wh > 0 && wh <= th.qh_wave;
+    bool qhb = valid && wh > th.qh_wave && wh <= th.qh_block;
+    // dense 16-bit counters need every count below 2^16; counts are bounded by d(x)
+    bool qhd = valid && wh > th.qh_block && d < 65536;
+    bool qhg = valid && wh > th.qh_block && d >= 65536;
+    list_push(qhw, WC_QH_WAVE, y, lists, st);
+    list_push(qhb, WC_QH_BLOCK, y, lists, st);
+    list_push(qhd, WC_QH_DENSE, y, lists, st);
+    list_push(qhg, WC_QH_GLOBAL, y, lists, st);
+    (void)dm;
+}
+
+// ---------------------------------------------------------------------------
+// Stage I / Stage II / tau probe kernels.
+// ---------------------------------------------------------------------------
+enum { PROBE_TRI = 0, PROBE_TAU = 1 };
+
+struct ProbeMem {
+    i32 *hkey;   // [hc]
+    i32 *hpos;   // [hc]
+    i32 *off;    // [cap+1]
+    i32 *nb;     // [cap]
+    i32 *tcnt;   // [cap]
+    u32 *A;      // [cap*words]
+    i64 *acc;    // [cap]
+};
+
+template <int NT, int MODE>
+__device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, const ProbeMem &M, int hc,
+                                           int words, i32 *__restrict__ t, i64 *__restrict__ K4,
+                                           i64 *__restrict__ tau, i64 *red, i32 *red32) {
+    const i32 base = g.nsplit[u];
+    const i32 du = g.nrp[u + 1] - base;
+    const u32 hmask = (u32)hc - 1;
+    const int nw = (du + 31) >> 5;
+    for (int i = tid; i < hc; i += NT) M.hkey[i] = -1;
+    item_sync<NT>();
+    for (int i = tid; i < du; i += NT) {
+        i32 v = g.ncol[base + i];
+        M.nb[i] = v;
+        M.off[i + 1] = g.nrp[v + 1] - g.nsplit[v];
+        u32 sl = hslot((u32)v, hmask);
+        while (atomicCAS(&M.hkey[sl], -1, v) != -1) sl = (sl + 1) & hmask;
+        M.hpos[sl] = i;
+        M.acc[i] = 0;
+        if (MODE == PROBE_TRI) {
+            M.tcnt[i] = 0;
+            for (int k = 0; k < nw; k++) M.A[i * words + k] = 0u;
+        }
+    }
+    item_sync<NT>();
+    item_scan<NT>(M.off, du, tid, red32);
+    const i32 total = M.off[du];
+    i64 tau_local = 0;
+    for (i32 e = tid; e < total; e += NT) {
+        int i = upper_index<i32>(M.off, 0, du, e);
+        i32 v = M.nb[i];
+        i32 q = g.nsplit[v] + (e - M.off[i]);
+        i32 w = g.ncol[q];
+        u32 sl = hslot((u32)w, hmask);
+        int p = -1;
+        while (true) {
+            i32 k = M.hkey[sl];
+            if (k == w) { p = M.hpos[sl]; break; }
+            if (k == -1) break;
+            sl = (sl + 1) & hmask;
+        }
+        if (p >= 0) {
+            if (MODE == PROBE_TRI) {
+                atomicAdd(&M.tcnt[i], 1);
+                atomicAdd(&M.tcnt[p], 1);
+                atomicAdd(&t[q], 1);
+                atomicOr(&M.A[i * words + (p >> 5)], 1u << (p & 31));
+                atomicOr(&M.A[p * words + (i >> 5)], 1u << (i & 31));
+            } else {
+                tau_local += t[q];
+                atomicAdd((unsigned long long *)&M.acc[i], (unsigned long long)t[base + p]);
+                atomicAdd((unsigned long long *)&M.acc[p], (unsigned long long)t[base + i]);
+            }
+        }
+    }
+    item_sync<NT>();
+    if (MODE == PROBE_TRI) {
+        i64 s_local = 0;
+        for (int j = tid; j < du; j += NT) {
+            i32 c = M.tcnt[j];
+            if (c) atomicAdd(&t[base + j], c);
+            i64 sj = 0;
+            for (int wd = 0; wd < nw; wd++) {
+                u32 bits = M.A[j * words + wd];
+                while (bits) {
+                    int b = __ffs(bits) - 1;
+                    bits &= bits - 1;
+                    int i = wd * 32 + b;
+                    for (int k = 0; k < nw; k++) sj += __popc(M.A[i * words + k] & M.A[j * words + k]);
+                }
+            }
+            // sj = 2 x (triangles of H_u through j) = 2 x (4-cliques containing u and nb[j])
+            if (sj) atomic_add_i64(&K4[M.nb[j]], sj >> 1);
+            s_local += sj;
+        }
+        i64 s = item_sum<NT>(s_local, red, tid);
+        if (tid == 0 && s) atomic_add_i64(&K4[u], s / 6);
+    } else {
+        for (int j = tid; j < du; j += NT) {
+            i64 a = M.acc[j];
+            if (a) atomic_add_i64(&tau[M.nb[j]], a);
+        }
+        i64 s = item_sum<NT>(tau_local, red, tid);
+        if (tid == 0 && s) atomic_add_i64(&tau[u], s);
+    }
+    item_sync<NT>();
+}
+
+// One wave per vertex, |N+(u)| <= 64, four items per 256-thread block.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__restrict__ list,
+                                                    const GraphStats *__restrict__ st, i32 *t, i64 *K4,
+                                                    i64 *tau) {
+    constexpr int CAP = TRI_WAVE_CAP, HC = 2 * CAP, WORDS = CAP / 32;
+    __shared__ i32 s_hkey[4][HC];
+    __shared__ i32 s_hpos[4][HC];
+    __shared__ i32 s_off[4][CAP + 1];
+    __shared__ i32 s_nb[4][CAP];
+    __shared__ i32 s_tcnt[4][CAP];
+    __shared__ u32 s_A[4][CAP * WORDS];
+    __shared__ i64 s_acc[4][CAP];
+    const int w = threadIdx.x / WAVE, tid = lane_id();
+    ProbeMem M{s_hkey[w], s_hpos[w], s_off[w], s_nb[w], s_tcnt[w], s_A[w], s_acc[w]};
+    const i32 cnt = st->cnt[WC_TRI_WAVE];
+    const int waves = gridDim.x * 4;
+    for (i32 it = blockIdx.x * 4 + w; it < cnt; it += waves)
+        probe_item<WAVE, MODE>(g, list[it], tid, M, HC, WORDS, t, K4, tau, nullptr, nullptr);
+}
+
+// One 256-thread workgroup per vertex, 64 < |N+(u)| <= TRI_BLOCK_CAP.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_probe_block(DevGraph g, const i32 *__restrict__ list,
+                                                     const GraphStats *__restrict__ st, i32 *t, i64 *K4,
+                                                     i64 *tau) {
+    constexpr int CAP = TRI_BLOCK_CAP, HC = 2 * CAP, WORDS = CAP / 32;
+    __shared__ i32 s_hkey[HC];
+    __shared__ i32 s_hpos[HC];
+    __shared__ i32 s_off[CAP + 1];
+    __shared__ i32 s_nb[CAP];
+    __shared__ i32 s_tcnt[CAP];
+    __shared__ u32 s_A[CAP * WORDS];
+    __shared__ i64 s_acc[CAP];
+    __shared__ i64 s_red[4];
+    __shared__ i32 s_red32[4];
+    ProbeMem M{s_hkey, s_hpos, s_off, s_nb, s_tcnt, s_A, s_acc};
+    const i32 cnt = st->cnt[WC_TRI_BLOCK];
+    for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
+        probe_item<256, MODE>(g, list[it], threadIdx.x, M, HC, WORDS, t, K4, tau, s_red, s_red32);
+}
+
+// |N+(u)| > TRI_BLOCK_CAP: the same item code on per-workgroup global scratch.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_probe_large(DevGraph g, const i32 *__restrict__ list,
+                                                     const GraphStats *__restrict__ st, i32 *t, i64 *K4,
+                                                     i64 *tau, char *scratch, i64 slice_bytes, int cap,
+                                                     int hc) {
+    __shared__ i64 s_red[4];
+    __shared__ i32 s_red32[4];
+    const int words = (cap + 31) / 32;
+    char *p = scratch + (i64)blockIdx.x * slice_bytes;
+    ProbeMem M;
+    M.acc = (i64 *)p; p += sizeof(i64) * cap;
+    M.hkey = (i32 *)p; p += sizeof(i32) * hc;
+    M.hpos = (i32 *)p; p += sizeof(i32) * hc;
+    M.off = (i32 *)p; p += sizeof(i32) * (cap + 1);
+    M.nb = (i32 *)p; p += sizeof(i32) * cap;
+    M.tcnt = (i32 *)p; p += sizeof(i32) * cap;
+    M.A = (u32 *)p;
+    const i32 cnt = st->cnt[WC_TRI_LARGE];
+    for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
+        probe_item<256, MODE>(g, list[it], threadIdx.x, M, hc, words, t, K4, tau, s_red, s_red32);
+}
+
+i64 probe_large_slice_bytes(int cap, int hc) {
+    int words = (cap + 31) / 32;
+    i64 b = sizeof(i64) * cap + sizeof(i32) * (2 * (i64)hc + 3 * (i64)cap + 1) + sizeof(u32) * (i64)cap * words;
+    return (b + 255) & ~255ll;
+}
+
+// ---------------------------------------------------------------------------
+// Neighbour sums over full rows (one wave per vertex, hubs first).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_sums(DevGraph g, const i32 *__restrict__ t, Accum acc) {
+    int waves = gridDim.x * (blockDim.x / WAVE);
+    int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    for (i32 x = g.n - 1 - wid; x >= 0; x -= waves) {
+        i32 b0 = g.nrp[x], sp = g.nsplit[x], e0 = g.nrp[x + 1];
+        i64 St = 0, Stt = 0, Std = 0, Sd = 0, Sdd = 0;
+        for (i32 s = b0 + lane_id(); s < e0; s += WAVE) {
+            i32 a = g.ncol[s];
+            i64 ta = (s < sp) ? t[g.mirror[s]] : t[s];
+            i64 da = g.ndeg[a];
+            St += ta;
+            Stt += ta * ta;
+            Std += ta * da;
+            Sd += da;
+            Sdd += da * da;
+        }
+        St = wave_sum64(St);
+        Stt = wave_sum64(Stt);
+        Std = wave_sum64(Std);
+        Sd = wave_sum64(Sd);
+        Sdd = wave_sum64(Sdd);
+        if (lane_id() == 0) {
+            acc.St[x] = St;
+            acc.Stt[x] = Stt;
+            acc.Std[x] = Std;
+            acc.Sd[x] = Sd;
+            acc.Sdd[x] = Sdd;
+            acc.T[x] = St >> 1;
+            acc.psi1[x] = Sd - (e0 - b0);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Second neighbour sums and the equations.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void solve_vertex(i64 d, i64 T, i64 psi1, i64 St, i64 Stt, i64 Std, i64 Sd, i64 Sdd,
+                                             i64 ST, i64 Spsi1, i64 tau, i64 Q, i64 k4, i64 *f, i64 *psi,
+                                             int *err) {
+    // f-variables (Table 1) as neighbour sums over a in N(x):
+    const i64 f13 = Stt - St;                                   // sum t(t-1)
+    const i64 f11 = (d - 1) * St - Stt;                         // sum t(d(x)-1-t)
+    const i64 f12 = tau - T;                                    // sum over triangles (t(yz)-1)
+    const i64 f10 = (Std - St) - 2 * tau;                       // sum t(d(a)-1) - 2 tau
+    const i64 f5 = (d - 1) * (Sd - d) - (d - 1) * St - (Std - St) + Stt;
+    const i64 f6 = (Sdd - 3 * Sd + 2 * d) - 2 * Std + 3 * St + Stt;
+    const i64 f9 = 2 * ST - St - 2 * tau;
+    const i64 f4 = Spsi1 - d * (d - 1) - (Std - St) - f9;
+    const i64 f8 = 2 * Q - f13;
+    f[0] = f12; f[1] = f10; f[2] = f13; f[3] = f11; f[4] = f5; f[5] = f6; f[6] = f9; f[7] = f4; f[8] = f8;
+    const i64 h13 = f13, h11 = f11 + f13, h9 = f9, h8 = f13 + f8, h6 = f6 - f13;
+    if ((h13 | h11 | h9 | h8 | h6) & 1) *err = 1;
+    psi[0] = d;
+    psi[1] = psi1;
+    psi[2] = d * (d - 1) / 2;
+    psi[3] = T;
+    psi[4] = 2 * f12 + f4 + f10 + f9;
+    psi[5] = 2 * f12 + f5 + f10 + f11;
+    psi[6] = h6 / 2 + f10 + 2 * f12;
+    psi[7] = d * (d - 1) * (d - 2) / 6;
+    psi[8] = h8 / 2;
+    psi[9] = f12 + h9 / 2;
+    psi[10] = f10 + 2 * f12;
+    psi[11] = h11 / 2;
+    psi[12] = f12;
+    psi[13] = h13 / 2;
+    psi[14] = k4;
+}
+
+__global__ void __launch_bounds__(256) k_solve(DevGraph g, Accum acc, i64 *__restrict__ out,
+                                               i64 *__restrict__ fvars, GraphStats *__restrict__ st) {
+    int waves = gridDim.x * (blockDim.x / WAVE);
+    int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    int err = 0;
+    for (i32 x = g.n - 1 - wid; x >= 0; x -= waves) {
+        i32 b0 = g.nrp[x], e0 = g.nrp[x + 1];
+        i64 ST = 0, Sp = 0;
+        for (i32 s = b0 + lane_id(); s < e0; s += WAVE) {
+            i32 a = g.ncol[s];
+            ST += acc.T[a];
+            Sp += acc.psi1[a];
+        }
+        ST = wave_sum64(ST);
+        Sp = wave_sum64(Sp);
+        // lanes 0..14 each write one column; all compute the same row
+        i64 f[9], psi[15];
+        solve_vertex(e0 - b0, acc.T[x], acc.psi1[x], acc.St[x], acc.Stt[x], acc.Std[x], acc.Sd[x], acc.Sdd[x], ST,
+                     Sp, acc.tau[x], acc.Q[x], acc.K4[x], f, psi, &err);
+        i64 xo = g.order[x];
+        int l = lane_id();
+        if (out && l < 15) {
+            i64 v = 0;
+#pragma unroll
+            for (int k = 0; k < 15; k++) v = (l == k) ? psi[k] : v;
+            out[xo * 15 + l] = v;
+        }
+        if (fvars && l < 9) {
+            i64 v = 0;
+#pragma unroll
+            for (int k = 0; k < 9; k++) v = (l == k) ? f[k] : v;
+            fvars[xo * 9 + l] = v;
+        }
+    }
+    if (err) atomicOr(&st->err, 1);
+}
+
+// ---------------------------------------------------------------------------
+// 4-cycles.
+// ---------------------------------------------------------------------------
+enum { Q_LIGHT = 0, Q_HEAVY = 1 };
+
+// Segment (wedge run) of slot s of item x.
+template <int MODE>
+__device__ __forceinline__ void q_segment(const DevGraph &g, i32 x, i32 s, i32 sp, i32 &v, i32 &beg, i32 &end) {
+    v = g.ncol[s];
+    if (MODE == Q_LIGHT) {
+        beg = g.nrp[v];
+        end = g.mirror[s];
+    } else {
+        beg = (x >= g.h0 && s < sp) ? g.mirror[s] + 1 : g.hstart[v];
+        end = g.nrp[v + 1];
+    }
+}
+
+struct QChunk {
+    i32 *off;    // [dc+1]
+    i32 *vv;     // [dc]
+    i32 *beg;    // [dc]
+    i64 *mid;    // [dc]
+};
+
+// Loads chunk [c0, c0+len) of the item's slots; returns its wedge count.
+template <int NT, int MODE>
+__device__ __forceinline__ i32 q_load_chunk(const DevGraph &g, i32 x, i32 s0, i32 sp, i32 c0, i32 len,
+                                            const QChunk &C, int tid, i32 *red32) {
+    for (int i = tid; i < len; i += NT) {
+        i32 v, b, e;
+        q_segment<MODE>(g, x, s0 + c0 + i, sp, v, b, e);
+        C.vv[i] = v;
+        C.beg[i] = b;
+        C.off[i + 1] = e - b;
+        C.mid[i] = 0;
+    }
+    item_sync<NT>();
+    item_scan<NT>(C.off, len, tid, red32);
+    return C.off[len];
+}
+
+// Hash counter in LDS: keys with counts; used[] lists occupied slots.
+struct QHash {
+    i32 *key;
+    i32 *cnt;
+    i32 *used;
+    i32 *nused;
+    u32 mask;
+};
+
+__device__ __forceinline__ void qhash_inc(const QHash &H, i32 k) {
+    u32 sl = hslot((u32)k, H.mask);
+    while (true) {
+        i32 cur = H.key[sl];
+        if (cur == k) break;
+        if (cur == -1) {
+            i32 prev = atomicCAS(&H.key[sl], -1, k);
+            if (prev == -1) {
+                H.used[atomicAdd(H.nused, 1)] = (i32)sl;
+                break;
+            }
+            if (prev == k) break;
+        }
+        sl = (sl + 1) & H.mask;
+    }
+    atomicAdd(&H.cnt[sl], 1);
+}
+
+__device__ __forceinline__ i32 qhash_get(const QHash &H, i32 k) {
+    u32 sl = hslot((u32)k, H.mask);
+    while (true) {
+        i32 cur = H.key[sl];
+        if (cur == k) return H.cnt[sl];
+        if (cur == -1) return 0;
+        sl = (sl + 1) & H.mask;
+    }
+}
+
+// Counter policies: HashCounter (LDS hash), DenseCounter (16-bit LDS counters over
+// [h0, h0+K)), GlobalCounter (int32 counters over [0, n) in global scratch).
+struct HashCounter {
+    QHash H;
+    __device__ void inc(i32 k) const { qhash_inc(H, k); }
+    __device__ i32 get(i32 k) const { return qhash_get(H, k); }
+};
+
+struct DenseCounter {
+    u32 *w;   // K/2 words
+    i32 h0;
+    __device__ void inc(i32 k) const {
+        i32 i = k - h0;
+        atomicAdd(&w[i >> 1], 1u << ((i & 1) << 4));
+    }
+    __device__ i32 get(i32 k) const {
+        i32 i = k - h0;
+        return (i32)((w[i >> 1] >> ((i & 1) << 4)) & 0xffffu);
+    }
+};
+
+struct GlobalCounter {
+    i32 *c;       // [n] zero between items
+    i32 *used;    // list of touched keys
+    i32 *nused;   // LDS counter
+    __device__ void inc(i32 k) const {
+        if (atomicAdd(&c[k], 1) == 0) used[atomicAdd(nused, 1)] = k;
+    }
+    __device__ i32 get(i32 k) const { return c[k]; }
+};
+
+// Both sweeps over the item's wedges, chunk by chunk.
+template <int NT, int MODE, typename Ctr>
+__device__ __forceinline__ void q_sweeps(const DevGraph &g, i32 x, const Ctr &ctr, const QChunk &C, int dc,
+                                         int tid, i32 *red32, i64 *__restrict__ Q) {
+    const i32 s0 = g.nrp[x], sp = g.nsplit[x];
+    const i32 ns = (MODE == Q_LIGHT) ? sp - s0 : g.nrp[x + 1] - s0;
+    const bool single = ns <= dc;
+    for (int pass = 0; pass < 2; pass++) {
+        for (i32 c0 = 0; c0 < ns; c0 += dc) {
+            i32 len = min(dc, ns - c0);
+            i32 total;
+            if (pass == 0 || !single) {
+                total = q_load_chunk<NT, MODE>(g, x, s0, sp, c0, len, C, tid, red32);
+            } else {
+                total = C.off[len];
+            }
+            for (i32 e = tid; e < total; e += NT) {
+                int i = upper_index<i32>(C.off, 0, len, e);
+                i32 k = g.ncol[C.beg[i] + (e - C.off[i])];
+                if (pass == 0) {
+                    ctr.inc(k);
+                } else {
+                    i32 c = ctr.get(k);
+                    if (c > 1) atomicAdd((unsigned long long *)&C.mid[i], (unsigned long long)(c - 1));
+                }
+            }
+            item_sync<NT>();
+            if (pass == 1) {
+                for (int i = tid; i < len; i += NT) {
+                    i64 m = C.mid[i];
+                    if (m) atomic_add_i64(&Q[C.vv[i]], m);
+                }
+                item_sync<NT>();
+            }
+        }
+    }
+}
+
+template <int NT, int MODE>
+__device__ __forceinline__ void q_item_hash(const DevGraph &g, i32 x, const QHash &H, const QChunk &C, int dc,
+                                            int tid, i64 *red, i32 *red32, i64 *__restrict__ Q) {
+    HashCounter ctr{H};
+    q_sweeps<NT, MODE>(g, x, ctr, C, dc, tid, red32, Q);
+    const i32 nu = *H.nused;
+    i64 local = 0;
+    for (i32 j = tid; j < nu; j += NT) {
+        i32 sl = H.used[j];
+        i64 c = H.cnt[sl];
+        if (c >= 2) {
+            i64 cc = c * (c - 1) / 2;
+            atomic_add_i64(&Q[H.key[sl]], cc);
+            local += cc;
+        }
+        H.key[sl] = -1;
+        H.cnt[sl] = 0;
+    }
+    i64 s = item_sum<NT>(local, red, tid);
+    if (tid == 0) {
+        if (s) atomic_add_i64(&Q[x], s);
+        *H.nused = 0;
+    }
+    item_sync<NT>();
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_q_wave(DevGraph g, const i32 *__restrict__ list,
+                                                const GraphStats *__restrict__ st, int wc, i64 *Q) {
+    constexpr int HC = QL_WAVE_HC, DC = QL_WAVE_DC;
+    __shared__ i32 s_key[4][HC];
+    __shared__ i32 s_cnt[4][HC];
+    __shared__ i32 s_used[4][HC / 2];
+    __shared__ i32 s_nused[4];
+    __shared__ i32 s_off[4][DC + 1];
+    __shared__ i32 s_vv[4][DC];
+    __shared__ i32 s_beg[4][DC];
+    __shared__ i64 s_mid[4][DC];
+    const int w = threadIdx.x / WAVE, tid = lane_id();
+    for (int i = tid; i < HC; i += WAVE) {
+        s_key[w][i] = -1;
+        s_cnt[w][i] = 0;
+    }
+    if (tid == 0) s_nused[w] = 0;
+    item_sync<WAVE>();
+    QHash H{s_key[w], s_cnt[w], s_used[w], &s_nused[w], HC - 1};
+    QChunk C{s_off[w], s_vv[w], s_beg[w], s_mid[w]};
+    const i32 cnt = st->cnt[wc];
+    const int waves = gridDim.x * 4;
+    for (i32 it = blockIdx.x * 4 + w; it < cnt; it += waves)
+        q_item_hash<WAVE, MODE>(g, list[it], H, C, DC, tid, nullptr, nullptr, Q);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) k_q_block(DevGraph g, const i32 *__restrict__ list,
+                                                 const GraphStats *__restrict__ st, int wc, i64 *Q) {
+    constexpr int HC = QL_BLOCK_HC, DC = QL_BLOCK_DC;
+    __shared__ i32 s_key[HC];
+    __shared__ i32 s_cnt[HC];
+    __shared__ i32 s_used[HC / 2];
+    __shared__ i32 s_nused;
+    __shared__ i32 s_off[DC + 1];
+    __shared__ i32 s_vv[DC];
+    __shared__ i32 s_beg[DC];
+    __shared__ i64 s_mid[DC];
+    __shared__ i64 s_red[4];
+    __shared__ i32 s_red32[4];
+    for (int i = threadIdx.x; i < HC; i += 256) {
+        s_key[i] = -1;
+        s_cnt[i] = 0;
+    }
+    if (threadIdx.x == 0) s_nused = 0;
+    __syncthreads();
+    QHash H{s_key, s_cnt, s_used, &s_nused, HC - 1};
+    QChunk C{s_off, s_vv, s_beg, s_mid};
+    const i32 cnt = st->cnt[wc];
+    for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
+        q_item_hash<256, MODE>(g, list[it], H, C, DC, threadIdx.x, s_red, s_red32, Q);
+}
+
+// Heavy largest vertices: dense 16-bit counters over [h0, n).
+#define QD_NT 512
+#define QD_DC 1024
+__global__ void __launch_bounds__(QD_NT) k_q_dense(DevGraph g, const i32 *__restrict__ list,
+                                                   const GraphStats *__restrict__ st, i64 *Q) {
+    __shared__ u32 s_w[QH_DENSE_K / 2];
+    __shared__ i32 s_off[QD_DC + 1];
+    __shared__ i32 s_vv[QD_DC];
+    __shared__ i32 s_beg[QD_DC];
+    __shared__ i64 s_mid[QD_DC];
+    __shared__ i64 s_red[QD_NT / WAVE];
+    __shared__ i32 s_red32[QD_NT / WAVE];
+    const i32 K = g.n - g.h0;
+    const i32 KW = (K + 1) >> 1;
+    for (int i = threadIdx.x; i < KW; i += QD_NT) s_w[i] = 0u;
+    __syncthreads();
+    DenseCounter ctr{s_w, g.h0};
+    QChunk C{s_off, s_vv, s_beg, s_mid};
+    const i32 cnt = st->cnt[WC_QH_DENSE];
+    for (i32 it = blockIdx.x; it < cnt; it += gridDim.x) {
+        i32 x = list[it];
+        q_sweeps<QD_NT, Q_HEAVY>(g, x, ctr, C, QD_DC, threadIdx.x, s_red32, Q);
+        i64 local = 0;
+        for (i32 i = threadIdx.x; i < KW; i += QD_NT) {
+            u32 word = s_w[i];
+            if (word) {
+                i64 c0 = word & 0xffffu, c1 = word >> 16;
+                if (c0 >= 2) {
+                    i64 cc = c0 * (c0 - 1) / 2;
+                    atomic_add_i64(&Q[g.h0 + 2 * i], cc);
+                    local += cc;
+                }
+                if (c1 >= 2) {
+                    i64 cc = c1 * (c1 - 1) / 2;
+                    atomic_add_i64(&Q[g.h0 + 2 * i + 1], cc);
+                    local += cc;
+                }
+                s_w[i] = 0u;
+            }
+        }
+        i64 s = item_sum<QD_NT>(local, s_red, threadIdx.x);
+        if (threadIdx.x == 0 && s) atomic_add_i64(&Q[x], s);
+        __syncthreads();
+    }
+}
+
+// Light largest vertices whose wedges overflow the LDS hash: int32 counters over
+// [0, n) in per-workgroup global scratch, touched keys listed for clearing.
+#define QG_NT 256
+#define QG_DC 1024
+template <int MODE>
+__global__ void __launch_bounds__(QG_NT) k_q_global(DevGraph g, const i32 *__restrict__ list,
+                                                    const GraphStats *__restrict__ st, int wc, i64 *Q,
+                                                    i32 *scratch, i64 slice_elems) {
+    __shared__ i32 s_off[QG_DC + 1];
+    __shared__ i32 s_vv[QG_DC];
+    __shared__ i32 s_beg[QG_DC];
+    __shared__ i64 s_mid[QG_DC];
+    __shared__ i64 s_red[QG_NT / WAVE];
+    __shared__ i32 s_red32[QG_NT / WAVE];
+    __shared__ i32 s_nused;
+    i32 *cnt_arr = scratch + (i64)blockIdx.x * slice_elems;
+    i32 *used = cnt_arr + g.n;
+    if (threadIdx.x == 0) s_nused = 0;
+    __syncthreads();
+    GlobalCounter ctr{cnt_arr, used, &s_nused};
+    QChunk C{s_off, s_vv, s_beg, s_mid};
+    const i32 cnt = st->cnt[wc];
+    for (i32 it = blockIdx.x; it < cnt; it += gridDim.x) {
+        i32 x = list[it];
+        q_sweeps<QG_NT, MODE>(g, x, ctr, C, QG_DC, threadIdx.x, s_red32, Q);
+        __threadfence_block();
+        const i32 nu = s_nused;
+        i64 local = 0;
+        for (i32 j = threadIdx.x; j < nu; j += QG_NT) {
+            i32 k = used[j];
+            i64 c = cnt_arr[k];
+            if (c >= 2) {
+                i64 cc = c * (c - 1) / 2;
+                atomic_add_i64(&Q[k], cc);
+                local += cc;
+            }
+            cnt_arr[k] = 0;
+        }
+        i64 s = item_sum<QG_NT>(local, s_red, threadIdx.x);
+        if (threadIdx.x == 0) {
+            if (s) atomic_add_i64(&Q[x], s);
+            s_nused = 0;
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch helpers (called from the API file).
+// ---------------------------------------------------------------------------
+hipError_t launch_classify(const DevGraph &g, const i64 *wl, const i64 *wh, const ListPtrs &lists, GraphStats *st,
+                           const Thresholds &th, hipStream_t s) {
+    if (g.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_classify, dim3((g.n + 255) / 256), dim3(256), 0, s, g, wl, wh, lists, st, th);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe(int mode, const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i32 *t,
+                        i64 *K4, i64 *tau, char *large_scratch, i64 large_slice, int large_cap, int large_hc,
+                        int large_blocks, int grid_wave, int grid_block, hipStream_t s) {
+    if (mode == PROBE_TRI) {
+        hipLaunchKernelGGL(k_probe_wave<PROBE_TRI>, dim3(grid_wave), dim3(256), 0, s, g, lists_host[WC_TRI_WAVE], st,
+                           t, K4, tau);
+        hipLaunchKernelGGL(k_probe_block<PROBE_TRI>, dim3(grid_block), dim3(256), 0, s, g,
+                           lists_host[WC_TRI_BLOCK], st, t, K4, tau);
+        if (large_blocks > 0)
+            hipLaunchKernelGGL(k_probe_large<PROBE_TRI>, dim3(large_blocks), dim3(256), 0, s, g,
+                               lists_host[WC_TRI_LARGE], st, t, K4, tau, large_scratch, large_slice, large_cap,
+                               large_hc);
+    } else {
+        hipLaunchKernelGGL(k_probe_wave<PROBE_TAU>, dim3(grid_wave), dim3(256), 0, s, g, lists_host[WC_TRI_WAVE], st,
+                           t, K4, tau);
+        hipLaunchKernelGGL(k_probe_block<PROBE_TAU>, dim3(grid_block), dim3(256), 0, s, g,
+                           lists_host[WC_TRI_BLOCK], st, t, K4, tau);
+        if (large_blocks > 0)
+            hipLaunchKernelGGL(k_probe_large<PROBE_TAU>, dim3(large_blocks), dim3(256), 0, s, g,
+                               lists_host[WC_TRI_LARGE], st, t, K4, tau, large_scratch, large_slice, large_cap,
+                               large_hc);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sums(const DevGraph &g, const i32 *t, const Accum &acc, int grid, hipStream_t s) {
+    if (g.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sums, dim3(grid), dim3(256), 0, s, g, t, acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvars, GraphStats *st, int grid,
+                        hipStream_t s) {
+    if (g.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_solve, dim3(grid), dim3(256), 0, s, g, acc, out, fvars, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i64 *Q, i32 *gscratch,
+                    i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, hipStream_t s) {
+    hipLaunchKernelGGL(k_q_wave<Q_LIGHT>, dim3(grid_wave), dim3(256), 0, s, g, lists_host[WC_QL_WAVE], st,
+                       (int)WC_QL_WAVE, Q);
+    hipLaunchKernelGGL(k_q_block<Q_LIGHT>, dim3(grid_block), dim3(256), 0, s, g, lists_host[WC_QL_BLOCK], st,
+                       (int)WC_QL_BLOCK, Q);
+    if (gblocks > 0)
+        hipLaunchKernelGGL(k_q_global<Q_LIGHT>, dim3(gblocks), dim3(QG_NT), 0, s, g, lists_host[WC_QL_GLOBAL], st,
+                           (int)WC_QL_GLOBAL, Q, gscratch, gslice);
+    hipLaunchKernelGGL(k_q_wave<Q_HEAVY>, dim3(grid_wave), dim3(256), 0, s, g, lists_host[WC_QH_WAVE], st,
+                       (int)WC_QH_WAVE, Q);
+    hipLaunchKernelGGL(k_q_block<Q_HEAVY>, dim3(grid_block), dim3(256), 0, s, g, lists_host[WC_QH_BLOCK], st,
+                       (int)WC_QH_BLOCK, Q);
+    hipLaunchKernelGGL(k_q_dense, dim3(grid_dense), dim3(QD_NT), 0, s, g, lists_host[WC_QH_DENSE], st, Q);
+    if (gblocks > 0)
+        hipLaunchKernelGGL(k_q_global<Q_HEAVY>, dim3(gblocks), dim3(QG_NT), 0, s, g, lists_host[WC_QH_GLOBAL], st,
+                           (int)WC_QH_GLOBAL, Q, gscratch, gslice);
+    return hipGetLastError();
+}

@@ -1,0 +1,118 @@
+// Internal interfaces between the host API and the kernel files.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#ifndef __HIPCC_RTC__
+#include "common.hpp"
+#endif
+
+// Statistics gathered on the device and read back once per count.
+struct GraphStats {
+    int dmax;        // largest degree
+    int dplus_max;   // largest |N+|
+    int err;         // device-side consistency flag (odd numerator)
+    int pad;         // counter of long N+ rows queued for the workgroup sort
+    int bad_input;   // row_ptr or col out of range (checked before any use)
+    int pad2[3];
+    // work-class list sizes (filled by the classification kernel)
+    int cnt[16];
+};
+
+// Classes of work items (indices into GraphStats::cnt and the list table).
+enum WorkClass {
+    WC_TRI_WAVE = 0,   // Stage I/II/tau, 2 <= |N+(u)| <= 64, one wave per vertex
+    WC_TRI_BLOCK,      // 64 < |N+(u)| <= 512, one workgroup
+    WC_TRI_LARGE,      // |N+(u)| > 512, one workgroup with global scratch
+    WC_QL_WAVE,        // 4-cycles, u as largest vertex (u < h0), small hash per wave
+    WC_QL_BLOCK,       // larger LDS hash per workgroup
+    WC_QL_GLOBAL,      // dense counters in global scratch
+    WC_QH_WAVE,        // 4-cycles, w opposite a heavy largest vertex, small hash per wave
+    WC_QH_BLOCK,       // hash per workgroup
+    WC_QH_DENSE,       // dense 16-bit LDS counters over the heavy range
+    WC_QH_GLOBAL,      // heavy-range items of degree >= 2^16: int32 counters in global scratch
+    WC_COUNT
+};
+
+struct ListPtrs {
+    i32 *l[WC_COUNT];
+};
+
+// Runtime class thresholds (each at most the capacity of its kernel).
+struct Thresholds {
+    int tri_wave;    // |N+| <= tri_wave -> wave class (<= TRI_WAVE_CAP)
+    int tri_block;   // |N+| <= tri_block -> workgroup class (<= TRI_BLOCK_CAP)
+    i64 ql_wave;     // wedges <= ql_wave -> wave hash (<= QL_WAVE_HC/2)
+    i64 ql_block;    // wedges <= ql_block -> workgroup hash (<= QL_BLOCK_HC/2)
+    i64 qh_wave;
+    i64 qh_block;
+};
+
+// Class capacities (shared by classification and kernels).
+#define TRI_WAVE_CAP 64
+#define TRI_BLOCK_CAP 512
+#define QL_WAVE_HC 512      // hash entries per wave, light 4-cycle items (W <= HC/2)
+#define QL_WAVE_DC 64       // segment (row slot) capacity per wave item
+#define QL_BLOCK_HC 8192
+#define QL_BLOCK_DC 1024
+#define QH_WAVE_HC 512
+#define QH_WAVE_DC 64
+#define QH_BLOCK_HC 8192
+#define QH_BLOCK_DC 1024
+#define QH_DENSE_K 32768    // size of the heavy key range (top-ranked vertices)
+#define QH_DENSE_DC 4096    // middles accumulated in LDS by the dense kernel (else global)
+
+// Per-vertex accumulators (new vertex ids), all int64[n].
+struct Accum {
+    i64 *St, *Stt, *Std, *Sd, *Sdd;  // neighbour sums of t, t^2, t*d(a), d(a), d(a)^2
+    i64 *T, *psi1;                   // triangles at x; non-induced 3-path ends
+    i64 *tau;                        // sum over triangles at x of t(opposite edge)
+    i64 *Q;                          // 4-cycles through x
+    i64 *K4;                         // 4-cliques containing x
+};
+
+// Everything the counting kernels read about the relabelled graph.
+struct DevGraph {
+    i32 n;
+    i32 nnz;
+    i32 h0;                 // first id of the heavy range (top QH_DENSE_K ranks)
+    const i32 *nrp;         // int32[n+1]
+    const i32 *nsplit;      // int32[n]: first slot of N+(y)
+    const i32 *ncol;        // int32[nnz]
+    const i32 *mirror;      // int32[nnz]: for lower slots, slot of y inside N+(b)
+    const i32 *hstart;      // int32[n]: first slot of N+(y) with id >= h0
+    const u32 *ndeg;        // uint32[n]: degree by new id
+    const u32 *order;       // uint32[n]: new id -> input id
+};
+
+// prep.hip
+i64 scan_ws_elems(i64 len);
+i64 radix_ws_elems(i64 n);
+hipError_t scan_u32_to_i32(const u32 *in, i64 len, i32 *out, i32 *ws, int write_total, hipStream_t s);
+hipError_t scan_i32_to_i32(const i32 *in, i64 len, i32 *out, i32 *ws, int write_total, hipStream_t s);
+hipError_t radix_sort_pairs(u32 *k, u32 *v, u32 *k2, u32 *v2, i64 n, int bits, i32 *hist, i32 *scan_ws,
+                            hipStream_t s);
+__global__ void k_degree(i32 n, i64 nnz, const i64 *rp, u32 *deg, u32 *vals, GraphStats *st);
+__global__ void k_invert(i32 n, const u32 *order, i32 *perm);
+__global__ void k_relabel(i32 n, const i64 *rp, const i32 *col, const u32 *order, const i32 *perm,
+                          const u32 *ndeg, const i32 *nrp, i32 *nsplit, i32 *ncol, GraphStats *st);
+__global__ void k_sort_upper_small(i32 n, const i32 *nrp, const i32 *nsplit, i32 *ncol, i32 *hstart, i32 h0,
+                                   i32 *longlist, i32 *longcount);
+__global__ void k_sort_upper_large(const i32 *nrp, const i32 *nsplit, i32 *ncol, i32 *hstart, i32 h0,
+                                   const i32 *longlist, const i32 *longcount);
+__global__ void k_mirror(i32 n, const i32 *nrp, const i32 *nsplit, const i32 *ncol, const i32 *hstart, i32 h0,
+                         i32 *mirror, i64 *wlight, i64 *wheavy);
+#define LSORT_CAP 16384
+
+// count.hip
+hipError_t launch_classify(const DevGraph &g, const i64 *wl, const i64 *wh, const ListPtrs &lists, GraphStats *st,
+                           const Thresholds &th, hipStream_t s);
+hipError_t launch_probe(int mode, const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i32 *t,
+                        i64 *K4, i64 *tau, char *large_scratch, i64 large_slice, int large_cap, int large_hc,
+                        int large_blocks, int grid_wave, int grid_block, hipStream_t s);
+hipError_t launch_sums(const DevGraph &g, const i32 *t, const Accum &acc, int grid, hipStream_t s);
+hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvars, GraphStats *st, int grid,
+                        hipStream_t s);
+hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i64 *Q, i32 *gscratch,
+                    i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, hipStream_t s);
+i64 probe_large_slice_bytes(int cap, int hc);

@@ -1,0 +1,68 @@
+"""Full-size parity on the bench workload (Chung-Lu, n = 4M, ~39M edges), in the
+launch configuration bench.py times: the whole n x 15 matrix is computed on the
+GPU; the CPU oracle recomputes sampled vertices one by one (uniform sample plus
+vertices of high degree), and orbit-sum identities that hold for any graph are
+checked on the complete output."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def column_identities(psi, g, tri_edges):
+    """Sums over all vertices that equal graphlet counts times orbit sizes."""
+    s = psi.sum(0, dtype=np.int64)
+    d = g.degrees().astype(np.int64)
+    e = g.edges()
+    c2 = int((d * (d - 1) // 2).sum())
+    c3 = int((d * (d - 1) * (d - 2) // 6).sum())
+    assert s[0] == 2 * g.m
+    assert s[1] == 2 * c2 and s[2] == c2
+    assert s[3] % 3 == 0
+    T = int(s[3] // 3)
+    p4 = int(((d[e[:, 0]] - 1) * (d[e[:, 1]] - 1)).sum()) - 3 * T
+    assert s[4] == 2 * p4 and s[5] == 2 * p4
+    assert s[6] == 3 * c3 and s[7] == c3
+    assert s[8] % 4 == 0 and s[14] % 4 == 0
+    tt = int((psi[:, 3] * (d - 2)).sum())
+    assert s[9] == tt and s[11] == tt and s[10] == 2 * tt
+    # per undirected edge, from the GPU's Stage I output (each edge appears twice)
+    dia = int((tri_edges.astype(np.int64) * (tri_edges.astype(np.int64) - 1) // 2).sum() // 2)
+    assert s[12] == 2 * dia and s[13] == 2 * dia
+
+
+def test_chung_lu_4m_sampled(tmp_path):
+    import torch
+    import oracle
+    import paper_2606_29651_amd as ni
+    oracle.build(force=False)
+    t0 = time.time()
+    g = gg.config_graph("chung_lu_4m")
+    _say(f"[gpu] chung_lu_4m generated n={g.n} m={g.m} in {time.time() - t0:.0f}s")
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    cl = torch.from_numpy(g.col).cuda()
+    psi = ni.count(rp, cl).cpu().numpy()
+    tri = ni.edge_triangles(rp, cl).cpu().numpy()
+    torch.cuda.synchronize()
+    _say("[gpu] counted; checking identities")
+    column_identities(psi, g, tri)
+    rng = np.random.default_rng(2024)
+    d = g.degrees()
+    uniform = rng.choice(g.n, 48, replace=False)
+    mid = np.flatnonzero((d >= 300) & (d <= 2500))
+    hubs = rng.choice(mid, min(6, len(mid)), replace=False)
+    xs = np.unique(np.concatenate([uniform, hubs])).astype(np.int32)
+    t0 = time.time()
+    ref = oracle.orbits_at(g.row_ptr, g.col, xs)
+    _say(f"[gpu] oracle on {len(xs)} vertices in {time.time() - t0:.0f}s")
+    assert np.array_equal(psi[xs], ref)
