@@ -85,6 +85,8 @@ uint64_t niorca_workspace_bytes(const niorca_ctx *ctx);
  *   "qh_wave"   0..256   4-cycle wedges opposite a heavy largest vertex: wave hash
  *   "qh_block"  0..4096  ... workgroup hash; above: dense LDS counters
  *   "heavy_k"   0..32768 how many top-ranked vertices form the heavy range
+ *   "tri_cache" 0..2^34  triangles kept from Stage I for the tau pass (8 bytes each;
+ *                        vertices whose triangles do not fit are probed again)
  * Returns EINVAL for an unknown name or a value out of range. */
 niorca_status niorca_set_param(niorca_ctx *ctx, const char *name, int64_t value);
 

@@ -32,6 +32,7 @@ struct niorca_ctx {
     // tunable class thresholds and the size of the heavy 4-cycle key range
     Thresholds th{TRI_WAVE_CAP, TRI_BLOCK_CAP, QL_WAVE_HC / 2, QL_BLOCK_HC / 2, QH_WAVE_HC / 2, QH_BLOCK_HC / 2};
     int32_t heavy_k = QH_DENSE_K;
+    int64_t tri_cache_records = (int64_t)1 << 29;  // 4 GiB of kept triangles for the tau pass
 };
 
 static niorca_status fail(niorca_ctx *c, niorca_status s, const char *fmt, ...) {
@@ -130,6 +131,9 @@ extern "C" niorca_status niorca_set_param(niorca_ctx *ctx, const char *name, int
     if (k == "heavy_k") {
         if (value < 0 || value > QH_DENSE_K) return bad(0, QH_DENSE_K);
         ctx->heavy_k = (int32_t)value;
+    } else if (k == "tri_cache") {
+        if (value < 0 || value > ((int64_t)1 << 34)) return bad(0, (int64_t)1 << 34);
+        ctx->tri_cache_records = value;
     } else if (k == "tri_wave") {
         if (value < 1 || value > TRI_WAVE_CAP) return bad(1, TRI_WAVE_CAP);
         ctx->th.tri_wave = (int)value;
@@ -266,6 +270,9 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     uint64_t o_lists[WC_COUNT];
     for (int c = 0; c < WC_COUNT; c++) o_lists[c] = A.take<i32>(n);
     uint64_t o_acc = A.take<i64>((uint64_t)n * 10);
+    uint64_t o_tcoff = A.take<i64>(n), o_tccnt = A.take<i32>(n), o_tcbump = A.take<u64>(1);
+    const i64 tc_cap = ctx->tri_cache_records;
+    uint64_t o_tcrec = A.take<u64>((uint64_t)(tc_cap > 0 ? tc_cap : 1));
     uint64_t base_bytes = A.off;
 
     // Validation first (it reads only the input).
@@ -336,6 +343,8 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     const int large_blocks = large_cap ? 2 * cu : 0;
     const i64 large_slice = large_cap ? probe_large_slice_bytes(large_cap, large_hc) : 0;
     uint64_t o_large = A.take<char>((uint64_t)large_slice * large_blocks);
+    const int part_rows = QH_PART_ROWS;
+    uint64_t o_part = A.take<i64>((uint64_t)part_rows * (uint64_t)(n - h0));
     const int gblocks = 32;
     const i64 gslice = 2 * (i64)n + 64;
     uint64_t o_g = A.take<i32>((uint64_t)gslice * gblocks);
@@ -347,6 +356,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     }
     char *large_scratch = W + o_large;
     i32 *gscratch = (i32 *)(W + o_g);
+    i64 *qpart = (i64 *)(W + o_part);
     HIP_TRY(hipMemsetAsync(gscratch, 0, sizeof(i32) * (size_t)gslice * gblocks, s));
     // ---- oriented layout: sorted N+, mirror slots, per-vertex 4-cycle work ----
     HIP_TRY(hipMemsetAsync(longcount, 0, sizeof(i32), s));
@@ -357,7 +367,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
                        longcount);
     hipLaunchKernelGGL(k_mirror, dim3(cu * 8), dim3(nthr), 0, s, n, nrp, nsplit, ncol, hstart, h0, mirror, wl, wh);
     HIP_TRY(hipGetLastError());
-    DevGraph g{n, (i32)nnz, h0, nrp, nsplit, ncol, mirror, hstart, deg, val};
+    DevGraph g{n, (i32)nnz, h0, nrp, nsplit, ncol, mirror, hstart, deg, val, wl, wh};
     HIP_TRY(launch_classify(g, wl, wh, lists, dst, ctx->th, s));
     STAGE_MARK(3);
     i32 *lh[WC_COUNT];
@@ -365,8 +375,11 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     // ---- Stage I (t) and Stage II (K4) ----
     HIP_TRY(hipMemsetAsync(t, 0, sizeof(i32) * (size_t)nnz, s));
     HIP_TRY(hipMemsetAsync(accb, 0, sizeof(i64) * 10 * (size_t)n, s));
+    TriCacheArgs tca{tc_cap > 0 ? (u64 *)(W + o_tcrec) : nullptr, tc_cap, (u64 *)(W + o_tcbump),
+                     (i64 *)(W + o_tcoff), (i32 *)(W + o_tccnt), 1 << 14, 1 << 18};
+    HIP_TRY(hipMemsetAsync(tca.bump, 0, sizeof(u64), s));
     STAGE_MARK(4);
-    HIP_TRY(launch_probe(0, g, lh, dst, t, acc.K4, acc.tau, large_scratch, large_slice, large_cap, large_hc,
+    HIP_TRY(launch_probe(0, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, large_slice, large_cap, large_hc,
                          large_blocks, cu * 8, cu * 2, s));
     STAGE_MARK(5);
     if (o.tri) {
@@ -382,10 +395,10 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     // ---- Stage III-a: neighbour sums, tau, 4-cycles ----
     HIP_TRY(launch_sums(g, t, acc, cu * 8, s));
     STAGE_MARK(6);
-    HIP_TRY(launch_probe(1, g, lh, dst, t, acc.K4, acc.tau, large_scratch, large_slice, large_cap, large_hc,
+    HIP_TRY(launch_probe(1, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, large_slice, large_cap, large_hc,
                          large_blocks, cu * 8, cu * 2, s));
     STAGE_MARK(7);
-    HIP_TRY(launch_q(g, lh, dst, acc.Q, gscratch, gslice, gblocks, cu * 8, cu, cu, s));
+    HIP_TRY(launch_q(g, lh, dst, acc.Q, gscratch, gslice, gblocks, cu * 4, cu * 4, cu * 2, qpart, part_rows, s));
     STAGE_MARK(8);
     // ---- Stage III-b: equations ----
     HIP_TRY(launch_solve(g, acc, o.psi, o.fvars, dst, cu * 8, s));

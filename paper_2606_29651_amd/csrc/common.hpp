@@ -71,4 +71,53 @@ __device__ __forceinline__ i32 lower_bound_i32(const i32 *a, i32 lo, i32 hi, i32
     return lo;
 }
 
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Segment index of element e0 + lane, for the 64 consecutive elements of one wave.
+// Segments are given by a non-decreasing prefix off[0..nseg] (off[0] = 0, off[nseg] =
+// total, e0 < total).  One binary search per wave finds the segment of e0; the later
+// segment starts inside the 64-element window are marked in LDS and spread to the
+// lanes by a prefix maximum.  All 64 lanes must call it with the same e0.  `mark`
+// is this wave's 64-int LDS array, all -1 on entry and again on return.
+__device__ __forceinline__ int locate64(const i32 *off, int nseg, i32 e0, i32 *mark) {
+    const int lane = lane_id();
+    const int lo = upper_index<i32>(off, 0, nseg, e0);
+    for (int k0 = lo + 1; k0 < nseg; k0 += WAVE) {
+        int j = k0 + lane;
+        i32 st = j < nseg ? off[j] : 0x7fffffff;
+        bool in = st < e0 + WAVE;
+        if (in) atomicMax(&mark[st - e0], j);  // empty segments share a start: the last one wins
+        if (!(__ballot(in) >> 63)) break;
+    }
+    wave_fence();
+    int v = mark[lane];
+    wave_fence();
+    mark[lane] = -1;
+    if (lane == 0) v = lo;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        int t = __shfl_up(v, o, WAVE);
+        if (lane >= o) v = max(v, t);
+    }
+    return v;
+}
+
+// Inclusive sum over runs of equal `key` in consecutive lanes; *last is set on the
+// last lane of each run, which then holds the run total.
+__device__ __forceinline__ i64 wave_run_sum(i64 v, int key, bool *last) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        i64 t = __shfl_up(v, o, WAVE);
+        int k = __shfl_up(key, o, WAVE);
+        if (lane >= o && k == key) v += t;
+    }
+    int nk = __shfl_down(key, 1, WAVE);
+    *last = (lane == WAVE - 1) || nk != key;
+    return v;
+}
+
 #define HIP_CHECK_LAUNCH() (hipGetLastError())

@@ -110,11 +110,13 @@ __global__ void k_classify(DevGraph g, const i64 *__restrict__ wlight, const i64
     list_push(qlw, WC_QL_WAVE, y, lists, st);
     list_push(qlb, WC_QL_BLOCK, y, lists, st);
     list_push(qlg, WC_QL_GLOBAL, y, lists, st);
-    bool qhw = valid && wh > 0 && wh <= th.qh_wave;
-    bool qhb = valid && wh > th.qh_wave && wh <= th.qh_block;
-    // dense 16-bit counters need every count below 2^16; counts are bounded by d(x)
-    bool qhd = valid && wh > th.qh_block && d < 65536;
-    bool qhg = valid && wh > th.qh_block && d >= 65536;
+    // packed 17-bit and dense 16-bit counters need every count below 2^16; a count
+    // is at most d(x), so vertices of degree >= 2^16 use int32 global counters
+    bool small_d = d < 65536;
+    bool qhw = valid && small_d && wh > 0 && wh <= th.qh_wave;
+    bool qhb = valid && small_d && wh > th.qh_wave && wh <= th.qh_block;
+    bool qhd = valid && small_d && wh > th.qh_block;
+    bool qhg = valid && !small_d && wh > 0;
     list_push(qhw, WC_QH_WAVE, y, lists, st);
     list_push(qhb, WC_QH_BLOCK, y, lists, st);
     list_push(qhd, WC_QH_DENSE, y, lists, st);
@@ -127,6 +129,8 @@ __global__ void k_classify(DevGraph g, const i64 *__restrict__ wlight, const i64
 // ---------------------------------------------------------------------------
 enum { PROBE_TRI = 0, PROBE_TAU = 1 };
 
+#define QU 4  // elements per thread per step in the flattened loops
+
 struct ProbeMem {
     i32 *hkey;   // [hc]
     i32 *hpos;   // [hc]
@@ -137,12 +141,60 @@ struct ProbeMem {
     i64 *acc;    // [cap]
 };
 
+// Triangle records kept by Stage I for the tau pass: one u64 per triangle found at
+// its lowest vertex u, (slot of v->w) << 32 | p << 16 | i, where i and p are the
+// positions of v and w in N+(u).  Vertex u owns records [off[u], off[u]+cnt[u]);
+// cnt[u] = -1 means its records were not kept and tau probes it again.  Space is
+// handed out in chunks per wave/workgroup, so there is one global atomic per chunk.
+struct TriCache {
+    u64 *rec;
+    i64 cap;        // records
+    u64 *bump;      // next free record
+    i64 *off;       // int64[n]
+    i32 *cnt;       // int32[n]
+    i64 chunk;      // records reserved at a time
+};
+
+struct ItemState {  // per item group, in LDS
+    i64 chunk_cur, chunk_end, item_base;
+    i32 item_ok, item_cnt;
+};
+
 template <int NT, int MODE>
 __device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, const ProbeMem &M, int hc,
                                            int words, i32 *__restrict__ t, i64 *__restrict__ K4,
-                                           i64 *__restrict__ tau, i64 *red, i32 *red32) {
+                                           i64 *__restrict__ tau, i64 *red, i32 *red32, const TriCache &tc,
+                                           ItemState *S) {
     const i32 base = g.nsplit[u];
     const i32 du = g.nrp[u + 1] - base;
+    if (MODE == PROBE_TAU && tc.cnt[u] >= 0) {
+        // cached triangles: tau from the records and the final t values
+        for (int i = tid; i < du; i += NT) {
+            M.nb[i] = g.ncol[base + i];
+            M.tcnt[i] = t[base + i];
+            M.acc[i] = 0;
+        }
+        item_sync<NT>();
+        const i64 r0 = tc.off[u], r1 = r0 + tc.cnt[u];
+        i64 tau_local = 0;
+        for (i64 r = r0 + tid; r < r1; r += NT) {
+            u64 rec = tc.rec[r];
+            int i = (int)(rec & 0xffffu), p = (int)((rec >> 16) & 0xffffu);
+            i32 q = (i32)(rec >> 32);
+            tau_local += t[q];
+            atomicAdd((unsigned long long *)&M.acc[i], (unsigned long long)M.tcnt[p]);
+            atomicAdd((unsigned long long *)&M.acc[p], (unsigned long long)M.tcnt[i]);
+        }
+        item_sync<NT>();
+        for (int j = tid; j < du; j += NT) {
+            i64 a = M.acc[j];
+            if (a) atomic_add_i64(&tau[M.nb[j]], a);
+        }
+        i64 s = item_sum<NT>(tau_local, red, tid);
+        if (tid == 0 && s) atomic_add_i64(&tau[u], s);
+        item_sync<NT>();
+        return;
+    }
     const u32 hmask = (u32)hc - 1;
     const int nw = (du + 31) >> 5;
     for (int i = tid; i < hc; i += NT) M.hkey[i] = -1;
@@ -163,27 +215,68 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, co
     item_sync<NT>();
     item_scan<NT>(M.off, du, tid, red32);
     const i32 total = M.off[du];
-    i64 tau_local = 0;
-    for (i32 e = tid; e < total; e += NT) {
-        int i = upper_index<i32>(M.off, 0, du, e);
-        i32 v = M.nb[i];
-        i32 q = g.nsplit[v] + (e - M.off[i]);
-        i32 w = g.ncol[q];
-        u32 sl = hslot((u32)w, hmask);
-        int p = -1;
-        while (true) {
-            i32 k = M.hkey[sl];
-            if (k == w) { p = M.hpos[sl]; break; }
-            if (k == -1) break;
-            sl = (sl + 1) & hmask;
+    if (MODE == PROBE_TRI && tid == 0) {
+        // room for every possible triangle of this item: min(probes, C(du, 2))
+        i64 ub = min((i64)total, (i64)du * (du - 1) / 2);
+        S->item_ok = 0;
+        S->item_cnt = 0;
+        if (tc.rec && ub <= tc.chunk) {
+            if (S->chunk_end - S->chunk_cur < ub) {
+                u64 b = atomicAdd((unsigned long long *)tc.bump, (unsigned long long)tc.chunk);
+                if ((i64)b + tc.chunk <= tc.cap) {
+                    S->chunk_cur = (i64)b;
+                    S->chunk_end = (i64)b + tc.chunk;
+                } else {
+                    S->chunk_cur = S->chunk_end = 0;
+                }
+            }
+            if (S->chunk_end - S->chunk_cur >= ub) {
+                S->item_ok = 1;
+                S->item_base = S->chunk_cur;
+            }
         }
-        if (p >= 0) {
+    }
+    item_sync<NT>();
+    const bool keep = MODE == PROBE_TRI && S->item_ok;
+    const i64 item_base = keep ? S->item_base : 0;
+    i64 tau_local = 0;
+    for (i32 eb = tid; eb < total; eb += NT * QU) {
+        int si[QU];
+        i32 qq[QU], ww[QU];
+        bool ok[QU];
+#pragma unroll
+        for (int u = 0; u < QU; u++) {
+            i32 e = eb + u * NT;
+            ok[u] = e < total;
+            si[u] = ok[u] ? upper_index<i32>(M.off, 0, du, e) : 0;
+            qq[u] = ok[u] ? g.nsplit[M.nb[si[u]]] + (e - M.off[si[u]]) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < QU; u++) ww[u] = ok[u] ? g.ncol[qq[u]] : -1;
+#pragma unroll
+        for (int u = 0; u < QU; u++) {
+            if (!ok[u]) continue;
+            const int i = si[u];
+            const i32 q = qq[u], w = ww[u];
+            u32 sl = hslot((u32)w, hmask);
+            int p = -1;
+            while (true) {
+                i32 k = M.hkey[sl];
+                if (k == w) { p = M.hpos[sl]; break; }
+                if (k == -1) break;
+                sl = (sl + 1) & hmask;
+            }
+            if (p < 0) continue;
             if (MODE == PROBE_TRI) {
                 atomicAdd(&M.tcnt[i], 1);
                 atomicAdd(&M.tcnt[p], 1);
                 atomicAdd(&t[q], 1);
                 atomicOr(&M.A[i * words + (p >> 5)], 1u << (p & 31));
                 atomicOr(&M.A[p * words + (i >> 5)], 1u << (i & 31));
+                if (keep) {
+                    i32 r = atomicAdd(&S->item_cnt, 1);
+                    tc.rec[item_base + r] = ((u64)(u32)q << 32) | ((u64)p << 16) | (u64)i;
+                }
             } else {
                 tau_local += t[q];
                 atomicAdd((unsigned long long *)&M.acc[i], (unsigned long long)t[base + p]);
@@ -193,6 +286,15 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, co
     }
     item_sync<NT>();
     if (MODE == PROBE_TRI) {
+        if (tid == 0) {
+            if (keep) {
+                tc.off[u] = item_base;
+                tc.cnt[u] = S->item_cnt;
+                S->chunk_cur += S->item_cnt;
+            } else {
+                tc.cnt[u] = -1;
+            }
+        }
         i64 s_local = 0;
         for (int j = tid; j < du; j += NT) {
             i32 c = M.tcnt[j];
@@ -228,7 +330,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, co
 template <int MODE>
 __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__restrict__ list,
                                                     const GraphStats *__restrict__ st, i32 *t, i64 *K4,
-                                                    i64 *tau) {
+                                                    i64 *tau, TriCache tc) {
     constexpr int CAP = TRI_WAVE_CAP, HC = 2 * CAP, WORDS = CAP / 32;
     __shared__ i32 s_hkey[4][HC];
     __shared__ i32 s_hpos[4][HC];
@@ -237,19 +339,23 @@ __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__res
     __shared__ i32 s_tcnt[4][CAP];
     __shared__ u32 s_A[4][CAP * WORDS];
     __shared__ i64 s_acc[4][CAP];
+    __shared__ ItemState s_st[4];
     const int w = threadIdx.x / WAVE, tid = lane_id();
     ProbeMem M{s_hkey[w], s_hpos[w], s_off[w], s_nb[w], s_tcnt[w], s_A[w], s_acc[w]};
+    if (tid == 0) s_st[w].chunk_cur = s_st[w].chunk_end = 0;
+    item_sync<WAVE>();
     const i32 cnt = st->cnt[WC_TRI_WAVE];
     const int waves = gridDim.x * 4;
     for (i32 it = blockIdx.x * 4 + w; it < cnt; it += waves)
-        probe_item<WAVE, MODE>(g, list[it], tid, M, HC, WORDS, t, K4, tau, nullptr, nullptr);
+        probe_item<WAVE, MODE>(g, list[it], tid, M, HC, WORDS, t, K4, tau, nullptr, nullptr, tc, &s_st[w]);
 }
 
 // One 256-thread workgroup per vertex, 64 < |N+(u)| <= TRI_BLOCK_CAP.
+#define PB_NT 512
 template <int MODE>
-__global__ void __launch_bounds__(256) k_probe_block(DevGraph g, const i32 *__restrict__ list,
+__global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__restrict__ list,
                                                      const GraphStats *__restrict__ st, i32 *t, i64 *K4,
-                                                     i64 *tau) {
+                                                     i64 *tau, TriCache tc) {
     constexpr int CAP = TRI_BLOCK_CAP, HC = 2 * CAP, WORDS = CAP / 32;
     __shared__ i32 s_hkey[HC];
     __shared__ i32 s_hpos[HC];
@@ -258,20 +364,23 @@ __global__ void __launch_bounds__(256) k_probe_block(DevGraph g, const i32 *__re
     __shared__ i32 s_tcnt[CAP];
     __shared__ u32 s_A[CAP * WORDS];
     __shared__ i64 s_acc[CAP];
-    __shared__ i64 s_red[4];
-    __shared__ i32 s_red32[4];
+    __shared__ i64 s_red[PB_NT / WAVE];
+    __shared__ i32 s_red32[PB_NT / WAVE];
+    __shared__ ItemState s_st;
     ProbeMem M{s_hkey, s_hpos, s_off, s_nb, s_tcnt, s_A, s_acc};
+    if (threadIdx.x == 0) s_st.chunk_cur = s_st.chunk_end = 0;
+    __syncthreads();
     const i32 cnt = st->cnt[WC_TRI_BLOCK];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
-        probe_item<256, MODE>(g, list[it], threadIdx.x, M, HC, WORDS, t, K4, tau, s_red, s_red32);
+        probe_item<PB_NT, MODE>(g, list[it], threadIdx.x, M, HC, WORDS, t, K4, tau, s_red, s_red32, tc, &s_st);
 }
 
 // |N+(u)| > TRI_BLOCK_CAP: the same item code on per-workgroup global scratch.
 template <int MODE>
 __global__ void __launch_bounds__(256) k_probe_large(DevGraph g, const i32 *__restrict__ list,
                                                      const GraphStats *__restrict__ st, i32 *t, i64 *K4,
-                                                     i64 *tau, char *scratch, i64 slice_bytes, int cap,
-                                                     int hc) {
+                                                     i64 *tau, TriCache tc, char *scratch, i64 slice_bytes,
+                                                     int cap, int hc) {
     __shared__ i64 s_red[4];
     __shared__ i32 s_red32[4];
     const int words = (cap + 31) / 32;
@@ -284,9 +393,12 @@ __global__ void __launch_bounds__(256) k_probe_large(DevGraph g, const i32 *__re
     M.nb = (i32 *)p; p += sizeof(i32) * cap;
     M.tcnt = (i32 *)p; p += sizeof(i32) * cap;
     M.A = (u32 *)p;
+    __shared__ ItemState s_st;
+    if (threadIdx.x == 0) s_st.chunk_cur = s_st.chunk_end = 0;
+    __syncthreads();
     const i32 cnt = st->cnt[WC_TRI_LARGE];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
-        probe_item<256, MODE>(g, list[it], threadIdx.x, M, hc, words, t, K4, tau, s_red, s_red32);
+        probe_item<256, MODE>(g, list[it], threadIdx.x, M, hc, words, t, K4, tau, s_red, s_red32, tc, &s_st);
 }
 
 i64 probe_large_slice_bytes(int cap, int hc) {
@@ -514,7 +626,9 @@ struct GlobalCounter {
     __device__ i32 get(i32 k) const { return c[k]; }
 };
 
-// Both sweeps over the item's wedges, chunk by chunk.
+// Both sweeps over the item's wedges, chunk by chunk.  Each thread takes QU wedges
+// per step (independent loads in flight); the segment of a wedge is found by a
+// binary search over the chunk's prefix offsets in LDS.
 template <int NT, int MODE, typename Ctr>
 __device__ __forceinline__ void q_sweeps(const DevGraph &g, i32 x, const Ctr &ctr, const QChunk &C, int dc,
                                          int tid, i32 *red32, i64 *__restrict__ Q) {
@@ -530,14 +644,28 @@ __device__ __forceinline__ void q_sweeps(const DevGraph &g, i32 x, const Ctr &ct
             } else {
                 total = C.off[len];
             }
-            for (i32 e = tid; e < total; e += NT) {
-                int i = upper_index<i32>(C.off, 0, len, e);
-                i32 k = g.ncol[C.beg[i] + (e - C.off[i])];
-                if (pass == 0) {
-                    ctr.inc(k);
-                } else {
-                    i32 c = ctr.get(k);
-                    if (c > 1) atomicAdd((unsigned long long *)&C.mid[i], (unsigned long long)(c - 1));
+            for (i32 eb = tid; eb < total; eb += NT * QU) {
+                int si[QU];
+                i32 key[QU];
+                bool ok[QU];
+#pragma unroll
+                for (int u = 0; u < QU; u++) {
+                    i32 e = eb + u * NT;
+                    ok[u] = e < total;
+                    si[u] = ok[u] ? upper_index<i32>(C.off, 0, len, e) : 0;
+                    key[u] = ok[u] ? C.beg[si[u]] + (e - C.off[si[u]]) : 0;
+                }
+#pragma unroll
+                for (int u = 0; u < QU; u++) key[u] = ok[u] ? g.ncol[key[u]] : 0;
+#pragma unroll
+                for (int u = 0; u < QU; u++) {
+                    if (!ok[u]) continue;
+                    if (pass == 0) {
+                        ctr.inc(key[u]);
+                    } else {
+                        i32 c = ctr.get(key[u]);
+                        if (c > 1) atomicAdd((unsigned long long *)&C.mid[si[u]], (unsigned long long)(c - 1));
+                    }
                 }
             }
             item_sync<NT>();
@@ -632,11 +760,135 @@ __global__ void __launch_bounds__(256) k_q_block(DevGraph g, const i32 *__restri
         q_item_hash<256, MODE>(g, list[it], H, C, DC, threadIdx.x, s_red, s_red32, Q);
 }
 
+// ---------------------------------------------------------------------------
+// Heavy largest vertices (keys u in [h0, n), at most QH_DENSE_K of them).
+// Credits C(c,2) to a heavy key go to the workgroup's own row of `part`
+// (int64[gridDim.x][K]), summed into Q by k_qh_reduce: every opposite vertex
+// credits the same few thousand hubs, and one shared counter per hub would
+// serialise those updates.
+// ---------------------------------------------------------------------------
+#define PK_SHIFT 17
+#define PK_CMASK 0x1ffffu
+#define PK_EMPTY 0xffffffffu
+
+// Hash of (key index, count) packed in one 32-bit word: idx << 17 | count.
+struct PackedHash {
+    u32 *tab;
+    u32 mask;
+    i32 h0;
+    __device__ void inc(i32 k) const {
+        const u32 idx = (u32)(k - h0);
+        u32 sl = hslot(idx, mask);
+        while (true) {
+            u32 cur = tab[sl];
+            if (cur == PK_EMPTY) {
+                u32 prev = atomicCAS(&tab[sl], PK_EMPTY, (idx << PK_SHIFT) | 1u);
+                if (prev == PK_EMPTY) return;
+                cur = prev;
+            }
+            if ((cur >> PK_SHIFT) == idx) {
+                atomicAdd(&tab[sl], 1u);
+                return;
+            }
+            sl = (sl + 1) & mask;
+        }
+    }
+    __device__ i32 get(i32 k) const {
+        const u32 idx = (u32)(k - h0);
+        u32 sl = hslot(idx, mask);
+        while (true) {
+            u32 cur = tab[sl];
+            if (cur == PK_EMPTY) return 0;
+            if ((cur >> PK_SHIFT) == idx) return (i32)(cur & PK_CMASK);
+            sl = (sl + 1) & mask;
+        }
+    }
+};
+
+template <int NT>
+__device__ __forceinline__ void qh_item_packed(const DevGraph &g, i32 x, const PackedHash &H0, int hc_max,
+                                               const QChunk &C, int dc, int tid, i64 *red, i32 *red32,
+                                               i64 *__restrict__ Q, i64 *__restrict__ prow) {
+    // the table used is the smallest power of two holding twice the item's wedges
+    int hc = 64;
+    while (hc < hc_max && (i64)hc < 2 * g.wheavy[x]) hc <<= 1;
+    PackedHash H{H0.tab, (u32)hc - 1, H0.h0};
+    q_sweeps<NT, Q_HEAVY>(g, x, H, C, dc, tid, red32, Q);
+    i64 local = 0;
+    for (int j = tid; j < hc; j += NT) {
+        u32 cur = H.tab[j];
+        if (cur != PK_EMPTY) {
+            i64 c = cur & PK_CMASK;
+            if (c >= 2) {
+                i64 cc = c * (c - 1) / 2;
+                atomicAdd((unsigned long long *)&prow[cur >> PK_SHIFT], (unsigned long long)cc);
+                local += cc;
+            }
+            H.tab[j] = PK_EMPTY;
+        }
+    }
+    i64 s = item_sum<NT>(local, red, tid);
+    if (tid == 0 && s) atomic_add_i64(&Q[x], s);
+    item_sync<NT>();
+}
+
+#define QHW_HC 1024
+#define QHW_DC 64
+__global__ void __launch_bounds__(256) k_qh_wave(DevGraph g, const i32 *__restrict__ list,
+                                                 const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 K) {
+    __shared__ u32 s_tab[4][QHW_HC];
+    __shared__ i32 s_off[4][QHW_DC + 1];
+    __shared__ i32 s_vv[4][QHW_DC];
+    __shared__ i32 s_beg[4][QHW_DC];
+    __shared__ i64 s_mid[4][QHW_DC];
+    const int w = threadIdx.x / WAVE, tid = lane_id();
+    for (int i = tid; i < QHW_HC; i += WAVE) s_tab[w][i] = PK_EMPTY;
+    item_sync<WAVE>();
+    PackedHash H{s_tab[w], QHW_HC - 1, g.h0};
+    QChunk C{s_off[w], s_vv[w], s_beg[w], s_mid[w]};
+    i64 *prow = part + (i64)blockIdx.x * K;
+    const i32 cnt = st->cnt[WC_QH_WAVE];
+    const int waves = gridDim.x * 4;
+    for (i32 it = blockIdx.x * 4 + w; it < cnt; it += waves)
+        qh_item_packed<WAVE>(g, list[it], H, QHW_HC, C, QHW_DC, tid, nullptr, nullptr, Q, prow);
+}
+
+#define QHB_HC 8192
+#define QHB_DC 256
+#define QHB_NT 512
+__global__ void __launch_bounds__(QHB_NT) k_qh_block(DevGraph g, const i32 *__restrict__ list,
+                                                     const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 K) {
+    __shared__ u32 s_tab[QHB_HC];
+    __shared__ i32 s_off[QHB_DC + 1];
+    __shared__ i32 s_vv[QHB_DC];
+    __shared__ i32 s_beg[QHB_DC];
+    __shared__ i64 s_mid[QHB_DC];
+    __shared__ i64 s_red[QHB_NT / WAVE];
+    __shared__ i32 s_red32[QHB_NT / WAVE];
+    for (int i = threadIdx.x; i < QHB_HC; i += QHB_NT) s_tab[i] = PK_EMPTY;
+    __syncthreads();
+    PackedHash H{s_tab, QHB_HC - 1, g.h0};
+    QChunk C{s_off, s_vv, s_beg, s_mid};
+    i64 *prow = part + (i64)blockIdx.x * K;
+    const i32 cnt = st->cnt[WC_QH_BLOCK];
+    for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
+        qh_item_packed<QHB_NT>(g, list[it], H, QHB_HC, C, QHB_DC, threadIdx.x, s_red, s_red32, Q, prow);
+}
+
+// part rows -> Q over the heavy range
+__global__ void k_qh_reduce(const i64 *__restrict__ part, int rows, i32 K, i32 h0, i64 *__restrict__ Q) {
+    i32 i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= K) return;
+    i64 s = 0;
+    for (int r = 0; r < rows; r++) s += part[(i64)r * K + i];
+    if (s) Q[h0 + i] += s;
+}
+
 // Heavy largest vertices: dense 16-bit counters over [h0, n).
-#define QD_NT 512
-#define QD_DC 1024
+#define QD_NT 1024
+#define QD_DC 256
 __global__ void __launch_bounds__(QD_NT) k_q_dense(DevGraph g, const i32 *__restrict__ list,
-                                                   const GraphStats *__restrict__ st, i64 *Q) {
+                                                   const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 Kp) {
     __shared__ u32 s_w[QH_DENSE_K / 2];
     __shared__ i32 s_off[QD_DC + 1];
     __shared__ i32 s_vv[QD_DC];
@@ -650,6 +902,7 @@ __global__ void __launch_bounds__(QD_NT) k_q_dense(DevGraph g, const i32 *__rest
     __syncthreads();
     DenseCounter ctr{s_w, g.h0};
     QChunk C{s_off, s_vv, s_beg, s_mid};
+    i64 *prow = part + (i64)blockIdx.x * Kp;
     const i32 cnt = st->cnt[WC_QH_DENSE];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x) {
         i32 x = list[it];
@@ -659,14 +912,15 @@ __global__ void __launch_bounds__(QD_NT) k_q_dense(DevGraph g, const i32 *__rest
             u32 word = s_w[i];
             if (word) {
                 i64 c0 = word & 0xffffu, c1 = word >> 16;
+                // key indices 2i and 2i+1 belong to this thread alone
                 if (c0 >= 2) {
                     i64 cc = c0 * (c0 - 1) / 2;
-                    atomic_add_i64(&Q[g.h0 + 2 * i], cc);
+                    prow[2 * i] += cc;
                     local += cc;
                 }
                 if (c1 >= 2) {
                     i64 cc = c1 * (c1 - 1) / 2;
-                    atomic_add_i64(&Q[g.h0 + 2 * i + 1], cc);
+                    prow[2 * i + 1] += cc;
                     local += cc;
                 }
                 s_w[i] = 0u;
@@ -737,25 +991,28 @@ hipError_t launch_classify(const DevGraph &g, const i64 *wl, const i64 *wh, cons
 }
 
 hipError_t launch_probe(int mode, const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i32 *t,
-                        i64 *K4, i64 *tau, char *large_scratch, i64 large_slice, int large_cap, int large_hc,
-                        int large_blocks, int grid_wave, int grid_block, hipStream_t s) {
+                        i64 *K4, i64 *tau, const TriCacheArgs &tca, char *large_scratch, i64 large_slice,
+                        int large_cap, int large_hc, int large_blocks, int grid_wave, int grid_block,
+                        hipStream_t s) {
+    TriCache tw{tca.rec, tca.cap, tca.bump, tca.off, tca.cnt, tca.chunk_wave};
+    TriCache tb{tca.rec, tca.cap, tca.bump, tca.off, tca.cnt, tca.chunk_block};
     if (mode == PROBE_TRI) {
         hipLaunchKernelGGL(k_probe_wave<PROBE_TRI>, dim3(grid_wave), dim3(256), 0, s, g, lists_host[WC_TRI_WAVE], st,
-                           t, K4, tau);
-        hipLaunchKernelGGL(k_probe_block<PROBE_TRI>, dim3(grid_block), dim3(256), 0, s, g,
-                           lists_host[WC_TRI_BLOCK], st, t, K4, tau);
+                           t, K4, tau, tw);
+        hipLaunchKernelGGL(k_probe_block<PROBE_TRI>, dim3(grid_block), dim3(PB_NT), 0, s, g,
+                           lists_host[WC_TRI_BLOCK], st, t, K4, tau, tb);
         if (large_blocks > 0)
             hipLaunchKernelGGL(k_probe_large<PROBE_TRI>, dim3(large_blocks), dim3(256), 0, s, g,
-                               lists_host[WC_TRI_LARGE], st, t, K4, tau, large_scratch, large_slice, large_cap,
+                               lists_host[WC_TRI_LARGE], st, t, K4, tau, tb, large_scratch, large_slice, large_cap,
                                large_hc);
     } else {
         hipLaunchKernelGGL(k_probe_wave<PROBE_TAU>, dim3(grid_wave), dim3(256), 0, s, g, lists_host[WC_TRI_WAVE], st,
-                           t, K4, tau);
-        hipLaunchKernelGGL(k_probe_block<PROBE_TAU>, dim3(grid_block), dim3(256), 0, s, g,
-                           lists_host[WC_TRI_BLOCK], st, t, K4, tau);
+                           t, K4, tau, tw);
+        hipLaunchKernelGGL(k_probe_block<PROBE_TAU>, dim3(grid_block), dim3(PB_NT), 0, s, g,
+                           lists_host[WC_TRI_BLOCK], st, t, K4, tau, tb);
         if (large_blocks > 0)
             hipLaunchKernelGGL(k_probe_large<PROBE_TAU>, dim3(large_blocks), dim3(256), 0, s, g,
-                               lists_host[WC_TRI_LARGE], st, t, K4, tau, large_scratch, large_slice, large_cap,
+                               lists_host[WC_TRI_LARGE], st, t, K4, tau, tb, large_scratch, large_slice, large_cap,
                                large_hc);
     }
     return hipGetLastError();
@@ -775,7 +1032,8 @@ hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvar
 }
 
 hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i64 *Q, i32 *gscratch,
-                    i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, hipStream_t s) {
+                    i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, i64 *part, int part_rows,
+                    hipStream_t s) {
     hipLaunchKernelGGL(k_q_wave<Q_LIGHT>, dim3(grid_wave), dim3(256), 0, s, g, lists_host[WC_QL_WAVE], st,
                        (int)WC_QL_WAVE, Q);
     hipLaunchKernelGGL(k_q_block<Q_LIGHT>, dim3(grid_block), dim3(256), 0, s, g, lists_host[WC_QL_BLOCK], st,
@@ -783,11 +1041,19 @@ hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats 
     if (gblocks > 0)
         hipLaunchKernelGGL(k_q_global<Q_LIGHT>, dim3(gblocks), dim3(QG_NT), 0, s, g, lists_host[WC_QL_GLOBAL], st,
                            (int)WC_QL_GLOBAL, Q, gscratch, gslice);
-    hipLaunchKernelGGL(k_q_wave<Q_HEAVY>, dim3(grid_wave), dim3(256), 0, s, g, lists_host[WC_QH_WAVE], st,
-                       (int)WC_QH_WAVE, Q);
-    hipLaunchKernelGGL(k_q_block<Q_HEAVY>, dim3(grid_block), dim3(256), 0, s, g, lists_host[WC_QH_BLOCK], st,
-                       (int)WC_QH_BLOCK, Q);
-    hipLaunchKernelGGL(k_q_dense, dim3(grid_dense), dim3(QD_NT), 0, s, g, lists_host[WC_QH_DENSE], st, Q);
+    const i32 K = g.n - g.h0;
+    if (K > 0) {
+        // rows of `part` are per workgroup: each kernel's grid stays within part_rows
+        int gw = grid_wave < part_rows ? grid_wave : part_rows;
+        int gb = grid_block < part_rows ? grid_block : part_rows;
+        int gd = grid_dense < part_rows ? grid_dense : part_rows;
+        hipError_t e = hipMemsetAsync(part, 0, sizeof(i64) * (size_t)K * part_rows, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_qh_wave, dim3(gw), dim3(256), 0, s, g, lists_host[WC_QH_WAVE], st, Q, part, K);
+        hipLaunchKernelGGL(k_qh_block, dim3(gb), dim3(QHB_NT), 0, s, g, lists_host[WC_QH_BLOCK], st, Q, part, K);
+        hipLaunchKernelGGL(k_q_dense, dim3(gd), dim3(QD_NT), 0, s, g, lists_host[WC_QH_DENSE], st, Q, part, K);
+        hipLaunchKernelGGL(k_qh_reduce, dim3((K + 255) / 256), dim3(256), 0, s, part, part_rows, K, g.h0, Q);
+    }
     if (gblocks > 0)
         hipLaunchKernelGGL(k_q_global<Q_HEAVY>, dim3(gblocks), dim3(QG_NT), 0, s, g, lists_host[WC_QH_GLOBAL], st,
                            (int)WC_QH_GLOBAL, Q, gscratch, gslice);

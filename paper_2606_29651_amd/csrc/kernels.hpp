@@ -55,10 +55,9 @@ struct Thresholds {
 #define QL_WAVE_DC 64       // segment (row slot) capacity per wave item
 #define QL_BLOCK_HC 8192
 #define QL_BLOCK_DC 1024
-#define QH_WAVE_HC 512
-#define QH_WAVE_DC 64
-#define QH_BLOCK_HC 8192
-#define QH_BLOCK_DC 1024
+#define QH_WAVE_HC 1024     // packed (key, count) entries per wave
+#define QH_BLOCK_HC 8192    // packed entries per workgroup
+#define QH_PART_ROWS 1024   // per-workgroup rows of heavy-key credits
 #define QH_DENSE_K 32768    // size of the heavy key range (top-ranked vertices)
 #define QH_DENSE_DC 4096    // middles accumulated in LDS by the dense kernel (else global)
 
@@ -83,6 +82,8 @@ struct DevGraph {
     const i32 *hstart;      // int32[n]: first slot of N+(y) with id >= h0
     const u32 *ndeg;        // uint32[n]: degree by new id
     const u32 *order;       // uint32[n]: new id -> input id
+    const i64 *wlight;      // int64[n]: 4-cycle wedges with y as largest (light) vertex
+    const i64 *wheavy;      // int64[n]: 4-cycle wedges with y opposite a heavy largest vertex
 };
 
 // prep.hip
@@ -107,12 +108,22 @@ __global__ void k_mirror(i32 n, const i32 *nrp, const i32 *nsplit, const i32 *nc
 // count.hip
 hipError_t launch_classify(const DevGraph &g, const i64 *wl, const i64 *wh, const ListPtrs &lists, GraphStats *st,
                            const Thresholds &th, hipStream_t s);
+struct TriCacheArgs {
+    u64 *rec;
+    i64 cap;
+    u64 *bump;
+    i64 *off;
+    i32 *cnt;
+    i64 chunk_wave, chunk_block;
+};
 hipError_t launch_probe(int mode, const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i32 *t,
-                        i64 *K4, i64 *tau, char *large_scratch, i64 large_slice, int large_cap, int large_hc,
-                        int large_blocks, int grid_wave, int grid_block, hipStream_t s);
+                        i64 *K4, i64 *tau, const TriCacheArgs &tca, char *large_scratch, i64 large_slice,
+                        int large_cap, int large_hc, int large_blocks, int grid_wave, int grid_block,
+                        hipStream_t s);
 hipError_t launch_sums(const DevGraph &g, const i32 *t, const Accum &acc, int grid, hipStream_t s);
 hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvars, GraphStats *st, int grid,
                         hipStream_t s);
 hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i64 *Q, i32 *gscratch,
-                    i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, hipStream_t s);
+                    i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, i64 *part, int part_rows,
+                    hipStream_t s);
 i64 probe_large_slice_bytes(int cap, int hc);
