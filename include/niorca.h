@@ -103,13 +103,19 @@ niorca_status niorca_count(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_
                            const int32_t *col, int64_t *out, void *stream, uint32_t flags);
 
 /* Many small graphs in one call.  Graph g owns vertices vtx_off[g]..vtx_off[g+1]-1
- * of a packed CSR whose row_ptr is global (int64[total_n+1]) and whose column ids
- * are LOCAL to the graph (0..n_g-1).  out is int64[total_n*15].  vtx_off is a
- * HOST int64[num_graphs+1] array (the packing is known to the host).  All graphs
- * are counted by one persistent launch per stage; with NIORCA_GRAPH_CAPTURE the
- * launch sequence is captured once per shape into a hipGraph and replayed. */
+ * of a packed CSR whose row_ptr is global (device int64[total_n+1], nnz = row_ptr[total_n])
+ * and whose column ids are LOCAL to the graph (0..n_g-1); out is device
+ * int64[total_n*15] in packed vertex order.  vtx_off is a HOST int64[num_graphs+1]
+ * array with vtx_off[0] = 0; each graph has at most 16385 vertices.
+ * The batch is counted as one disjoint union, one launch sequence for all graphs,
+ * with launch sizes taken from host-known bounds, so nothing waits on the device.
+ * With NIORCA_GRAPH_CAPTURE (non-null stream; not with VALIDATE or TIMING) that
+ * sequence is captured once into a hipGraph and replayed by later calls of the same
+ * shape (sizes, buffers, vtx_off and tuning parameters).  Bad ids inside the packed
+ * CSR give wrong counts, never an out-of-bounds access; NIORCA_VALIDATE checks them
+ * (and waits). */
 #define NIORCA_GRAPH_CAPTURE 0x100u
-niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graphs, const int64_t *vtx_off,
+niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graphs, const int64_t *vtx_off, int64_t nnz,
                                    const int64_t *row_ptr, const int32_t *col, int64_t *out,
                                    void *stream, uint32_t flags);
 

@@ -65,7 +65,7 @@ def load_library():
         lib.niorca_workspace_bytes.restype = u64
         lib.niorca_set_param.argtypes = [P, ctypes.c_char_p, i64]
         lib.niorca_count.argtypes = [P, i32, i64, P, P, P, P, u32]
-        lib.niorca_count_batched.argtypes = [P, i32, P, P, P, P, P, u32]
+        lib.niorca_count_batched.argtypes = [P, i32, P, i64, P, P, P, P, u32]
         lib.niorca_edge_triangles.argtypes = [P, i32, i64, P, P, P, P]
         lib.niorca_k4.argtypes = [P, i32, i64, P, P, P, P]
         lib.niorca_fvars.argtypes = [P, i32, i64, P, P, P, P]
@@ -193,4 +193,22 @@ def fvars(row_ptr, col, ctx: Context = None, stream=None) -> torch.Tensor:
     out = torch.empty((n, 9), dtype=torch.int64, device=row_ptr.device)
     ctx.check(ctx.lib.niorca_fvars(ctx.h, n, nnz, _p(row_ptr), _p(col), _p(out), _stream_ptr(stream)),
               "niorca_fvars")
+    return out
+
+
+def count_batched(vtx_off, row_ptr: torch.Tensor, col: torch.Tensor, flags: int = 0, out: torch.Tensor = None,
+                  ctx: Context = None, stream=None) -> torch.Tensor:
+    """psi (int64[total_n, 15]) of many packed graphs: vtx_off is a host int64 array
+    (numpy or list), row_ptr global, col ids local to each graph."""
+    import numpy as np
+    voff = np.ascontiguousarray(np.asarray(vtx_off, dtype=np.int64))
+    row_ptr, col, n, nnz = _graph(row_ptr, col)
+    if voff.ndim != 1 or voff.shape[0] < 1 or int(voff[-1]) != n:
+        raise ValueError("vtx_off must end at the number of rows")
+    ctx = ctx or context(row_ptr.device.index)
+    if out is None:
+        out = torch.empty((n, 15), dtype=torch.int64, device=row_ptr.device)
+    rc = ctx.lib.niorca_count_batched(ctx.h, voff.shape[0] - 1, voff.ctypes.data_as(ctypes.c_void_p), nnz,
+                                      _p(row_ptr), _p(col), _p(out), _stream_ptr(stream), flags)
+    ctx.check(rc, "niorca_count_batched")
     return out

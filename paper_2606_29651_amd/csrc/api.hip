@@ -32,6 +32,12 @@ struct niorca_ctx {
     // tunable class thresholds and the size of the heavy 4-cycle key range
     Thresholds th{TRI_WAVE_CAP, TRI_BLOCK_CAP, QL_WAVE_HC / 2, QL_BLOCK_HC / 2, QH_WAVE_HC / 2, QH_BLOCK_HC / 2};
     int32_t heavy_k = QH_DENSE_K;
+    // the last captured batched sequence and the shape it was captured for
+    hipGraphExec_t gexec = nullptr;
+    uint64_t gkey = 0;
+    // the region of global 4-cycle counters last cleared (kernels leave it zero)
+    char *gz_ws = nullptr;
+    uint64_t gz_off = 0, gz_bytes = 0;
     int64_t tri_cache_records = (int64_t)1 << 29;  // 4 GiB of kept triangles for the tau pass
 };
 
@@ -103,6 +109,7 @@ extern "C" void niorca_destroy(niorca_ctx *ctx) {
     if (!ctx) return;
     if (ctx->ev_made)
         for (auto &e : ctx->ev) (void)hipEventDestroy(e);
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->ws) {
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
@@ -229,6 +236,13 @@ struct Outputs {
     int64_t *k4 = nullptr;     // [n] input order
 };
 
+// Bounds the host already knows (batched calls): with them the pipeline needs no
+// wait on the device, so the whole sequence can be captured into a hipGraph.
+struct HostBounds {
+    int dmax;       // maximum degree
+    int dplus_max;  // maximum |N+|
+};
+
 static niorca_status check_graph_args(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *rp, const int32_t *col) {
     if (!ctx) return NIORCA_EINVAL;
     ctx->err.clear();
@@ -242,8 +256,75 @@ static niorca_status check_graph_args(niorca_ctx *ctx, int32_t n, int64_t nnz, c
     return NIORCA_OK;
 }
 
+// Workspace layout of one count.
+struct Layout {
+    uint64_t st, deg, val, k2, v2, hist, scan, perm, nrp, nsplit, hstart, lng, ncol, mirror, t, wl, wh;
+    uint64_t lists[WC_COUNT];
+    uint64_t acc, tcoff, tccnt, tcbump, tcrec;
+    uint64_t base_end;  // everything above needs no graph statistics
+    uint64_t large, part, gcnt, colg, voff;
+    uint64_t total;
+    i64 tc_cap;
+    int large_cap, large_hc, large_blocks, part_rows, gblocks;
+    i64 large_slice, gslice;
+    i32 h0;
+};
+
+static void layout_base(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz, Arena &A) {
+    const i64 radix_tiles_elems = radix_ws_elems(n);
+    const i64 scan_elems = scan_ws_elems(radix_tiles_elems > n + 1 ? radix_tiles_elems : n + 1) + 8;
+    L.st = A.take<GraphStats>(1);
+    L.deg = A.take<u32>(n); L.val = A.take<u32>(n); L.k2 = A.take<u32>(n); L.v2 = A.take<u32>(n);
+    L.hist = A.take<i32>(radix_tiles_elems); L.scan = A.take<i32>(scan_elems);
+    L.perm = A.take<i32>(n); L.nrp = A.take<i32>(n + 1); L.nsplit = A.take<i32>(n);
+    L.hstart = A.take<i32>(n); L.lng = A.take<i32>(n + 1);
+    // slot arrays carry a pad so that a one-past-the-row read never leaves the buffer
+    L.ncol = A.take<i32>(nnz + 64); L.mirror = A.take<i32>(nnz + 64); L.t = A.take<i32>(nnz + 64);
+    L.wl = A.take<i64>(n); L.wh = A.take<i64>(n);
+    for (int c = 0; c < WC_COUNT; c++) L.lists[c] = A.take<i32>(n);
+    L.acc = A.take<i64>((uint64_t)n * 10);
+    L.tcoff = A.take<i64>(n); L.tccnt = A.take<i32>(n); L.tcbump = A.take<u64>(1);
+    L.tc_cap = ctx->tri_cache_records;
+    L.tcrec = A.take<u64>((uint64_t)(L.tc_cap > 0 ? L.tc_cap : 1));
+    L.base_end = A.off;
+}
+
+static void layout_rest(Layout &L, const niorca_ctx *ctx, int32_t n, int dplus_max, bool bounded, Arena &A) {
+    const int cu = ctx->num_cu;
+    L.h0 = n > ctx->heavy_k ? n - ctx->heavy_k : 0;
+    // vertices with |N+| above the workgroup threshold go to the global-scratch class
+    L.large_cap = dplus_max > ctx->th.tri_block ? dplus_max : 0;
+    L.large_hc = 1;
+    while (L.large_hc < 2 * L.large_cap) L.large_hc <<= 1;
+    L.large_blocks = L.large_cap ? 2 * cu : 0;
+    L.large_slice = L.large_cap ? probe_large_slice_bytes(L.large_cap, L.large_hc) : 0;
+    L.large = A.take<char>((uint64_t)L.large_slice * L.large_blocks);
+    L.part_rows = QH_PART_ROWS;
+    L.part = A.take<i64>((uint64_t)L.part_rows * (uint64_t)(n - L.h0));
+    // int32 counters over all vertices for the rare 4-cycle items that overflow LDS;
+    // fewer workgroups on very large graphs keep this region small
+    L.gblocks = bounded ? 2 : (n <= (1 << 22) ? 32 : 8);
+    L.gslice = 2 * (i64)n + 64;
+    L.gcnt = A.take<i32>((uint64_t)L.gslice * L.gblocks);
+    L.total = A.off;
+}
+
+// Fill kernels (no memset nodes: the sequence may be captured into a hipGraph).
+__global__ void k_fill32(u32 *__restrict__ p, i64 words, u32 v) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (i64)gridDim.x * blockDim.x) p[i] = v;
+}
+
+static hipError_t fill32(void *p, i64 bytes, u32 v, hipStream_t s) {
+    i64 words = bytes / 4;
+    if (words <= 0) return hipSuccess;
+    i64 blocks = (words + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill32, dim3((u32)blocks), dim3(256), 0, s, (u32 *)p, words, v);
+    return hipGetLastError();
+}
+
 static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *rp, const int32_t *col,
-                         const Outputs &o, hipStream_t s, uint32_t flags) {
+                         const Outputs &o, hipStream_t s, uint32_t flags, const HostBounds *hb) {
     HIP_TRY(hipSetDevice(ctx->device));
     const bool timing = (flags & NIORCA_TIMING) != 0;
     ctx->ev_valid = false;
@@ -255,32 +336,18 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     if (timing) HIP_TRY(hipEventRecord(ctx->ev[i], s))
     const int nthr = 256;
     const int cu = ctx->num_cu;
-    // ---- workspace layout ----
+    Layout L;
     Arena A;
-    const i64 radix_tiles_elems = radix_ws_elems(n);
-    const i64 scan_elems = scan_ws_elems(radix_tiles_elems > n + 1 ? radix_tiles_elems : n + 1) + 8;
-    uint64_t o_st = A.take<GraphStats>(1);
-    uint64_t o_deg = A.take<u32>(n), o_val = A.take<u32>(n), o_k2 = A.take<u32>(n), o_v2 = A.take<u32>(n);
-    uint64_t o_hist = A.take<i32>(radix_tiles_elems), o_scan = A.take<i32>(scan_elems);
-    uint64_t o_perm = A.take<i32>(n), o_nrp = A.take<i32>(n + 1), o_nsplit = A.take<i32>(n);
-    uint64_t o_hstart = A.take<i32>(n), o_long = A.take<i32>(n + 1);
-    // slot arrays carry a pad so that a one-past-the-row read never leaves the buffer
-    uint64_t o_ncol = A.take<i32>(nnz + 64), o_mirror = A.take<i32>(nnz + 64), o_t = A.take<i32>(nnz + 64);
-    uint64_t o_wl = A.take<i64>(n), o_wh = A.take<i64>(n);
-    uint64_t o_lists[WC_COUNT];
-    for (int c = 0; c < WC_COUNT; c++) o_lists[c] = A.take<i32>(n);
-    uint64_t o_acc = A.take<i64>((uint64_t)n * 10);
-    uint64_t o_tcoff = A.take<i64>(n), o_tccnt = A.take<i32>(n), o_tcbump = A.take<u64>(1);
-    const i64 tc_cap = ctx->tri_cache_records;
-    uint64_t o_tcrec = A.take<u64>((uint64_t)(tc_cap > 0 ? tc_cap : 1));
-    uint64_t base_bytes = A.off;
+    layout_base(L, ctx, n, nnz, A);
+    if (hb) layout_rest(L, ctx, n, hb->dplus_max, true, A);
+    const uint64_t need_now = hb ? A.off : L.base_end;
 
     // Validation first (it reads only the input).
     if (flags & NIORCA_VALIDATE) {
-        niorca_status st = ensure_ws(ctx, base_bytes);
+        niorca_status st = ensure_ws(ctx, need_now);
         if (st) return st;
-        int *bad = (int *)(ctx->ws + o_st);
-        HIP_TRY(hipMemsetAsync(bad, 0, sizeof(int), s));
+        int *bad = (int *)(ctx->ws + L.st);
+        HIP_TRY(fill32(bad, sizeof(int), 0u, s));
         if (n > 0) hipLaunchKernelGGL(k_validate, dim3(cu * 8), dim3(nthr), 0, s, n, nnz, rp, col, bad);
         HIP_TRY(hipGetLastError());
         int hbad = 0;
@@ -290,26 +357,26 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     }
     if (n == 0) return NIORCA_OK;
     {
-        niorca_status st = ensure_ws(ctx, base_bytes);
+        niorca_status st = ensure_ws(ctx, need_now);
         if (st) return st;
     }
     char *W = ctx->ws;
-    GraphStats *dst = (GraphStats *)(W + o_st);
-    u32 *deg = (u32 *)(W + o_deg), *val = (u32 *)(W + o_val), *k2 = (u32 *)(W + o_k2), *v2 = (u32 *)(W + o_v2);
-    i32 *hist = (i32 *)(W + o_hist), *scanw = (i32 *)(W + o_scan);
-    i32 *perm = (i32 *)(W + o_perm), *nrp = (i32 *)(W + o_nrp), *nsplit = (i32 *)(W + o_nsplit);
-    i32 *hstart = (i32 *)(W + o_hstart), *longlist = (i32 *)(W + o_long);
-    i32 *ncol = (i32 *)(W + o_ncol), *mirror = (i32 *)(W + o_mirror), *t = (i32 *)(W + o_t);
-    i64 *wl = (i64 *)(W + o_wl), *wh = (i64 *)(W + o_wh);
+    GraphStats *dst = (GraphStats *)(W + L.st);
+    u32 *deg = (u32 *)(W + L.deg), *val = (u32 *)(W + L.val), *k2 = (u32 *)(W + L.k2), *v2 = (u32 *)(W + L.v2);
+    i32 *hist = (i32 *)(W + L.hist), *scanw = (i32 *)(W + L.scan);
+    i32 *perm = (i32 *)(W + L.perm), *nrp = (i32 *)(W + L.nrp), *nsplit = (i32 *)(W + L.nsplit);
+    i32 *hstart = (i32 *)(W + L.hstart), *longlist = (i32 *)(W + L.lng);
+    i32 *ncol = (i32 *)(W + L.ncol), *mirror = (i32 *)(W + L.mirror), *t = (i32 *)(W + L.t);
+    i64 *wl = (i64 *)(W + L.wl), *wh = (i64 *)(W + L.wh);
     ListPtrs lists;
-    for (int c = 0; c < WC_COUNT; c++) lists.l[c] = (i32 *)(W + o_lists[c]);
-    i64 *accb = (i64 *)(W + o_acc);
+    for (int c = 0; c < WC_COUNT; c++) lists.l[c] = (i32 *)(W + L.lists[c]);
+    i64 *accb = (i64 *)(W + L.acc);
     Accum acc{accb, accb + n, accb + 2 * (i64)n, accb + 3 * (i64)n, accb + 4 * (i64)n,
               accb + 5 * (i64)n, accb + 6 * (i64)n, accb + 7 * (i64)n, accb + 8 * (i64)n, accb + 9 * (i64)n};
     i32 *longcount = &dst->pad;
 
     STAGE_MARK(0);
-    HIP_TRY(hipMemsetAsync(dst, 0, sizeof(GraphStats), s));
+    HIP_TRY(fill32(dst, sizeof(GraphStats), 0u, s));
     // ---- a1: degrees and rank order (stable radix sort of degrees) ----
     hipLaunchKernelGGL(k_degree, dim3((n + nthr - 1) / nthr), dim3(nthr), 0, s, n, (i64)nnz, rp, deg, val, dst);
     HIP_TRY(hipGetLastError());
@@ -323,43 +390,41 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
                        dst);
     HIP_TRY(hipGetLastError());
     STAGE_MARK(1);
-    // ---- the one wait: graph statistics ----
-    GraphStats hs;
-    HIP_TRY(hipMemcpyAsync(&hs, dst, sizeof(GraphStats), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (hs.bad_input)
-        return fail(ctx, NIORCA_EINVAL, "row_ptr or col holds values outside the graph (use NIORCA_VALIDATE)");
-    if (hs.dmax > 1200000)
-        return fail(ctx, NIORCA_EOVERFLOW, "maximum degree %d could overflow int64 counts", hs.dmax);
-    if (hs.dplus_max > LSORT_CAP)
-        return fail(ctx, NIORCA_ENOTIMPL, "an oriented out-degree of %d exceeds %d", hs.dplus_max, LSORT_CAP);
-    const i32 heavy_k = ctx->heavy_k;
-    const i32 h0 = n > heavy_k ? n - heavy_k : 0;
-    // ---- scratch for the large classes, sized by the statistics ----
-    // vertices with |N+| above the workgroup threshold go to the global-scratch class
-    const int large_cap = hs.dplus_max > ctx->th.tri_block ? hs.dplus_max : 0;
-    int large_hc = 1;
-    while (large_hc < 2 * large_cap) large_hc <<= 1;
-    const int large_blocks = large_cap ? 2 * cu : 0;
-    const i64 large_slice = large_cap ? probe_large_slice_bytes(large_cap, large_hc) : 0;
-    uint64_t o_large = A.take<char>((uint64_t)large_slice * large_blocks);
-    const int part_rows = QH_PART_ROWS;
-    uint64_t o_part = A.take<i64>((uint64_t)part_rows * (uint64_t)(n - h0));
-    const int gblocks = 32;
-    const i64 gslice = 2 * (i64)n + 64;
-    uint64_t o_g = A.take<i32>((uint64_t)gslice * gblocks);
-    {
+    GraphStats hs{};
+    if (!hb) {
+        // ---- the one wait: graph statistics ----
+        HIP_TRY(hipMemcpyAsync(&hs, dst, sizeof(GraphStats), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (hs.bad_input)
+            return fail(ctx, NIORCA_EINVAL, "row_ptr or col holds values outside the graph (use NIORCA_VALIDATE)");
+        if (hs.dmax > 1200000)
+            return fail(ctx, NIORCA_EOVERFLOW, "maximum degree %d could overflow int64 counts", hs.dmax);
+        if (hs.dplus_max > LSORT_CAP)
+            return fail(ctx, NIORCA_ENOTIMPL, "an oriented out-degree of %d exceeds %d", hs.dplus_max, LSORT_CAP);
+        layout_rest(L, ctx, n, hs.dplus_max, false, A);
         niorca_status st = ensure_ws(ctx, A.off);
         if (st) return st;
         // The workspace grew and moved: start again; this time it is large enough.
-        if (ctx->ws != W) return run(ctx, n, nnz, rp, col, o, s, flags & ~(uint32_t)NIORCA_VALIDATE);
+        if (ctx->ws != W) return run(ctx, n, nnz, rp, col, o, s, flags & ~(uint32_t)NIORCA_VALIDATE, hb);
+    } else {
+        hs.dmax = hb->dmax;
+        hs.dplus_max = hb->dplus_max;
     }
-    char *large_scratch = W + o_large;
-    i32 *gscratch = (i32 *)(W + o_g);
-    i64 *qpart = (i64 *)(W + o_part);
-    HIP_TRY(hipMemsetAsync(gscratch, 0, sizeof(i32) * (size_t)gslice * gblocks, s));
+    const i32 h0 = L.h0;
+    char *large_scratch = W + L.large;
+    i32 *gscratch = (i32 *)(W + L.gcnt);
+    i64 *qpart = (i64 *)(W + L.part);
+    // The global 4-cycle counters are returned to zero by the kernels that use them,
+    // so they are cleared only when their place in the workspace changes -- and on
+    // every bounded (possibly captured) run, whose replays may follow other calls.
+    if (hb || ctx->gz_ws != W || ctx->gz_off != L.gcnt || ctx->gz_bytes != (uint64_t)L.gslice * L.gblocks * 4) {
+        HIP_TRY(fill32(gscratch, (i64)L.gslice * L.gblocks * 4, 0u, s));
+        ctx->gz_ws = W;
+        ctx->gz_off = L.gcnt;
+        ctx->gz_bytes = (uint64_t)L.gslice * L.gblocks * 4;
+    }
     // ---- oriented layout: sorted N+, mirror slots, per-vertex 4-cycle work ----
-    HIP_TRY(hipMemsetAsync(longcount, 0, sizeof(i32), s));
+    HIP_TRY(fill32(longcount, sizeof(i32), 0u, s));
     STAGE_MARK(2);
     hipLaunchKernelGGL(k_sort_upper_small, dim3(cu * 8), dim3(nthr), 0, s, n, nrp, nsplit, ncol, hstart, h0,
                        longlist, longcount);
@@ -373,14 +438,14 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     i32 *lh[WC_COUNT];
     for (int c = 0; c < WC_COUNT; c++) lh[c] = lists.l[c];
     // ---- Stage I (t) and Stage II (K4) ----
-    HIP_TRY(hipMemsetAsync(t, 0, sizeof(i32) * (size_t)nnz, s));
-    HIP_TRY(hipMemsetAsync(accb, 0, sizeof(i64) * 10 * (size_t)n, s));
-    TriCacheArgs tca{tc_cap > 0 ? (u64 *)(W + o_tcrec) : nullptr, tc_cap, (u64 *)(W + o_tcbump),
-                     (i64 *)(W + o_tcoff), (i32 *)(W + o_tccnt), 1 << 14, 1 << 18};
-    HIP_TRY(hipMemsetAsync(tca.bump, 0, sizeof(u64), s));
+    HIP_TRY(fill32(t, sizeof(i32) * nnz, 0u, s));
+    HIP_TRY(fill32(accb, sizeof(i64) * 10 * (i64)n, 0u, s));
+    TriCacheArgs tca{L.tc_cap > 0 ? (u64 *)(W + L.tcrec) : nullptr, L.tc_cap, (u64 *)(W + L.tcbump),
+                     (i64 *)(W + L.tcoff), (i32 *)(W + L.tccnt), 1 << 14, 1 << 18};
+    HIP_TRY(fill32(tca.bump, sizeof(u64), 0u, s));
     STAGE_MARK(4);
-    HIP_TRY(launch_probe(0, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, large_slice, large_cap, large_hc,
-                         large_blocks, cu * 8, cu * 2, s));
+    HIP_TRY(launch_probe(0, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, L.large_slice, L.large_cap,
+                         L.large_hc, L.large_blocks, cu * 8, cu * 2, s));
     STAGE_MARK(5);
     if (o.tri) {
         hipLaunchKernelGGL(k_tri_to_input, dim3(cu * 8), dim3(nthr), 0, s, n, rp, col, perm, g, t, o.tri);
@@ -395,10 +460,12 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     // ---- Stage III-a: neighbour sums, tau, 4-cycles ----
     HIP_TRY(launch_sums(g, t, acc, cu * 8, s));
     STAGE_MARK(6);
-    HIP_TRY(launch_probe(1, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, large_slice, large_cap, large_hc,
-                         large_blocks, cu * 8, cu * 2, s));
+    HIP_TRY(launch_probe(1, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, L.large_slice, L.large_cap,
+                         L.large_hc, L.large_blocks, cu * 8, cu * 2, s));
     STAGE_MARK(7);
-    HIP_TRY(launch_q(g, lh, dst, acc.Q, gscratch, gslice, gblocks, cu * 4, cu * 4, cu * 2, qpart, part_rows, s));
+    if (n - h0 > 0) HIP_TRY(fill32(qpart, (i64)sizeof(i64) * L.part_rows * (n - h0), 0u, s));
+    HIP_TRY(launch_q(g, lh, dst, acc.Q, gscratch, L.gslice, L.gblocks, cu * 4, cu * 4, cu * 2, qpart, L.part_rows,
+                     s));
     STAGE_MARK(8);
     // ---- Stage III-b: equations ----
     HIP_TRY(launch_solve(g, acc, o.psi, o.fvars, dst, cu * 8, s));
@@ -423,7 +490,7 @@ extern "C" niorca_status niorca_count(niorca_ctx *ctx, int32_t n, int64_t nnz, c
     if (flags & ~known) return fail(ctx, NIORCA_EINVAL, "unknown flag bits 0x%x", flags & ~known);
     Outputs o;
     o.psi = out;
-    return run(ctx, n, nnz, row_ptr, col, o, as_stream(stream), flags);
+    return run(ctx, n, nnz, row_ptr, col, o, as_stream(stream), flags, nullptr);
 }
 
 extern "C" niorca_status niorca_edge_triangles(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
@@ -433,7 +500,7 @@ extern "C" niorca_status niorca_edge_triangles(niorca_ctx *ctx, int32_t n, int64
     if (nnz > 0 && !tri) return fail(ctx, NIORCA_EINVAL, "tri is NULL");
     Outputs o;
     o.tri = tri;
-    return run(ctx, n, nnz, row_ptr, col, o, as_stream(stream), 0);
+    return run(ctx, n, nnz, row_ptr, col, o, as_stream(stream), 0, nullptr);
 }
 
 extern "C" niorca_status niorca_k4(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
@@ -443,7 +510,7 @@ extern "C" niorca_status niorca_k4(niorca_ctx *ctx, int32_t n, int64_t nnz, cons
     if (n > 0 && !k4) return fail(ctx, NIORCA_EINVAL, "k4 is NULL");
     Outputs o;
     o.k4 = k4;
-    return run(ctx, n, nnz, row_ptr, col, o, as_stream(stream), 0);
+    return run(ctx, n, nnz, row_ptr, col, o, as_stream(stream), 0, nullptr);
 }
 
 extern "C" niorca_status niorca_fvars(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
@@ -453,14 +520,121 @@ extern "C" niorca_status niorca_fvars(niorca_ctx *ctx, int32_t n, int64_t nnz, c
     if (n > 0 && !fvars) return fail(ctx, NIORCA_EINVAL, "fvars is NULL");
     Outputs o;
     o.fvars = fvars;
-    return run(ctx, n, nnz, row_ptr, col, o, as_stream(stream), 0);
+    return run(ctx, n, nnz, row_ptr, col, o, as_stream(stream), 0, nullptr);
+}
+
+// Packed batch -> one disjoint union: column ids local to graph g become global by
+// adding vtx_off[g] (one wave per row; the graph of a row by binary search).
+__global__ void k_localize(int32_t total_n, int32_t G, const int64_t *__restrict__ voff,
+                           const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                           int32_t *__restrict__ colg) {
+    int waves = gridDim.x * (blockDim.x / WAVE);
+    int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    for (int32_t x = wid; x < total_n; x += waves) {
+        int lo = 0, hi = G;  // largest g with voff[g] <= x
+        while (hi - lo > 1) {
+            int mid = (lo + hi) >> 1;
+            if (voff[mid] <= x) lo = mid; else hi = mid;
+        }
+        const int32_t base = (int32_t)voff[lo];
+        for (int64_t s = rp[x] + lane_id(); s < rp[x + 1]; s += WAVE) colg[s] = col[s] + base;
+    }
+}
+
+static uint64_t mix64(uint64_t h, uint64_t v) {
+    h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+    return h;
 }
 
 extern "C" niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graphs, const int64_t *vtx_off,
-                                              const int64_t *row_ptr, const int32_t *col, int64_t *out,
-                                              void *stream, uint32_t flags) {
-    (void)num_graphs; (void)vtx_off; (void)row_ptr; (void)col; (void)out; (void)stream; (void)flags;
-    return fail(ctx, NIORCA_ENOTIMPL, "batched counting is not built yet");
+                                              int64_t nnz, const int64_t *row_ptr, const int32_t *col,
+                                              int64_t *out, void *stream, uint32_t flags) {
+    if (!ctx) return NIORCA_EINVAL;
+    ctx->err.clear();
+    if (num_graphs < 0) return fail(ctx, NIORCA_EINVAL, "num_graphs is negative");
+    if (num_graphs == 0) return NIORCA_OK;
+    if (!vtx_off) return fail(ctx, NIORCA_EINVAL, "vtx_off is NULL");
+    const uint32_t known = NIORCA_VALIDATE | NIORCA_GRAPH_CAPTURE | NIORCA_TIMING;
+    if (flags & ~known) return fail(ctx, NIORCA_EINVAL, "unknown or unsupported flag bits 0x%x", flags & ~known);
+    const bool capture = (flags & NIORCA_GRAPH_CAPTURE) != 0;
+    if (capture && (flags & (NIORCA_VALIDATE | NIORCA_TIMING)))
+        return fail(ctx, NIORCA_EINVAL, "NIORCA_GRAPH_CAPTURE cannot be combined with VALIDATE or TIMING");
+    if (capture && !stream) return fail(ctx, NIORCA_EINVAL, "NIORCA_GRAPH_CAPTURE needs a non-null stream");
+    if (vtx_off[0] != 0) return fail(ctx, NIORCA_EINVAL, "vtx_off[0] must be 0");
+    int64_t max_n = 0;
+    uint64_t vh = 0;
+    for (int32_t g = 0; g < num_graphs; g++) {
+        int64_t ng = vtx_off[g + 1] - vtx_off[g];
+        if (ng < 0) return fail(ctx, NIORCA_EINVAL, "vtx_off decreases at graph %d", g);
+        if (ng > max_n) max_n = ng;
+        vh = mix64(vh, (uint64_t)vtx_off[g + 1]);
+    }
+    const int64_t total = vtx_off[num_graphs];
+    if (total >= ((int64_t)1 << 31)) return fail(ctx, NIORCA_ENOTIMPL, "more than 2^31 - 1 vertices in the batch");
+    const int32_t n = (int32_t)total;
+    niorca_status st = check_graph_args(ctx, n, nnz, row_ptr, col);
+    if (st) return st;
+    if (n > 0 && !out) return fail(ctx, NIORCA_EINVAL, "out is NULL");
+    if (n == 0) return NIORCA_OK;
+    hipStream_t s = as_stream(stream);
+    HIP_TRY(hipSetDevice(ctx->device));
+    // Bounds known on the host: no vertex has more than max_n - 1 neighbours.
+    HostBounds hb{(int)(max_n - 1), (int)(max_n - 1)};
+    if (hb.dplus_max > LSORT_CAP)
+        return fail(ctx, NIORCA_ENOTIMPL, "a graph of %lld vertices exceeds the batched size limit %d",
+                    (long long)max_n, LSORT_CAP + 1);
+    Layout L;
+    Arena A;
+    layout_base(L, ctx, n, nnz, A);
+    layout_rest(L, ctx, n, hb.dplus_max, true, A);
+    L.colg = A.take<int32_t>(nnz + 64);
+    L.voff = A.take<int64_t>(num_graphs + 1);
+    st = ensure_ws(ctx, A.off);
+    if (st) return st;
+    int32_t *colg = (int32_t *)(ctx->ws + L.colg);
+    int64_t *dvoff = (int64_t *)(ctx->ws + L.voff);
+    HIP_TRY(hipMemcpyAsync(dvoff, vtx_off, sizeof(int64_t) * (num_graphs + 1), hipMemcpyHostToDevice, s));
+    Outputs o;
+    o.psi = out;
+    const int cu = ctx->num_cu;
+    if (!capture) {
+        hipLaunchKernelGGL(k_localize, dim3(cu * 8), dim3(256), 0, s, n, num_graphs, dvoff, row_ptr, col, colg);
+        HIP_TRY(hipGetLastError());
+        return run(ctx, n, nnz, row_ptr, colg, o, s, flags, &hb);
+    }
+    // Replay the captured sequence when the call has the same shape and buffers.
+    uint64_t key = 0;
+    for (uint64_t v : {(uint64_t)n, (uint64_t)nnz, (uint64_t)num_graphs, (uint64_t)(uintptr_t)row_ptr,
+                       (uint64_t)(uintptr_t)col, (uint64_t)(uintptr_t)out, (uint64_t)(uintptr_t)ctx->ws,
+                       ctx->ws_bytes, vh, (uint64_t)ctx->heavy_k, (uint64_t)ctx->tri_cache_records,
+                       (uint64_t)ctx->th.tri_wave, (uint64_t)ctx->th.tri_block, (uint64_t)ctx->th.ql_wave,
+                       (uint64_t)ctx->th.ql_block, (uint64_t)ctx->th.qh_wave, (uint64_t)ctx->th.qh_block})
+        key = mix64(key, v);
+    if (!ctx->gexec || ctx->gkey != key) {
+        if (ctx->gexec) {
+            (void)hipGraphExecDestroy(ctx->gexec);
+            ctx->gexec = nullptr;
+        }
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipLaunchKernelGGL(k_localize, dim3(cu * 8), dim3(256), 0, s, n, num_graphs, dvoff, row_ptr, col, colg);
+        niorca_status rs = run(ctx, n, nnz, row_ptr, colg, o, s, flags & ~(uint32_t)NIORCA_GRAPH_CAPTURE, &hb);
+        hipGraph_t graph = nullptr;
+        hipError_t ce = hipStreamEndCapture(s, &graph);
+        if (rs != NIORCA_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rs;
+        }
+        if (ce != hipSuccess) return fail(ctx, NIORCA_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ce));
+        hipError_t ie = hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ie != hipSuccess) {
+            ctx->gexec = nullptr;
+            return fail(ctx, NIORCA_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ie));
+        }
+        ctx->gkey = key;
+    }
+    HIP_TRY(hipGraphLaunch(ctx->gexec, s));
+    return NIORCA_OK;
 }
 
 extern "C" niorca_status niorca_work_counters(niorca_ctx *ctx, int32_t n, int64_t *counters, void *stream) {

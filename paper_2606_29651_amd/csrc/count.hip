@@ -1047,8 +1047,6 @@ hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats 
         int gw = grid_wave < part_rows ? grid_wave : part_rows;
         int gb = grid_block < part_rows ? grid_block : part_rows;
         int gd = grid_dense < part_rows ? grid_dense : part_rows;
-        hipError_t e = hipMemsetAsync(part, 0, sizeof(i64) * (size_t)K * part_rows, s);
-        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_qh_wave, dim3(gw), dim3(256), 0, s, g, lists_host[WC_QH_WAVE], st, Q, part, K);
         hipLaunchKernelGGL(k_qh_block, dim3(gb), dim3(QHB_NT), 0, s, g, lists_host[WC_QH_BLOCK], st, Q, part, K);
         hipLaunchKernelGGL(k_q_dense, dim3(gd), dim3(QD_NT), 0, s, g, lists_host[WC_QH_DENSE], st, Q, part, K);

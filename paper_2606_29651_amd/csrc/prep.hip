@@ -211,6 +211,14 @@ __global__ void k_radix_scatter(const u32 *__restrict__ kin, const u32 *__restri
 
 i64 radix_ws_elems(i64 n) { return 256 * ((n + RADIX_TILE - 1) / RADIX_TILE) + 1; }
 
+__global__ void k_copy_pairs(const u32 *__restrict__ ks, const u32 *__restrict__ vs, u32 *__restrict__ kd,
+                             u32 *__restrict__ vd, i64 n) {
+    for (i64 i = (i64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (i64)gridDim.x * blockDim.x) {
+        kd[i] = ks[i];
+        vd[i] = vs[i];
+    }
+}
+
 // Sorts (k, v) stably by the low `bits` bits of k.  Result in (k, v); (k2, v2) are temporaries.
 hipError_t radix_sort_pairs(u32 *k, u32 *v, u32 *k2, u32 *v2, i64 n, int bits, i32 *hist, i32 *scan_ws,
                             hipStream_t s) {
@@ -229,9 +237,9 @@ hipError_t radix_sort_pairs(u32 *k, u32 *v, u32 *k2, u32 *v2, i64 n, int bits, i
         ki = ko; vi = vo; ko = tk; vo = tv;
     }
     if (ki != k) {
-        hipError_t e = hipMemcpyAsync(k, ki, sizeof(u32) * n, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess) e = hipMemcpyAsync(v, vi, sizeof(u32) * n, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return e;
+        i64 blocks = (n + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        hipLaunchKernelGGL(k_copy_pairs, dim3((u32)blocks), dim3(256), 0, s, ki, vi, k, v, n);
     }
     return hipGetLastError();
 }

@@ -41,7 +41,8 @@ def test_argument_errors(ni):
     assert _raw(ni, ctx, 0, 0, None, None, None) == ni.OK                      # empty graph
     assert lib.niorca_set_param(ctx.h, b"no_such_knob", 1) == ni.EINVAL
     assert lib.niorca_set_param(ctx.h, b"tri_wave", 65) == ni.EINVAL
-    assert lib.niorca_count_batched(ctx.h, 0, None, None, None, None, None, 0) in (ni.OK, ni.EINVAL, ni.ENOTIMPL)
+    assert lib.niorca_count_batched(ctx.h, 0, None, 0, None, None, None, None, 0) == ni.OK
+    assert lib.niorca_count_batched(ctx.h, 1, None, 0, None, None, None, None, 0) == ni.EINVAL
     assert _raw(ni, ctx, 5, 20, ok(rp), ok(cl), ok(out)) == ni.OK
     torch.cuda.synchronize()
     ctx.close()
