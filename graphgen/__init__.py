@@ -318,19 +318,70 @@ def disjoint_union(graphs) -> CSR:
 
 
 def batch_mix(num_graphs: int, n_lo: int = 20, n_hi: int = 2000, seed: int = 42):
-    """Many small graphs of uneven size: half ER (average degree U(2, 12)), half
-    Barabasi-Albert (k uniform in 2..8), n uniform in [n_lo, n_hi]."""
+    """Many small graphs of uneven size: even positions Erdos-Renyi (average degree
+    uniform in [2, 12]), odd positions Barabasi-Albert (k uniform in 2..8); n uniform
+    in [n_lo, n_hi]."""
     rng = _rng(seed)
-    out = []
+    ns = rng.integers(n_lo, n_hi + 1, size=num_graphs)
+    degs = rng.uniform(2.0, 12.0, size=num_graphs)
+    ks = rng.integers(2, 9, size=num_graphs)
+    subs = rng.integers(0, 2**31 - 1, size=num_graphs)
+    out = [None] * num_graphs
+    ba_idx = []
     for gi in range(num_graphs):
-        n = int(rng.integers(n_lo, n_hi + 1))
-        sub = int(rng.integers(0, 2**31 - 1))
+        n = int(ns[gi])
         if gi % 2 == 0:
-            deg = float(rng.uniform(2.0, 12.0))
-            out.append(er_gnp(n, min(1.0, deg / max(n - 1, 1)), sub))
+            out[gi] = er_gnp(n, min(1.0, float(degs[gi]) / max(n - 1, 1)), int(subs[gi]))
         else:
-            k = int(rng.integers(2, 9))
-            out.append(_ba_fast(n, k, sub))
+            ba_idx.append(gi)
+    if ba_idx:
+        for gi, g in zip(ba_idx, ba_many(ns[ba_idx], ks[ba_idx], seed + 7)):
+            out[gi] = g
+    return out
+
+
+_BA_LIB = None
+
+
+def _ba_lib():
+    """Compile and load graphgen/ba.c (gcc), once."""
+    global _BA_LIB
+    if _BA_LIB is None:
+        import ctypes
+        import os
+        import subprocess
+        here = os.path.dirname(os.path.abspath(__file__))
+        so = os.path.join(here, "libba.so")
+        src = os.path.join(here, "ba.c")
+        if not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(src):
+            tmp = so + f".tmp{os.getpid()}"
+            subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, src], check=True)
+            os.replace(tmp, so)
+        lib = ctypes.CDLL(so)
+        P = ctypes.c_void_p
+        lib.ba_edges.argtypes = [ctypes.c_int64, P, P, ctypes.c_uint64, P, P, P]
+        lib.ba_edges.restype = ctypes.c_int
+        _BA_LIB = lib
+    return _BA_LIB
+
+
+def ba_many(ns, ks, seed: int):
+    """Preferential-attachment graphs (see ba.c), one per (n, k) pair, k <= 16."""
+    import ctypes
+    ns = np.ascontiguousarray(ns, dtype=np.int64)
+    ks = np.ascontiguousarray(np.clip(ks, 1, 16), dtype=np.int64)
+    small = ns <= ks
+    cap = int((ns * ks)[~small].sum() + (ns * ns)[small].sum() + 1)
+    src = np.empty(cap, np.int64)
+    dst = np.empty(cap, np.int64)
+    eoff = np.zeros(len(ns) + 1, np.int64)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _ba_lib().ba_edges(len(ns), ptr(ns), ptr(ks), ctypes.c_uint64(seed & (2**64 - 1)), ptr(src), ptr(dst),
+                       ptr(eoff))
+    out = []
+    for j in range(len(ns)):
+        a, b = eoff[j], eoff[j + 1]
+        out.append(from_edges(int(ns[j]), src[a:b], dst[a:b], f"ba({int(ns[j])},{int(ks[j])})"))
     return out
 
 
@@ -391,6 +442,9 @@ def config_graph(name: str, seed: int = 42) -> CSR:
         return chung_lu(4_000_000, 2.2, 20.0, 50_000.0, seed)
     if name == "rmat22":
         return rmat(22, 16, 0.57, 0.19, 0.19, seed)
+    if name.startswith("batch_"):
+        # batch_<count>: packed mix of small ER and BA graphs (use pack_batch)
+        raise KeyError("batched workloads are lists of graphs: use batch_mix")
     if name.startswith("er_"):
         # er_<n>_<deg>, e.g. er_1m_8
         _, ns, ds = name.split("_")
