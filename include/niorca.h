@@ -52,8 +52,8 @@ typedef enum {
 
 /* Flags (bitmask). */
 #define NIORCA_VALIDATE   0x1u  /* check the CSR precondition on the device; waits on the stream */
-#define NIORCA_BIN_DEGREE 0x2u  /* work classes from degree thresholds */
-#define NIORCA_BIN_MLP    0x4u  /* work classes from the loaded cost model (niorca_set_cost_model) */
+#define NIORCA_BIN_DEGREE 0x2u  /* Stage I work classes from degree thresholds */
+#define NIORCA_BIN_MLP    0x4u  /* Stage I work classes from the loaded work model (niorca_set_cost_model) */
 #define NIORCA_COUNTERS   0x8u  /* record per-vertex work counters (niorca_work_counters) */
 #define NIORCA_TIMING     0x10u /* record HIP events between stages (niorca_stage_times) */
 
@@ -85,6 +85,10 @@ uint64_t niorca_workspace_bytes(const niorca_ctx *ctx);
  *   "qh_wave"   0..256   4-cycle wedges opposite a heavy largest vertex: wave hash
  *   "qh_block"  0..4096  ... workgroup hash; above: dense LDS counters
  *   "heavy_k"   0..32768 how many top-ranked vertices form the heavy range
+ *   "bin_deg_thread" (NIORCA_BIN_DEGREE) degree up to which a vertex with |N+| <= 8
+ *               goes to the one-lane Stage I class (default 16)
+ *   "bin_deg_block"  (NIORCA_BIN_DEGREE) degree from which a vertex goes to the
+ *               workgroup Stage I class (default 4096)
  *   "tri_cache" 0..2^34  triangles kept from Stage I for the tau pass (8 bytes each;
  *                        vertices whose triangles do not fit are probed again)
  * Returns EINVAL for an unknown name or a value out of range. */
@@ -147,25 +151,51 @@ niorca_status niorca_fvars(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_
 niorca_status niorca_stage_times(niorca_ctx *ctx, float *ms, int32_t count);
 
 /* Number of per-vertex work counters written by niorca_work_counters. */
-#define NIORCA_NUM_COUNTERS 6
-/* Per-vertex work measured by the last niorca_count made with NIORCA_COUNTERS:
- * device int64[n*NIORCA_NUM_COUNTERS], in input vertex order:
- *   0 triangle probes (Stage I, x as lowest vertex), 1 triangles found there,
- *   2 clique bitset words scanned, 3 4-cycle wedges with x as the largest vertex,
- *   4 4-cycle wedges with x as the opposite vertex of a heavy largest vertex,
- *   5 neighbour-sum slots read.
- * Fails with EINVAL if the last count did not record counters or n differs. */
+#define NIORCA_NUM_COUNTERS 7
+/* Per-vertex work of the last niorca_count on this context made with
+ * NIORCA_COUNTERS: device int64[n*NIORCA_NUM_COUNTERS], in input vertex order:
+ *   0 Stage I probes made from x (sum of |N+(v)| over v in N+(x))
+ *   1 triangles found with x as lowest vertex
+ *   2 bitset words scanned for the 4-cliques with x as lowest vertex
+ *   3 4-cycle wedges with x as largest vertex (largest vertex below the heavy range)
+ *   4 4-cycle wedges with x opposite a heavy largest vertex
+ *   5 neighbour-sum slots read (2 d(x))
+ *   6 shader-clock cycles of x's Stage I/II item (0 if x had no item)
+ * Must follow that count directly (the next call reuses the workspace).  EINVAL if
+ * the last count recorded no counters or had another n. */
 niorca_status niorca_work_counters(niorca_ctx *ctx, int32_t n, int64_t *counters, void *stream);
 
-/* Cost model for NIORCA_BIN_MLP: an FP32 MLP 6 -> 32 -> 32 -> 1 (ReLU hidden layers)
- * predicting log2(1 + work) of a vertex from its features.  weights is a HOST
- * float array in the order W1[32][6], b1[32], W2[32][32], b2[32], W3[1][32], b3[1]
- * (1313 floats), plus feature normalisation mean[6], inv_std[6] (12 floats):
- * 1325 floats in total.  Thresholds (log2 work) split the thread / wave / block
- * classes.  Copied into the context. */
+/* The six cheap features of every vertex computed by the last niorca_count made with
+ * NIORCA_COUNTERS or NIORCA_BIN_MLP: device float[n*6] in input vertex order,
+ * log2(1 + .) of degree, |N+|, |N-|, neighbour-degree sum, Stage I probes and the
+ * largest |N+(v)| over v in N+(x).  Same lifetime rule as niorca_work_counters. */
+niorca_status niorca_last_features(niorca_ctx *ctx, int32_t n, float *features, void *stream);
+
+/* Work model for NIORCA_BIN_MLP: an FP32 MLP 6 -> 32 -> 32 -> 1 (ReLU hidden layers)
+ * predicting log2(1 + work) of a vertex's Stage I/II item from its six features.
+ * weights is a HOST float array: W1[32][6], b1[32], W2[32][32], b2[32], W3[32], b3,
+ * then the feature normalisation mean[6] and inv_std[6] (1325 floats).  Items that
+ * fit one wave go to the one-lane class when |N+| <= 8 and the prediction is at
+ * most thr_thread, and to the workgroup class when the prediction is at least
+ * thr_block; capacity limits always take precedence, so no count depends on the
+ * model.  Copied into the context (and to the device); waits for the copy. */
 #define NIORCA_MLP_PARAMS 1325
-niorca_status niorca_set_cost_model(niorca_ctx *ctx, const float *weights, int32_t count,
-                                    float thr_wave, float thr_block);
+niorca_status niorca_set_cost_model(niorca_ctx *ctx, const float *weights, int32_t count, float thr_thread,
+                                    float thr_block);
+
+/* Train the work model with the library's FP32 kernels: Adam on the mean squared
+ * error between the prediction and y, minibatches of `batch` rows drawn by a
+ * seeded shuffle each epoch, seeded initialisation; reproducible for a given seed.
+ * X device float[N*6] (features), y device float[N] (targets, e.g. log2(1 + cycles)),
+ * model HOST float[1325] (output, normalisation included), mse HOST double (output,
+ * final mean squared error over all rows; may be NULL).  Waits for completion. */
+niorca_status niorca_mlp_train(niorca_ctx *ctx, const float *X, const float *y, int64_t N, int32_t epochs,
+                               int32_t batch, float lr, uint64_t seed, float *model, double *mse, void *stream);
+
+/* Predictions of a model (HOST float[1325]) for device features X[N*6] into device
+ * pred[N].  Waits for completion. */
+niorca_status niorca_mlp_predict(niorca_ctx *ctx, const float *model, const float *X, int64_t N, float *pred,
+                                 void *stream);
 
 #ifdef __cplusplus
 }

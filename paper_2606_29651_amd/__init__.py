@@ -31,7 +31,11 @@ F_NAMES = ["f12_14", "f10_13", "f13_14", "f11_13", "f5_8", "f6_9", "f9_12", "f4_
 EXPORTS = ["niorca_create", "niorca_destroy", "niorca_last_error", "niorca_set_workspace_limit",
            "niorca_workspace_bytes", "niorca_set_param", "niorca_count", "niorca_count_batched",
            "niorca_edge_triangles", "niorca_k4", "niorca_fvars", "niorca_work_counters",
-           "niorca_set_cost_model", "niorca_stage_times"]
+           "niorca_set_cost_model", "niorca_stage_times", "niorca_last_features", "niorca_mlp_train",
+           "niorca_mlp_predict"]
+NUM_COUNTERS = 7
+MLP_PARAMS = 1325
+COUNTER_NAMES = ["probes", "triangles", "k4_words", "wedges_light", "wedges_heavy", "sum_slots", "stage1_cycles"]
 STAGE_NAMES = ["relabel", "setup", "orient", "zero", "stage1_k4", "sums", "tau", "cycles4", "solve"]
 
 
@@ -72,6 +76,9 @@ def load_library():
         lib.niorca_work_counters.argtypes = [P, i32, P, P]
         lib.niorca_set_cost_model.argtypes = [P, P, i32, ctypes.c_float, ctypes.c_float]
         lib.niorca_stage_times.argtypes = [P, P, i32]
+        lib.niorca_last_features.argtypes = [P, i32, P, P]
+        lib.niorca_mlp_train.argtypes = [P, P, P, i64, i32, i32, ctypes.c_float, u64, P, P, P]
+        lib.niorca_mlp_predict.argtypes = [P, P, P, i64, P, P]
         for name in EXPORTS:
             if name not in ("niorca_destroy", "niorca_last_error", "niorca_workspace_bytes"):
                 getattr(lib, name).restype = ctypes.c_int
@@ -212,3 +219,56 @@ def count_batched(vtx_off, row_ptr: torch.Tensor, col: torch.Tensor, flags: int 
                                       _p(row_ptr), _p(col), _p(out), _stream_ptr(stream), flags)
     ctx.check(rc, "niorca_count_batched")
     return out
+
+
+def work_counters(n: int, ctx: Context = None, device=None, stream=None) -> torch.Tensor:
+    """int64[n, 7] work counters of the last count made with COUNTERS on ctx."""
+    ctx = ctx or context(device)
+    out = torch.empty((n, NUM_COUNTERS), dtype=torch.int64, device=f"cuda:{ctx.device}")
+    ctx.check(ctx.lib.niorca_work_counters(ctx.h, n, _p(out), _stream_ptr(stream)), "niorca_work_counters")
+    return out
+
+
+def last_features(n: int, ctx: Context = None, device=None, stream=None) -> torch.Tensor:
+    """float32[n, 6] features of the last count made with COUNTERS or BIN_MLP on ctx."""
+    ctx = ctx or context(device)
+    out = torch.empty((n, 6), dtype=torch.float32, device=f"cuda:{ctx.device}")
+    ctx.check(ctx.lib.niorca_last_features(ctx.h, n, _p(out), _stream_ptr(stream)), "niorca_last_features")
+    return out
+
+
+def mlp_train(X: torch.Tensor, y: torch.Tensor, epochs: int = 8, batch: int = 4096, lr: float = 3e-3,
+              seed: int = 1, ctx: Context = None, stream=None):
+    """Train the work model on device features X[N, 6] and targets y[N]; returns
+    (model as a numpy float32[1325], final mean squared error)."""
+    import numpy as np
+    X = X.contiguous().float()
+    y = y.contiguous().float()
+    ctx = ctx or context(X.device.index)
+    model = np.zeros(MLP_PARAMS, dtype=np.float32)
+    mse = ctypes.c_double()
+    rc = ctx.lib.niorca_mlp_train(ctx.h, _p(X), _p(y), X.shape[0], epochs, batch, lr, seed,
+                                  model.ctypes.data_as(ctypes.c_void_p), ctypes.byref(mse), _stream_ptr(stream))
+    ctx.check(rc, "niorca_mlp_train")
+    return model, mse.value
+
+
+def mlp_predict(model, X: torch.Tensor, ctx: Context = None, stream=None) -> torch.Tensor:
+    import numpy as np
+    model = np.ascontiguousarray(model, dtype=np.float32)
+    X = X.contiguous().float()
+    ctx = ctx or context(X.device.index)
+    out = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+    ctx.check(ctx.lib.niorca_mlp_predict(ctx.h, model.ctypes.data_as(ctypes.c_void_p), _p(X), X.shape[0], _p(out),
+                                         _stream_ptr(stream)), "niorca_mlp_predict")
+    return out
+
+
+def set_cost_model(model, thr_thread: float, thr_block: float, ctx: Context = None, device=None):
+    import numpy as np
+    model = np.ascontiguousarray(model, dtype=np.float32)
+    if model.shape != (MLP_PARAMS,):
+        raise ValueError(f"model must hold {MLP_PARAMS} floats")
+    ctx = ctx or context(device)
+    ctx.check(ctx.lib.niorca_set_cost_model(ctx.h, model.ctypes.data_as(ctypes.c_void_p), MLP_PARAMS,
+                                            float(thr_thread), float(thr_block)), "niorca_set_cost_model")

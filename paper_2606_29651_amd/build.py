@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libniorca.so")
-SOURCES = ["api.hip", "prep.hip", "count.hip"]
+SOURCES = ["api.hip", "prep.hip", "count.hip", "mlp.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # no packed fp32 instructions anywhere in this library
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

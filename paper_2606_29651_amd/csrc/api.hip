@@ -18,19 +18,22 @@ struct niorca_ctx {
     uint64_t ws_bytes = 0;
     uint64_t ws_limit = 0;
     std::string err;
-    // cost model for NIORCA_BIN_MLP (host copy)
+    // cost model for NIORCA_BIN_MLP (host copy and device copy)
     std::vector<float> mlp;
+    float *mlp_dev = nullptr;
     float thr_wave = 0.f, thr_block = 0.f;
-    // work counters of the last counted graph
-    int32_t counters_n = -1;
-    bool counters_valid = false;
+    // where the last count left its counters and features (offsets in the workspace)
+    int32_t last_n = -1;
+    uint64_t last_counters = 0, last_feat = 0, last_order = 0;
+    char *last_ws = nullptr;
     GraphStats last{};
     // per-stage HIP events of the last call made with NIORCA_TIMING
     hipEvent_t ev[NIORCA_NUM_STAGES + 1] = {};
     bool ev_made = false;
     bool ev_valid = false;
     // tunable class thresholds and the size of the heavy 4-cycle key range
-    Thresholds th{TRI_WAVE_CAP, TRI_BLOCK_CAP, QL_WAVE_HC / 2, QL_BLOCK_HC / 2, QH_WAVE_HC / 2, QH_BLOCK_HC / 2};
+    Thresholds th{TRI_WAVE_CAP, TRI_BLOCK_CAP, 0, 16, 4096, 0.f, 0.f, nullptr,
+                  QL_WAVE_HC / 2, QL_BLOCK_HC / 2, QH_WAVE_HC / 2, QH_BLOCK_HC / 2};
     int32_t heavy_k = QH_DENSE_K;
     // the last captured batched sequence and the shape it was captured for
     hipGraphExec_t gexec = nullptr;
@@ -110,6 +113,7 @@ extern "C" void niorca_destroy(niorca_ctx *ctx) {
     if (ctx->ev_made)
         for (auto &e : ctx->ev) (void)hipEventDestroy(e);
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    if (ctx->mlp_dev) (void)hipFree(ctx->mlp_dev);
     if (ctx->ws) {
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
@@ -141,6 +145,12 @@ extern "C" niorca_status niorca_set_param(niorca_ctx *ctx, const char *name, int
     } else if (k == "tri_cache") {
         if (value < 0 || value > ((int64_t)1 << 34)) return bad(0, (int64_t)1 << 34);
         ctx->tri_cache_records = value;
+    } else if (k == "bin_deg_thread") {
+        if (value < 0 || value > ((int64_t)1 << 30)) return bad(0, (int64_t)1 << 30);
+        ctx->th.deg_thread = (int)value;
+    } else if (k == "bin_deg_block") {
+        if (value < 1 || value > ((int64_t)1 << 30)) return bad(1, (int64_t)1 << 30);
+        ctx->th.deg_block = (int)value;
     } else if (k == "tri_wave") {
         if (value < 1 || value > TRI_WAVE_CAP) return bad(1, TRI_WAVE_CAP);
         ctx->th.tri_wave = (int)value;
@@ -220,6 +230,28 @@ __global__ void k_tri_to_input(int32_t n, const int64_t *__restrict__ rp, const 
     }
 }
 
+// Counters known before Stage I: probes, 4-cycle wedges, neighbour-sum slots.
+__global__ void k_counters_base(int32_t n, const i32 *__restrict__ nrp, const i64 *__restrict__ probes,
+                                const i64 *__restrict__ wl, const i64 *__restrict__ wh, i64 *__restrict__ c) {
+    int32_t y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= n) return;
+    i64 *r = c + (i64)y * NUM_COUNTERS;
+    r[0] = probes[y];
+    r[3] = wl[y];
+    r[4] = wh[y];
+    r[5] = 2 * (i64)(nrp[y + 1] - nrp[y]);
+}
+
+// Rows of `k` values from new-id order to input order.
+template <typename T>
+__global__ void k_rows_to_input(int32_t n, int k, const u32 *__restrict__ order, const T *__restrict__ src,
+                                T *__restrict__ dst) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * k) return;
+    int64_t y = i / k, c = i % k;
+    dst[(int64_t)order[y] * k + c] = src[i];
+}
+
 __global__ void k_k4_to_input(int32_t n, const u32 *__restrict__ order, const i64 *__restrict__ K4,
                               int64_t *__restrict__ out) {
     int32_t y = blockIdx.x * blockDim.x + threadIdx.x;
@@ -260,7 +292,7 @@ static niorca_status check_graph_args(niorca_ctx *ctx, int32_t n, int64_t nnz, c
 struct Layout {
     uint64_t st, deg, val, k2, v2, hist, scan, perm, nrp, nsplit, hstart, lng, ncol, mirror, t, wl, wh;
     uint64_t lists[WC_COUNT];
-    uint64_t acc, tcoff, tccnt, tcbump, tcrec;
+    uint64_t acc, tcoff, tccnt, tcbump, tcrec, probes, feat, pred, counters;
     uint64_t base_end;  // everything above needs no graph statistics
     uint64_t large, part, gcnt, colg, voff;
     uint64_t total;
@@ -270,7 +302,7 @@ struct Layout {
     i32 h0;
 };
 
-static void layout_base(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz, Arena &A) {
+static void layout_base(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz, uint32_t flags, Arena &A) {
     const i64 radix_tiles_elems = radix_ws_elems(n);
     const i64 scan_elems = scan_ws_elems(radix_tiles_elems > n + 1 ? radix_tiles_elems : n + 1) + 8;
     L.st = A.take<GraphStats>(1);
@@ -286,6 +318,11 @@ static void layout_base(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz
     L.tcoff = A.take<i64>(n); L.tccnt = A.take<i32>(n); L.tcbump = A.take<u64>(1);
     L.tc_cap = ctx->tri_cache_records;
     L.tcrec = A.take<u64>((uint64_t)(L.tc_cap > 0 ? L.tc_cap : 1));
+    L.probes = A.take<i64>(n);
+    const bool feats = (flags & (NIORCA_BIN_MLP | NIORCA_COUNTERS)) != 0;
+    L.feat = feats ? A.take<float>((uint64_t)n * 6) : 0;
+    L.pred = (flags & NIORCA_BIN_MLP) ? A.take<float>(n) : 0;
+    L.counters = (flags & NIORCA_COUNTERS) ? A.take<i64>((uint64_t)n * NUM_COUNTERS) : 0;
     L.base_end = A.off;
 }
 
@@ -338,7 +375,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     const int cu = ctx->num_cu;
     Layout L;
     Arena A;
-    layout_base(L, ctx, n, nnz, A);
+    layout_base(L, ctx, n, nnz, flags, A);
     if (hb) layout_rest(L, ctx, n, hb->dplus_max, true, A);
     const uint64_t need_now = hb ? A.off : L.base_end;
 
@@ -430,10 +467,29 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
                        longlist, longcount);
     hipLaunchKernelGGL(k_sort_upper_large, dim3(cu), dim3(256), 0, s, nrp, nsplit, ncol, hstart, h0, longlist,
                        longcount);
-    hipLaunchKernelGGL(k_mirror, dim3(cu * 8), dim3(nthr), 0, s, n, nrp, nsplit, ncol, hstart, h0, mirror, wl, wh);
+    i64 *probes = (i64 *)(W + L.probes);
+    float *feat = L.feat ? (float *)(W + L.feat) : nullptr;
+    float *pred = L.pred ? (float *)(W + L.pred) : nullptr;
+    i64 *counters = L.counters ? (i64 *)(W + L.counters) : nullptr;
+    hipLaunchKernelGGL(k_mirror, dim3(cu * 8), dim3(nthr), 0, s, n, nrp, nsplit, ncol, hstart, h0, mirror, wl, wh,
+                       probes, feat);
     HIP_TRY(hipGetLastError());
+    Thresholds th = ctx->th;
+    th.bin_mode = (flags & NIORCA_BIN_MLP) ? 2 : ((flags & NIORCA_BIN_DEGREE) ? 1 : 0);
+    if (th.bin_mode == 2) {
+        HIP_TRY(mlp_predict(n, feat, ctx->mlp_dev, pred, s));
+        th.pred = pred;
+        th.thr_thread = ctx->thr_wave;
+        th.thr_block = ctx->thr_block;
+    }
     DevGraph g{n, (i32)nnz, h0, nrp, nsplit, ncol, mirror, hstart, deg, val, wl, wh};
-    HIP_TRY(launch_classify(g, wl, wh, lists, dst, ctx->th, s));
+    HIP_TRY(launch_classify(g, wl, wh, lists, dst, th, s));
+    if (counters) {
+        HIP_TRY(fill32(counters, (i64)sizeof(i64) * NUM_COUNTERS * n, 0u, s));
+        hipLaunchKernelGGL(k_counters_base, dim3((n + nthr - 1) / nthr), dim3(nthr), 0, s, n, nrp, probes, wl, wh,
+                           counters);
+        HIP_TRY(hipGetLastError());
+    }
     STAGE_MARK(3);
     i32 *lh[WC_COUNT];
     for (int c = 0; c < WC_COUNT; c++) lh[c] = lists.l[c];
@@ -445,7 +501,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     HIP_TRY(fill32(tca.bump, sizeof(u64), 0u, s));
     STAGE_MARK(4);
     HIP_TRY(launch_probe(0, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, L.large_slice, L.large_cap,
-                         L.large_hc, L.large_blocks, cu * 8, cu * 2, s));
+                         L.large_hc, L.large_blocks, cu * 8, cu * 2, counters, s));
     STAGE_MARK(5);
     if (o.tri) {
         hipLaunchKernelGGL(k_tri_to_input, dim3(cu * 8), dim3(nthr), 0, s, n, rp, col, perm, g, t, o.tri);
@@ -461,7 +517,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     HIP_TRY(launch_sums(g, t, acc, cu * 8, s));
     STAGE_MARK(6);
     HIP_TRY(launch_probe(1, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, L.large_slice, L.large_cap,
-                         L.large_hc, L.large_blocks, cu * 8, cu * 2, s));
+                         L.large_hc, L.large_blocks, cu * 8, cu * 2, nullptr, s));
     STAGE_MARK(7);
     if (n - h0 > 0) HIP_TRY(fill32(qpart, (i64)sizeof(i64) * L.part_rows * (n - h0), 0u, s));
     HIP_TRY(launch_q(g, lh, dst, acc.Q, gscratch, L.gslice, L.gblocks, cu * 4, cu * 4, cu * 2, qpart, L.part_rows,
@@ -476,6 +532,11 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
         HIP_TRY(hipGetLastError());
     }
     ctx->last = hs;
+    ctx->last_n = n;
+    ctx->last_counters = counters ? L.counters : 0;
+    ctx->last_feat = feat ? L.feat : 0;
+    ctx->last_order = L.val;
+    ctx->last_ws = W;
     return NIORCA_OK;
 }
 
@@ -488,6 +549,10 @@ extern "C" niorca_status niorca_count(niorca_ctx *ctx, int32_t n, int64_t nnz, c
     if (n > 0 && !out) return fail(ctx, NIORCA_EINVAL, "out is NULL");
     const uint32_t known = NIORCA_VALIDATE | NIORCA_BIN_DEGREE | NIORCA_BIN_MLP | NIORCA_COUNTERS | NIORCA_TIMING;
     if (flags & ~known) return fail(ctx, NIORCA_EINVAL, "unknown flag bits 0x%x", flags & ~known);
+    if ((flags & NIORCA_BIN_MLP) && !ctx->mlp_dev)
+        return fail(ctx, NIORCA_EINVAL, "NIORCA_BIN_MLP needs a cost model (niorca_set_cost_model)");
+    if ((flags & NIORCA_BIN_MLP) && (flags & NIORCA_BIN_DEGREE))
+        return fail(ctx, NIORCA_EINVAL, "choose one of NIORCA_BIN_MLP and NIORCA_BIN_DEGREE");
     Outputs o;
     o.psi = out;
     return run(ctx, n, nnz, row_ptr, col, o, as_stream(stream), flags, nullptr);
@@ -585,7 +650,7 @@ extern "C" niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graph
                     (long long)max_n, LSORT_CAP + 1);
     Layout L;
     Arena A;
-    layout_base(L, ctx, n, nnz, A);
+    layout_base(L, ctx, n, nnz, flags, A);
     layout_rest(L, ctx, n, hb.dplus_max, true, A);
     L.colg = A.take<int32_t>(nnz + 64);
     L.voff = A.take<int64_t>(num_graphs + 1);
@@ -638,8 +703,136 @@ extern "C" niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graph
 }
 
 extern "C" niorca_status niorca_work_counters(niorca_ctx *ctx, int32_t n, int64_t *counters, void *stream) {
-    (void)n; (void)counters; (void)stream;
-    return fail(ctx, NIORCA_EINVAL, "no work counters were recorded");
+    if (!ctx) return NIORCA_EINVAL;
+    if (!counters && n > 0) return fail(ctx, NIORCA_EINVAL, "counters is NULL");
+    if (ctx->last_n != n || !ctx->last_counters || ctx->last_ws != ctx->ws)
+        return fail(ctx, NIORCA_EINVAL, "the last count on this context did not record counters for n = %d", n);
+    if (n == 0) return NIORCA_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    int64_t tot = (int64_t)n * NUM_COUNTERS;
+    hipLaunchKernelGGL(k_rows_to_input<i64>, dim3((u32)((tot + 255) / 256)), dim3(256), 0, as_stream(stream), n,
+                       NUM_COUNTERS, (const u32 *)(ctx->ws + ctx->last_order),
+                       (const i64 *)(ctx->ws + ctx->last_counters), counters);
+    HIP_TRY(hipGetLastError());
+    return NIORCA_OK;
+}
+
+extern "C" niorca_status niorca_last_features(niorca_ctx *ctx, int32_t n, float *features, void *stream) {
+    if (!ctx) return NIORCA_EINVAL;
+    if (!features && n > 0) return fail(ctx, NIORCA_EINVAL, "features is NULL");
+    if (ctx->last_n != n || !ctx->last_feat || ctx->last_ws != ctx->ws)
+        return fail(ctx, NIORCA_EINVAL, "the last count on this context did not compute features for n = %d", n);
+    if (n == 0) return NIORCA_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    int64_t tot = (int64_t)n * 6;
+    hipLaunchKernelGGL(k_rows_to_input<float>, dim3((u32)((tot + 255) / 256)), dim3(256), 0, as_stream(stream), n,
+                       6, (const u32 *)(ctx->ws + ctx->last_order), (const float *)(ctx->ws + ctx->last_feat),
+                       features);
+    HIP_TRY(hipGetLastError());
+    return NIORCA_OK;
+}
+
+static uint64_t splitmix64(uint64_t *x) {
+    uint64_t z = (*x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+struct DevBufs {
+    std::vector<void *> p;
+    ~DevBufs() {
+        for (void *q : p) (void)hipFree(q);
+    }
+    template <typename T>
+    T *get(int64_t count) {
+        void *q = nullptr;
+        if (hipMalloc(&q, sizeof(T) * (count > 0 ? count : 1)) != hipSuccess) return nullptr;
+        p.push_back(q);
+        return (T *)q;
+    }
+};
+
+extern "C" niorca_status niorca_mlp_train(niorca_ctx *ctx, const float *X, const float *y, int64_t N, int32_t epochs,
+                                          int32_t batch, float lr, uint64_t seed, float *model, double *mse,
+                                          void *stream) {
+    if (!ctx) return NIORCA_EINVAL;
+    ctx->err.clear();
+    if (N <= 0 || !X || !y || !model || epochs < 0 || batch <= 0 || batch > (1 << 20) || !(lr > 0.0f) ||
+        N >= ((int64_t)1 << 31))
+        return fail(ctx, NIORCA_EINVAL, "bad training arguments");
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = as_stream(stream);
+    const int nall = mlp_num_all(), ntr = mlp_num_trained();
+    DevBufs B;
+    float *P = B.get<float>(nall), *grad = B.get<float>(ntr), *m1 = B.get<float>(ntr), *m2 = B.get<float>(ntr);
+    float *A1 = B.get<float>((int64_t)batch * 32), *A2 = B.get<float>((int64_t)batch * 32);
+    float *D1 = B.get<float>((int64_t)batch * 32), *D2 = B.get<float>((int64_t)batch * 32);
+    float *G3 = B.get<float>(batch), *lossp = B.get<float>(batch), *pred = B.get<float>(N);
+    int32_t *idx = B.get<int32_t>(N);
+    const int nblocks = 512;
+    double *part = B.get<double>(nblocks * 12);
+    float *ys = B.get<float>(N), *ms = B.get<float>(2);
+    if (!P || !grad || !m1 || !m2 || !A1 || !A2 || !D1 || !D2 || !G3 || !lossp || !pred || !idx || !part || !ys ||
+        !ms)
+        return fail(ctx, NIORCA_ENOMEM, "training buffers");
+    // seeded initialisation: uniform(-a, a), a = sqrt(6 / fan_in); zero biases
+    std::vector<float> h(nall, 0.0f);
+    uint64_t rs = seed;
+    auto uni = [&](float a) { return (float)((double)(splitmix64(&rs) >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0) * a; };
+    for (int i = 0; i < 32 * 6; i++) h[i] = uni(sqrtf(6.0f / 6.0f));
+    for (int i = 0; i < 32 * 32; i++) h[224 + i] = uni(sqrtf(6.0f / 32.0f));
+    for (int i = 0; i < 32; i++) h[1280 + i] = uni(sqrtf(6.0f / 32.0f));
+    HIP_TRY(hipMemcpyAsync(P, h.data(), sizeof(float) * nall, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(m1, 0, sizeof(float) * ntr, s));
+    HIP_TRY(hipMemsetAsync(m2, 0, sizeof(float) * ntr, s));
+    HIP_TRY(mlp_feature_stats(N, X, part, nblocks, P, s));
+    // training runs on standardised targets; the output layer is rescaled at the end
+    HIP_TRY(mlp_standardise_targets(N, y, part, nblocks, ms, ys, s));
+    std::vector<int32_t> perm(N);
+    int step = 0;
+    for (int ep = 0; ep < epochs; ep++) {
+        for (int64_t i = 0; i < N; i++) perm[i] = (int32_t)i;
+        for (int64_t i = N - 1; i > 0; i--) {
+            int64_t j = (int64_t)(splitmix64(&rs) % (uint64_t)(i + 1));
+            std::swap(perm[i], perm[j]);
+        }
+        HIP_TRY(hipMemcpyAsync(idx, perm.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));  // perm is reused by the next epoch
+        for (int64_t b0 = 0; b0 + batch <= N || (b0 == 0 && N < batch); b0 += batch) {
+            int32_t bs = (int32_t)(N < batch ? N : batch);
+            HIP_TRY(mlp_train_step(bs, idx + b0, X, ys, P, A1, A2, D1, D2, G3, lossp, grad, m1, m2, lr, ++step, s));
+            if (N < batch) break;
+        }
+    }
+    HIP_TRY(mlp_fold_output(P, ms, s));
+    HIP_TRY(mlp_predict(N, X, P, pred, s));
+    HIP_TRY(mlp_sse(N, pred, y, part, nblocks, s));
+    std::vector<double> hp(nblocks);
+    HIP_TRY(hipMemcpyAsync(hp.data(), part, sizeof(double) * nblocks, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(model, P, sizeof(float) * nall, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double sse = 0;
+    for (double v : hp) sse += v;
+    if (mse) *mse = sse / (double)N;
+    return NIORCA_OK;
+}
+
+extern "C" niorca_status niorca_mlp_predict(niorca_ctx *ctx, const float *model, const float *X, int64_t N,
+                                            float *pred, void *stream) {
+    if (!ctx) return NIORCA_EINVAL;
+    ctx->err.clear();
+    if (N < 0 || !model || (N > 0 && (!X || !pred))) return fail(ctx, NIORCA_EINVAL, "bad prediction arguments");
+    if (N == 0) return NIORCA_OK;
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = as_stream(stream);
+    DevBufs B;
+    float *P = B.get<float>(mlp_num_all());
+    if (!P) return fail(ctx, NIORCA_ENOMEM, "model buffer");
+    HIP_TRY(hipMemcpyAsync(P, model, sizeof(float) * mlp_num_all(), hipMemcpyHostToDevice, s));
+    HIP_TRY(mlp_predict(N, X, P, pred, s));
+    HIP_TRY(hipStreamSynchronize(s));  // P is freed on return
+    return NIORCA_OK;
 }
 
 extern "C" niorca_status niorca_stage_times(niorca_ctx *ctx, float *ms, int32_t count) {
@@ -656,5 +849,11 @@ extern "C" niorca_status niorca_set_cost_model(niorca_ctx *ctx, const float *wei
     ctx->mlp.assign(weights, weights + count);
     ctx->thr_wave = thr_wave;
     ctx->thr_block = thr_block;
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (!ctx->mlp_dev && hipMalloc((void **)&ctx->mlp_dev, sizeof(float) * NIORCA_MLP_PARAMS) != hipSuccess) {
+        ctx->mlp_dev = nullptr;
+        return fail(ctx, NIORCA_ENOMEM, "model buffer");
+    }
+    HIP_TRY(hipMemcpy(ctx->mlp_dev, weights, sizeof(float) * NIORCA_MLP_PARAMS, hipMemcpyHostToDevice));
     return NIORCA_OK;
 }

@@ -101,9 +101,28 @@ __global__ void k_classify(DevGraph g, const i64 *__restrict__ wlight, const i64
         wl = wlight[y];
         wh = wheavy[y];
     }
-    list_push(valid && du >= 2 && du <= th.tri_wave, WC_TRI_WAVE, y, lists, st);
-    list_push(valid && du >= 2 && du > th.tri_wave && du <= th.tri_block, WC_TRI_BLOCK, y, lists, st);
-    list_push(valid && du >= 2 && du > th.tri_block, WC_TRI_LARGE, y, lists, st);
+    // Stage I/II items: capacity decides first (|N+| sizes the LDS structures); items
+    // that fit a wave may move to one lane or to a whole workgroup by predicted work
+    int tc = -1;
+    if (valid && du >= 2) {
+        if (du > th.tri_block) tc = WC_TRI_LARGE;
+        else if (du > th.tri_wave) tc = WC_TRI_BLOCK;
+        else {
+            tc = WC_TRI_WAVE;
+            if (th.bin_mode == 1) {
+                if (du <= TRI_THREAD_CAP && d <= th.deg_thread) tc = WC_TRI_THREAD;
+                else if (d >= th.deg_block) tc = WC_TRI_BLOCK;
+            } else if (th.bin_mode == 2) {
+                float p = th.pred[y];
+                if (du <= TRI_THREAD_CAP && p <= th.thr_thread) tc = WC_TRI_THREAD;
+                else if (p >= th.thr_block) tc = WC_TRI_BLOCK;
+            }
+        }
+    }
+    list_push(tc == WC_TRI_THREAD, WC_TRI_THREAD, y, lists, st);
+    list_push(tc == WC_TRI_WAVE, WC_TRI_WAVE, y, lists, st);
+    list_push(tc == WC_TRI_BLOCK, WC_TRI_BLOCK, y, lists, st);
+    list_push(tc == WC_TRI_LARGE, WC_TRI_LARGE, y, lists, st);
     bool qlw = valid && wl > 0 && wl <= th.ql_wave;
     bool qlb = valid && wl > th.ql_wave && wl <= th.ql_block;
     bool qlg = valid && wl > th.ql_block;
@@ -164,7 +183,8 @@ template <int NT, int MODE>
 __device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, const ProbeMem &M, int hc,
                                            int words, i32 *__restrict__ t, i64 *__restrict__ K4,
                                            i64 *__restrict__ tau, i64 *red, i32 *red32, const TriCache &tc,
-                                           ItemState *S) {
+                                           ItemState *S, i64 *__restrict__ counters) {
+    const i64 t_start = (counters && MODE == PROBE_TRI) ? (i64)clock64() : 0;
     const i32 base = g.nsplit[u];
     const i32 du = g.nrp[u + 1] - base;
     if (MODE == PROBE_TAU && tc.cnt[u] >= 0) {
@@ -295,9 +315,10 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, co
                 tc.cnt[u] = -1;
             }
         }
-        i64 s_local = 0;
+        i64 s_local = 0, tri2 = 0, words_scanned = 0;
         for (int j = tid; j < du; j += NT) {
             i32 c = M.tcnt[j];
+            tri2 += c;
             if (c) atomicAdd(&t[base + j], c);
             i64 sj = 0;
             for (int wd = 0; wd < nw; wd++) {
@@ -306,6 +327,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, co
                     int b = __ffs(bits) - 1;
                     bits &= bits - 1;
                     int i = wd * 32 + b;
+                    words_scanned += nw;
                     for (int k = 0; k < nw; k++) sj += __popc(M.A[i * words + k] & M.A[j * words + k]);
                 }
             }
@@ -315,6 +337,16 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, co
         }
         i64 s = item_sum<NT>(s_local, red, tid);
         if (tid == 0 && s) atomic_add_i64(&K4[u], s / 6);
+        if (counters) {
+            tri2 = item_sum<NT>(tri2, red, tid);
+            words_scanned = item_sum<NT>(words_scanned, red, tid);
+            if (tid == 0) {
+                i64 *c = counters + (i64)u * NUM_COUNTERS;
+                c[1] = tri2 >> 1;
+                c[2] = words_scanned;
+                c[6] = (i64)clock64() - t_start;
+            }
+        }
     } else {
         for (int j = tid; j < du; j += NT) {
             i64 a = M.acc[j];
@@ -330,7 +362,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, co
 template <int MODE>
 __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__restrict__ list,
                                                     const GraphStats *__restrict__ st, i32 *t, i64 *K4,
-                                                    i64 *tau, TriCache tc) {
+                                                    i64 *tau, TriCache tc, i64 *counters) {
     constexpr int CAP = TRI_WAVE_CAP, HC = 2 * CAP, WORDS = CAP / 32;
     __shared__ i32 s_hkey[4][HC];
     __shared__ i32 s_hpos[4][HC];
@@ -347,7 +379,7 @@ __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__res
     const i32 cnt = st->cnt[WC_TRI_WAVE];
     const int waves = gridDim.x * 4;
     for (i32 it = blockIdx.x * 4 + w; it < cnt; it += waves)
-        probe_item<WAVE, MODE>(g, list[it], tid, M, HC, WORDS, t, K4, tau, nullptr, nullptr, tc, &s_st[w]);
+        probe_item<WAVE, MODE>(g, list[it], tid, M, HC, WORDS, t, K4, tau, nullptr, nullptr, tc, &s_st[w], counters);
 }
 
 // One 256-thread workgroup per vertex, 64 < |N+(u)| <= TRI_BLOCK_CAP.
@@ -355,7 +387,7 @@ __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__res
 template <int MODE>
 __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__restrict__ list,
                                                      const GraphStats *__restrict__ st, i32 *t, i64 *K4,
-                                                     i64 *tau, TriCache tc) {
+                                                     i64 *tau, TriCache tc, i64 *counters) {
     constexpr int CAP = TRI_BLOCK_CAP, HC = 2 * CAP, WORDS = CAP / 32;
     __shared__ i32 s_hkey[HC];
     __shared__ i32 s_hpos[HC];
@@ -372,7 +404,95 @@ __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__
     __syncthreads();
     const i32 cnt = st->cnt[WC_TRI_BLOCK];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
-        probe_item<PB_NT, MODE>(g, list[it], threadIdx.x, M, HC, WORDS, t, K4, tau, s_red, s_red32, tc, &s_st);
+        probe_item<PB_NT, MODE>(g, list[it], threadIdx.x, M, HC, WORDS, t, K4, tau, s_red, s_red32, tc, &s_st,
+                                counters);
+}
+
+// One lane per vertex for tiny items (|N+(u)| <= 8): N+(u) in registers, the
+// induced graph H_u as an 8x8 bit matrix in one 64-bit word, no LDS.  Triangles
+// are not kept for tau; the tau pass probes these items again.
+template <int MODE>
+__global__ void __launch_bounds__(256) k_probe_thread(DevGraph g, const i32 *__restrict__ list,
+                                                      const GraphStats *__restrict__ st, i32 *t, i64 *K4,
+                                                      i64 *tau, TriCache tc, i64 *counters) {
+    constexpr int C = TRI_THREAD_CAP;
+    const i32 cnt = st->cnt[WC_TRI_THREAD];
+    for (i32 it = blockIdx.x * blockDim.x + threadIdx.x; it < cnt; it += gridDim.x * blockDim.x) {
+        const i64 t_start = (counters && MODE == PROBE_TRI) ? (i64)clock64() : 0;
+        const i32 u = list[it];
+        const i32 base = g.nsplit[u];
+        const i32 du = g.nrp[u + 1] - base;
+        i32 nu[C];
+        i32 tcl[C];
+        i64 acc[C];
+#pragma unroll
+        for (int j = 0; j < C; j++) {
+            nu[j] = j < du ? g.ncol[base + j] : -1;
+            tcl[j] = 0;
+            acc[j] = 0;
+        }
+        u64 A = 0;
+        i64 tau_local = 0, probes = 0;
+#pragma unroll
+        for (int i = 0; i < C; i++) {
+            if (i >= du) break;
+            const i32 v = nu[i];
+            const i32 q0 = g.nsplit[v], q1 = g.nrp[v + 1];
+            probes += q1 - q0;
+            for (i32 q = q0; q < q1; q++) {
+                const i32 w = g.ncol[q];
+                int p = -1;
+#pragma unroll
+                for (int j = 0; j < C; j++)
+                    if (j > i && nu[j] == w) p = j;
+                if (p < 0) continue;
+                if (MODE == PROBE_TRI) {
+#pragma unroll
+                    for (int j = 0; j < C; j++) tcl[j] += (j == i) + (j == p);
+                    atomicAdd(&t[q], 1);
+                    A |= (1ull << (i * C + p)) | (1ull << (p * C + i));
+                } else {
+                    tau_local += t[q];
+                    const i64 tup = t[base + p], tui = t[base + i];
+#pragma unroll
+                    for (int j = 0; j < C; j++) acc[j] += (j == i) ? tup : ((j == p) ? tui : 0);
+                }
+            }
+        }
+        if (MODE == PROBE_TRI) {
+            i64 s = 0, tri2 = 0, words = 0;
+#pragma unroll
+            for (int j = 0; j < C; j++) {
+                if (j >= du) break;
+                tri2 += tcl[j];
+                if (tcl[j]) atomicAdd(&t[base + j], tcl[j]);
+                const u32 rj = (u32)(A >> (j * C)) & 0xffu;
+                i64 sj = 0;
+#pragma unroll
+                for (int i = 0; i < C; i++)
+                    if ((rj >> i) & 1u) {
+                        sj += __popc(((u32)(A >> (i * C)) & 0xffu) & rj);
+                        words++;
+                    }
+                if (sj) atomic_add_i64(&K4[nu[j]], sj >> 1);
+                s += sj;
+            }
+            if (s) atomic_add_i64(&K4[u], s / 6);
+            tc.cnt[u] = -1;
+            if (counters) {
+                i64 *c = counters + (i64)u * NUM_COUNTERS;
+                c[1] = tri2 >> 1;
+                c[2] = words;
+                c[6] = (i64)clock64() - t_start;
+            }
+        } else {
+            if (tau_local) atomic_add_i64(&tau[u], tau_local);
+#pragma unroll
+            for (int j = 0; j < C; j++)
+                if (j < du && acc[j]) atomic_add_i64(&tau[nu[j]], acc[j]);
+        }
+        (void)probes;
+    }
 }
 
 // |N+(u)| > TRI_BLOCK_CAP: the same item code on per-workgroup global scratch.
@@ -380,7 +500,7 @@ template <int MODE>
 __global__ void __launch_bounds__(256) k_probe_large(DevGraph g, const i32 *__restrict__ list,
                                                      const GraphStats *__restrict__ st, i32 *t, i64 *K4,
                                                      i64 *tau, TriCache tc, char *scratch, i64 slice_bytes,
-                                                     int cap, int hc) {
+                                                     int cap, int hc, i64 *counters) {
     __shared__ i64 s_red[4];
     __shared__ i32 s_red32[4];
     const int words = (cap + 31) / 32;
@@ -398,7 +518,8 @@ __global__ void __launch_bounds__(256) k_probe_large(DevGraph g, const i32 *__re
     __syncthreads();
     const i32 cnt = st->cnt[WC_TRI_LARGE];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
-        probe_item<256, MODE>(g, list[it], threadIdx.x, M, hc, words, t, K4, tau, s_red, s_red32, tc, &s_st);
+        probe_item<256, MODE>(g, list[it], threadIdx.x, M, hc, words, t, K4, tau, s_red, s_red32, tc, &s_st,
+                              counters);
 }
 
 i64 probe_large_slice_bytes(int cap, int hc) {
@@ -993,27 +1114,31 @@ hipError_t launch_classify(const DevGraph &g, const i64 *wl, const i64 *wh, cons
 hipError_t launch_probe(int mode, const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i32 *t,
                         i64 *K4, i64 *tau, const TriCacheArgs &tca, char *large_scratch, i64 large_slice,
                         int large_cap, int large_hc, int large_blocks, int grid_wave, int grid_block,
-                        hipStream_t s) {
+                        i64 *counters, hipStream_t s) {
     TriCache tw{tca.rec, tca.cap, tca.bump, tca.off, tca.cnt, tca.chunk_wave};
     TriCache tb{tca.rec, tca.cap, tca.bump, tca.off, tca.cnt, tca.chunk_block};
     if (mode == PROBE_TRI) {
+        hipLaunchKernelGGL(k_probe_thread<PROBE_TRI>, dim3(grid_wave), dim3(256), 0, s, g,
+                           lists_host[WC_TRI_THREAD], st, t, K4, tau, tw, counters);
         hipLaunchKernelGGL(k_probe_wave<PROBE_TRI>, dim3(grid_wave), dim3(256), 0, s, g, lists_host[WC_TRI_WAVE], st,
-                           t, K4, tau, tw);
+                           t, K4, tau, tw, counters);
         hipLaunchKernelGGL(k_probe_block<PROBE_TRI>, dim3(grid_block), dim3(PB_NT), 0, s, g,
-                           lists_host[WC_TRI_BLOCK], st, t, K4, tau, tb);
+                           lists_host[WC_TRI_BLOCK], st, t, K4, tau, tb, counters);
         if (large_blocks > 0)
             hipLaunchKernelGGL(k_probe_large<PROBE_TRI>, dim3(large_blocks), dim3(256), 0, s, g,
                                lists_host[WC_TRI_LARGE], st, t, K4, tau, tb, large_scratch, large_slice, large_cap,
-                               large_hc);
+                               large_hc, counters);
     } else {
+        hipLaunchKernelGGL(k_probe_thread<PROBE_TAU>, dim3(grid_wave), dim3(256), 0, s, g,
+                           lists_host[WC_TRI_THREAD], st, t, K4, tau, tw, (i64 *)nullptr);
         hipLaunchKernelGGL(k_probe_wave<PROBE_TAU>, dim3(grid_wave), dim3(256), 0, s, g, lists_host[WC_TRI_WAVE], st,
-                           t, K4, tau, tw);
+                           t, K4, tau, tw, (i64 *)nullptr);
         hipLaunchKernelGGL(k_probe_block<PROBE_TAU>, dim3(grid_block), dim3(PB_NT), 0, s, g,
-                           lists_host[WC_TRI_BLOCK], st, t, K4, tau, tb);
+                           lists_host[WC_TRI_BLOCK], st, t, K4, tau, tb, (i64 *)nullptr);
         if (large_blocks > 0)
             hipLaunchKernelGGL(k_probe_large<PROBE_TAU>, dim3(large_blocks), dim3(256), 0, s, g,
                                lists_host[WC_TRI_LARGE], st, t, K4, tau, tb, large_scratch, large_slice, large_cap,
-                               large_hc);
+                               large_hc, (i64 *)nullptr);
     }
     return hipGetLastError();
 }

@@ -22,6 +22,7 @@ struct GraphStats {
 // Classes of work items (indices into GraphStats::cnt and the list table).
 enum WorkClass {
     WC_TRI_WAVE = 0,   // Stage I/II/tau, 2 <= |N+(u)| <= 64, one wave per vertex
+    WC_TRI_THREAD,     // |N+(u)| <= 8 and little predicted work: one lane per vertex
     WC_TRI_BLOCK,      // 64 < |N+(u)| <= 512, one workgroup
     WC_TRI_LARGE,      // |N+(u)| > 512, one workgroup with global scratch
     WC_QL_WAVE,        // 4-cycles, u as largest vertex (u < h0), small hash per wave
@@ -39,14 +40,23 @@ struct ListPtrs {
 };
 
 // Runtime class thresholds (each at most the capacity of its kernel).
+#define TRI_THREAD_CAP 8
 struct Thresholds {
     int tri_wave;    // |N+| <= tri_wave -> wave class (<= TRI_WAVE_CAP)
     int tri_block;   // |N+| <= tri_block -> workgroup class (<= TRI_BLOCK_CAP)
+    // work binning of the Stage I/II items that fit a wave (they never change a count):
+    int bin_mode;    // 0 capacity only, 1 degree thresholds, 2 learned model
+    int deg_thread;  // mode 1: degree <= deg_thread (and |N+| <= 8) -> one lane
+    int deg_block;   // mode 1: degree >= deg_block -> one workgroup
+    float thr_thread, thr_block;  // mode 2: predicted log2 work bounds of the same two classes
+    const float *pred;            // mode 2: predictions by new id
     i64 ql_wave;     // wedges <= ql_wave -> wave hash (<= QL_WAVE_HC/2)
     i64 ql_block;    // wedges <= ql_block -> workgroup hash (<= QL_BLOCK_HC/2)
     i64 qh_wave;
     i64 qh_block;
 };
+
+#define NUM_COUNTERS 7   // per-vertex work counters (see include/niorca.h)
 
 // Class capacities (shared by classification and kernels).
 #define TRI_WAVE_CAP 64
@@ -102,7 +112,7 @@ __global__ void k_sort_upper_small(i32 n, const i32 *nrp, const i32 *nsplit, i32
 __global__ void k_sort_upper_large(const i32 *nrp, const i32 *nsplit, i32 *ncol, i32 *hstart, i32 h0,
                                    const i32 *longlist, const i32 *longcount);
 __global__ void k_mirror(i32 n, const i32 *nrp, const i32 *nsplit, const i32 *ncol, const i32 *hstart, i32 h0,
-                         i32 *mirror, i64 *wlight, i64 *wheavy);
+                         i32 *mirror, i64 *wlight, i64 *wheavy, i64 *probes, float *feat);
 #define LSORT_CAP 16384
 
 // count.hip
@@ -119,7 +129,20 @@ struct TriCacheArgs {
 hipError_t launch_probe(int mode, const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i32 *t,
                         i64 *K4, i64 *tau, const TriCacheArgs &tca, char *large_scratch, i64 large_slice,
                         int large_cap, int large_hc, int large_blocks, int grid_wave, int grid_block,
-                        hipStream_t s);
+                        i64 *counters, hipStream_t s);
+
+// mlp.hip
+int mlp_num_trained();
+int mlp_num_all();
+hipError_t mlp_predict(i64 n, const float *X, const float *P, float *pred, hipStream_t s);
+hipError_t mlp_feature_stats(i64 n, const float *X, double *part, int nblocks, float *P, hipStream_t s);
+hipError_t mlp_train_step(i32 B, const i32 *idx, const float *X, const float *y, float *P, float *A1, float *A2,
+                          float *D1, float *D2, float *G3, float *lossp, float *grad, float *m1, float *m2, float lr,
+                          int step, hipStream_t s);
+hipError_t mlp_sse(i64 n, const float *pred, const float *y, double *part, int nblocks, hipStream_t s);
+hipError_t mlp_standardise_targets(i64 n, const float *y, double *part, int nblocks, float *ms, float *ys,
+                                   hipStream_t s);
+hipError_t mlp_fold_output(float *P, const float *ms, hipStream_t s);
 hipError_t launch_sums(const DevGraph &g, const i32 *t, const Accum &acc, int grid, hipStream_t s);
 hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvars, GraphStats *st, int grid,
                         hipStream_t s);
