@@ -1,15 +1,20 @@
 """Benchmark: edges/s of the full 15-orbit non-induced count on one MI355X.
 
 One step = one niorca_count call on a device-resident CSR (degree orientation,
-Stage I, Stage II, Stage III and the equations), inputs already in HBM.
+Stage I, Stage II, Stage III and the equations); inputs are in HBM before the
+timed region starts, outputs stay there.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload chung_lu_4m]
+                    [--forms all|none] [--cpu-budget S]
 
-Prints one JSON line.  `roofline` reports the dominant stage's algorithmic bytes
-(the CSR words the method itself must read and the counters it must update,
-computed on the host from the graph) over that stage's HIP-event duration on the
-launching stream; `cpu_baseline` times the CPU oracle on a bounded random sample
-of vertices and scales it to the whole graph.
+Prints one JSON line.  `value` is the plain form on the workload; `forms` adds
+the degree-binned and MLP-binned forms (on the workload and on R-MAT scale 22)
+and the batched form (50,000 small graphs, hipGraph-captured, autotuned).
+`roofline` is for the dominant kernel of the timed steps: its algorithmic bytes
+(the CSR words and row metadata the method itself must read for the work units
+that launch processed, reported by the library's work classes) over its HIP-event
+duration on the launching stream.  `cpu_baseline` times the CPU oracle on a
+bounded random vertex sample and scales it to the whole graph.
 """
 from __future__ import annotations
 
@@ -25,37 +30,47 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TUNE_FILE = os.path.join(ROOT, "paper_2606_29651_amd", "tuning.json")
 
 
-def rank_layout(g):
-    """Host model of the degree orientation: new ids by (degree, id), per-vertex
-    out-degree d+ and in-degree d- (numpy, for the byte accounting only)."""
-    d = g.degrees().astype(np.int64)
-    n = g.n
-    order = np.lexsort((np.arange(n), d))
-    perm = np.empty(n, np.int64)
-    perm[order] = np.arange(n)
-    src = np.repeat(np.arange(n, dtype=np.int64), d)
-    up = perm[g.col.astype(np.int64)] > perm[src]
-    dplus = np.bincount(src[up], minlength=n)
-    return d, dplus, d - dplus
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(g):
-    """Bytes each stage must move at minimum (int32 = 4 B), from the CSR alone.
+# Algorithmic bytes per unit, per kernel ("Measurement"):
+#   Stage I/II probe kernels: 4 B per probe (one N+(v) entry), 12 B per N+(u) entry
+#     (the entry and the two row offsets of v);
+#   4-cycle kernels: 8 B per wedge (its key is read in each of the two sweeps) and
+#     16 B per row slot (neighbour id, segment bounds).
+KERNEL_CLASS = {"probe_thread": "tri_thread", "probe_wave": "tri_wave", "probe_block": "tri_block",
+                "probe_large": "tri_large", "ql_wave": "ql_wave", "ql_block": "ql_block",
+                "ql_global": "ql_global", "qh_wave": "qh_wave", "qh_block": "qh_block",
+                "qh_dense": "qh_dense", "qh_global": "qh_global"}
 
-    stage1_k4: every oriented edge u->v reads the list N+(v) once (4 B per entry),
-               N+(u) once per u, two row offsets per oriented edge, and updates
-               t of the three edges of each triangle (read + write, 8 B each); the
-               triangle count comes from the same probe model (one hit per entry of
-               N+(v) that lies in N+(u)) and is not known before counting, so the
-               probe reads alone are used as the lower bound.
-    """
-    d, dplus, dminus = rank_layout(g)
-    m = g.m
-    probes = int((dminus * dplus).sum())
-    stage1 = 4 * probes + 4 * m + 8 * m
-    return {"stage1_k4": stage1, "probes": probes}
+
+def kernel_bytes(kernel, stats):
+    cnt, work, slots = stats[KERNEL_CLASS[kernel]]
+    if kernel.startswith("probe"):
+        return 4 * work + 12 * slots
+    return 8 * work + 16 * slots
+
+
+def time_count(ni, ctx, rp, cl, out, flags, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        ni.count(rp, cl, out=out, ctx=ctx, flags=flags)
+    torch.cuda.synchronize()
+    stages, kernels = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ni.count(rp, cl, out=out, ctx=ctx, flags=flags | ni.TIMING)
+        stages.append(ctx.stage_times())
+        kernels.append(ctx.kernel_times())
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / steps
+    avg_s = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
+    avg_k = {k: float(np.mean([s[k] for s in kernels])) for k in kernels[0]}
+    return ms, avg_s, avg_k
 
 
 def cpu_baseline(g, budget_s: float = 15.0, seed: int = 7):
@@ -80,6 +95,117 @@ def cpu_baseline(g, budget_s: float = 15.0, seed: int = 7):
                       f"with oracle.orbits_at (per-vertex paper method), scaled by n/{done}"}
 
 
+def stage1_work(c):
+    return c[:, 0] + 4 * c[:, 1] + c[:, 2]
+
+
+def train_work_model(ni, ctx, graphs):
+    """Counters of the plain form on the training graphs -> model of log2 work."""
+    import torch
+    Xs, ys = [], []
+    for g in graphs:
+        rp, cl = torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda()
+        ni.count(rp, cl, ctx=ctx, flags=ni.COUNTERS)
+        c = ni.work_counters(g.n, ctx=ctx)
+        X = ni.last_features(g.n, ctx=ctx)
+        keep = c[:, 6] > 0
+        Xs.append(X[keep])
+        ys.append(torch.log2(1.0 + stage1_work(c[keep]).double()).float())
+        del rp, cl
+    X = torch.cat(Xs).contiguous()
+    y = torch.cat(ys).contiguous()
+    model, mse = ni.mlp_train(X, y, epochs=3, batch=8192, lr=3e-3, seed=1, ctx=ctx)
+    var = float(torch.var(y.double()))
+    return model, {"rows": int(X.shape[0]), "mse": mse, "target_var": var}
+
+
+def forms(args, ni, ctx, g, rp, cl, out, base_ms):
+    import torch
+    import graphgen as gg
+    from paper_2606_29651_amd import autotune
+    res = {}
+    t0 = time.time()
+    er = gg.config_graph("er_tiny", seed=args.seed)
+    model, fit = train_work_model(ni, ctx, [er, g])
+    log(f"[bench] work model trained on {fit['rows']} items, mse {fit['mse']:.3f} (target var "
+        f"{fit['target_var']:.3f}) in {time.time() - t0:.1f}s")
+    # thresholds of the learned binning: a small search on the training graph
+    ref = out.clone()
+    best = None
+    for thr_t in (8.0, 10.0, 12.0):
+        for thr_b in (15.0, 17.0, 99.0):
+            ni.set_cost_model(model, thr_t, thr_b, ctx=ctx)
+            ms, _, _ = time_count(ni, ctx, rp, cl, out, ni.BIN_MLP, 2, 1)
+            if best is None or ms < best[0]:
+                best = (ms, thr_t, thr_b)
+    ni.set_cost_model(model, best[1], best[2], ctx=ctx)
+    res["work_model"] = {"train_rows": fit["rows"], "mse": round(fit["mse"], 4),
+                         "target_var": round(fit["target_var"], 4), "thr_thread": best[1], "thr_block": best[2]}
+    deg_ms, _, _ = time_count(ni, ctx, rp, cl, out, ni.BIN_DEGREE, 3, 1)
+    same_deg = bool(torch.equal(out, ref))
+    mlp_ms, _, _ = time_count(ni, ctx, rp, cl, out, ni.BIN_MLP, 3, 1)
+    same_mlp = bool(torch.equal(out, ref))
+    res[args.workload] = {"plain": g.m / (base_ms * 1e-3), "degree": g.m / (deg_ms * 1e-3),
+                          "mlp": g.m / (mlp_ms * 1e-3), "identical": same_deg and same_mlp}
+    del ref
+    # R-MAT scale 22: plain vs degree-binned vs MLP-binned
+    t0 = time.time()
+    r = gg.config_graph("rmat22", seed=args.seed)
+    log(f"[bench] rmat22 n={r.n} m={r.m} generated in {time.time() - t0:.1f}s")
+    rrp, rcl = torch.from_numpy(r.row_ptr).cuda(), torch.from_numpy(r.col).cuda()
+    rout = torch.empty((r.n, 15), dtype=torch.int64, device="cuda")
+    pl_ms, pl_st, _ = time_count(ni, ctx, rrp, rcl, rout, 0, 3, 1)
+    rref = rout.clone()
+    dg_ms, _, _ = time_count(ni, ctx, rrp, rcl, rout, ni.BIN_DEGREE, 3, 1)
+    same = bool(torch.equal(rout, rref))
+    ml_ms, _, _ = time_count(ni, ctx, rrp, rcl, rout, ni.BIN_MLP, 3, 1)
+    same = same and bool(torch.equal(rout, rref))
+    res["rmat22"] = {"n": r.n, "m": r.m, "plain": r.m / (pl_ms * 1e-3), "degree": r.m / (dg_ms * 1e-3),
+                     "mlp": r.m / (ml_ms * 1e-3), "identical": same,
+                     "plain_stage_ms": {k: round(v, 3) for k, v in pl_st.items()}}
+    del rrp, rcl, rout, rref
+    torch.cuda.empty_cache()
+    # batched: 50,000 small graphs, autotuned parameters, captured hipGraph
+    t0 = time.time()
+    graphs = gg.batch_mix(args.batch_graphs, 20, 2000, seed=args.seed)
+    vtx_off, brp, bcol = gg.pack_batch(graphs)
+    bm = int(brp[-1] // 2)
+    log(f"[bench] batch of {len(graphs)} graphs, n={vtx_off[-1]} m={bm} in {time.time() - t0:.1f}s")
+    # tune on a tenth of the batch
+    sub = graphs[: max(1, len(graphs) // 10)]
+    s_off, s_rp, s_col = gg.pack_batch(sub)
+    d_srp, d_scol = torch.from_numpy(s_rp).cuda(), torch.from_numpy(s_col).cuda()
+    s_out = torch.empty((int(s_off[-1]), 15), dtype=torch.int64, device="cuda")
+    tctx = ni.Context(0)
+    cands = autotune.grid(heavy_k=[0, 4096, 32768], tri_wave=[32, 64], qh_wave=[256, 512], ql_wave=[128, 256])
+    tuned = autotune.tune(tctx, lambda: ni.count_batched(s_off, d_srp, d_scol, out=s_out, ctx=tctx), cands,
+                          repeats=2)
+    autotune.save(TUNE_FILE, "batch_mix", {"best": tuned["best"], "ms_on_tenth": tuned["ms"]})
+    del d_srp, d_scol, s_out
+    d_brp, d_bcol = torch.from_numpy(brp).cuda(), torch.from_numpy(bcol).cuda()
+    b_out = torch.empty((int(vtx_off[-1]), 15), dtype=torch.int64, device="cuda")
+    stream = torch.cuda.Stream()
+    ni.count_batched(vtx_off, d_brp, d_bcol, out=b_out, ctx=tctx, stream=stream, flags=ni.GRAPH_CAPTURE)
+    stream.synchronize()
+    reps = 3
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        ni.count_batched(vtx_off, d_brp, d_bcol, out=b_out, ctx=tctx, stream=stream, flags=ni.GRAPH_CAPTURE)
+    stream.synchronize()
+    b_ms = 1000.0 * (time.perf_counter() - t1) / reps
+    # the same batch through the plain per-call path (no capture) for comparison
+    b_ref = b_out.clone()
+    t1 = time.perf_counter()
+    ni.count_batched(vtx_off, d_brp, d_bcol, out=b_out, ctx=tctx, stream=stream)
+    stream.synchronize()
+    nb_ms = 1000.0 * (time.perf_counter() - t1)
+    res["batch_mix"] = {"graphs": len(graphs), "n": int(vtx_off[-1]), "m": bm, "captured_ms": b_ms,
+                        "value": bm / (b_ms * 1e-3), "uncaptured_ms": nb_ms,
+                        "identical": bool(torch.equal(b_out, b_ref)), "tuned": tuned["best"]}
+    tctx.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +215,8 @@ def main():
     ap.add_argument("--seed", type=int, default=42)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forms", default="all", choices=["all", "none"])
+    ap.add_argument("--batch-graphs", type=int, default=50000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
@@ -101,36 +229,24 @@ def main():
 
     t0 = time.time()
     g = gg.config_graph(args.workload, seed=args.seed)
-    print(f"[bench] generated {g.name} n={g.n} m={g.m} in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    log(f"[bench] generated {g.name} n={g.n} m={g.m} in {time.time() - t0:.1f}s")
     dev = torch.device("cuda:0")
     rp = torch.from_numpy(g.row_ptr).to(dev)
     cl = torch.from_numpy(g.col).to(dev)
     out = torch.empty((g.n, 15), dtype=torch.int64, device=dev)
     ctx = ni.Context(0)
-    for _ in range(args.warmup):
-        ni.count(rp, cl, out=out, ctx=ctx)
-    torch.cuda.synchronize()
-    print("[bench] warmup done", file=sys.stderr, flush=True)
-    stages = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        ni.count(rp, cl, out=out, ctx=ctx, flags=ni.TIMING)
-        stages.append(ctx.stage_times())
-    torch.cuda.synchronize()
-    total_s = time.perf_counter() - t_start
-    ms = 1000.0 * total_s / args.steps
-    avg = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
-    print("[bench] stage ms " + json.dumps({k: round(v, 3) for k, v in avg.items()}), file=sys.stderr, flush=True)
-
-    ab = algorithmic_bytes(g)
-    dom = max(avg, key=avg.get)
-    roof = {"bound": "hbm", "kernel": "stage1_k4", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": None, "traffic": None, "dominant_stage": dom}
-    if avg["stage1_k4"] > 0:
-        ach = ab["stage1_k4"] / (avg["stage1_k4"] * 1e-3) / 1e9
-        roof.update(achieved=round(ach, 1), frac=round(ach / HBM_PEAK_GBS, 4))
-    cpu = None if args.no_cpu_baseline else cpu_baseline(g, args.cpu_budget)
+    ms, stage_ms, kernel_ms = time_count(ni, ctx, rp, cl, out, 0, args.steps, args.warmup)
+    stats = ctx.class_stats()
+    log("[bench] stage ms " + json.dumps({k: round(v, 3) for k, v in stage_ms.items()}))
+    log("[bench] kernel ms " + json.dumps({k: round(v, 3) for k, v in kernel_ms.items()}))
+    dom = max(kernel_ms, key=kernel_ms.get)
+    bytes_dom = kernel_bytes(dom, stats)
+    ach = bytes_dom / (kernel_ms[dom] * 1e-3) / 1e9 if kernel_ms[dom] > 0 else 0.0
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel_ms": round(kernel_ms[dom], 4), "algorithmic_bytes": int(bytes_dom),
+            "units": {"class": KERNEL_CLASS[dom], "items": stats[KERNEL_CLASS[dom]][0],
+                      "work": stats[KERNEL_CLASS[dom]][1], "slots": stats[KERNEL_CLASS[dom]][2]}}
     rec = {
         "metric": "edges/sec for full 15-orbit non-induced count",
         "value": g.m / (ms * 1e-3),
@@ -145,10 +261,13 @@ def main():
         "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": g.n, "m": g.m, "form": "plain", "seed": args.seed},
-        "stage_ms": {k: round(v, 4) for k, v in avg.items()},
+        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "kernel_ms": {k: round(v, 4) for k, v in kernel_ms.items()},
         "roofline": roof,
-        "cpu_baseline": cpu,
     }
+    if args.forms == "all":
+        rec["forms"] = forms(args, ni, ctx, g, rp, cl, out, ms)
+    rec["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(g, args.cpu_budget)
     print(json.dumps(rec))
     ctx.close()
 

@@ -150,6 +150,26 @@ niorca_status niorca_fvars(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_
 #define NIORCA_NUM_STAGES 9
 niorca_status niorca_stage_times(niorca_ctx *ctx, float *ms, int32_t count);
 
+/* Durations in ms of the kernel launches of the last NIORCA_TIMING count, from HIP
+ * events recorded around each launch on the call's stream (a launch with nothing to
+ * do still appears, with its near-zero time).  ms holds NIORCA_NUM_KERNEL_TIMES floats:
+ *   0 Stage I/II one-lane   1 Stage I/II wave   2 Stage I/II workgroup   3 Stage I/II large
+ *   4 4-cycles light, wave  5 light, workgroup   6 light, global counters
+ *   7 4-cycles heavy, wave  8 heavy, workgroup   9 heavy, dense LDS counters
+ *   10 heavy, global counters and the heavy-key reduction
+ * Waits for the call to finish. */
+#define NIORCA_NUM_KERNEL_TIMES 11
+niorca_status niorca_kernel_times(niorca_ctx *ctx, float *ms, int32_t count);
+
+/* Work classes of the last count: out HOST int64[3*NIORCA_NUM_CLASSES]: vertices per
+ * class, then their work units (Stage I probes for the first four classes, 4-cycle
+ * wedges for the others), then their row slots (|N+| for the first four, |N-| for the
+ * light 4-cycle classes, degree for the heavy ones).  Class order: Stage I/II wave,
+ * one-lane, workgroup, large; 4-cycles light wave, light workgroup, light global;
+ * heavy wave, heavy workgroup, heavy dense, heavy global.  Waits for the device. */
+#define NIORCA_NUM_CLASSES 11
+niorca_status niorca_class_stats(niorca_ctx *ctx, int64_t *out, int32_t count);
+
 /* Number of per-vertex work counters written by niorca_work_counters. */
 #define NIORCA_NUM_COUNTERS 7
 /* Per-vertex work of the last niorca_count on this context made with

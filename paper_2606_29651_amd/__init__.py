@@ -32,7 +32,11 @@ EXPORTS = ["niorca_create", "niorca_destroy", "niorca_last_error", "niorca_set_w
            "niorca_workspace_bytes", "niorca_set_param", "niorca_count", "niorca_count_batched",
            "niorca_edge_triangles", "niorca_k4", "niorca_fvars", "niorca_work_counters",
            "niorca_set_cost_model", "niorca_stage_times", "niorca_last_features", "niorca_mlp_train",
-           "niorca_mlp_predict"]
+           "niorca_mlp_predict", "niorca_kernel_times", "niorca_class_stats"]
+KERNEL_NAMES = ["probe_thread", "probe_wave", "probe_block", "probe_large", "ql_wave", "ql_block", "ql_global",
+                "qh_wave", "qh_block", "qh_dense", "qh_global"]
+CLASS_NAMES = ["tri_wave", "tri_thread", "tri_block", "tri_large", "ql_wave", "ql_block", "ql_global",
+               "qh_wave", "qh_block", "qh_dense", "qh_global"]
 NUM_COUNTERS = 7
 MLP_PARAMS = 1325
 COUNTER_NAMES = ["probes", "triangles", "k4_words", "wedges_light", "wedges_heavy", "sum_slots", "stage1_cycles"]
@@ -76,6 +80,8 @@ def load_library():
         lib.niorca_work_counters.argtypes = [P, i32, P, P]
         lib.niorca_set_cost_model.argtypes = [P, P, i32, ctypes.c_float, ctypes.c_float]
         lib.niorca_stage_times.argtypes = [P, P, i32]
+        lib.niorca_kernel_times.argtypes = [P, P, i32]
+        lib.niorca_class_stats.argtypes = [P, P, i32]
         lib.niorca_last_features.argtypes = [P, i32, P, P]
         lib.niorca_mlp_train.argtypes = [P, P, P, i64, i32, i32, ctypes.c_float, u64, P, P, P]
         lib.niorca_mlp_predict.argtypes = [P, P, P, i64, P, P]
@@ -123,6 +129,21 @@ class Context:
 
     def workspace_bytes(self) -> int:
         return int(self.lib.niorca_workspace_bytes(self.h))
+
+    def kernel_times(self) -> dict:
+        """Per-kernel ms of the last call made with TIMING (waits for it)."""
+        buf = (ctypes.c_float * len(KERNEL_NAMES))()
+        self.check(self.lib.niorca_kernel_times(self.h, ctypes.cast(buf, ctypes.c_void_p), len(KERNEL_NAMES)),
+                   "kernel_times")
+        return dict(zip(KERNEL_NAMES, [float(x) for x in buf]))
+
+    def class_stats(self) -> dict:
+        """{class: (vertices, work units, row slots)} of the last count."""
+        import numpy as np
+        k = len(CLASS_NAMES)
+        buf = np.zeros(3 * k, dtype=np.int64)
+        self.check(self.lib.niorca_class_stats(self.h, buf.ctypes.data_as(ctypes.c_void_p), 3 * k), "class_stats")
+        return {name: (int(buf[i]), int(buf[k + i]), int(buf[2 * k + i])) for i, name in enumerate(CLASS_NAMES)}
 
     def stage_times(self) -> dict:
         """Per-stage ms of the last call made with TIMING (waits for it)."""

@@ -1,0 +1,75 @@
+"""Autotuner for the work-class parameters (bin thresholds and the heavy 4-cycle
+range) of niorca_count / niorca_count_batched.
+
+A tuning run times each candidate parameter set on a representative workload
+(median of a few calls, HIP events inside the library) and keeps the fastest.
+Results are stored as JSON keyed by a workload label, so a later run can load
+them instead of searching again.  Counts never depend on these parameters; only
+which kernel shape handles a vertex does.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+import time
+from typing import Callable, Dict, Iterable, List
+
+DEFAULTS = {"tri_wave": 64, "tri_block": 512, "ql_wave": 256, "ql_block": 4096, "qh_wave": 512,
+            "qh_block": 4096, "heavy_k": 32768}
+
+
+def grid(**axes) -> List[Dict[str, int]]:
+    """All combinations of the given parameter axes."""
+    keys = list(axes)
+    return [dict(zip(keys, vals)) for vals in itertools.product(*(axes[k] for k in keys))]
+
+
+def apply(ctx, params: Dict[str, int]) -> None:
+    for k, v in {**DEFAULTS, **params}.items():
+        ctx.set_param(k, int(v))
+
+
+def tune(ctx, run: Callable[[], None], candidates: Iterable[Dict[str, int]], repeats: int = 3,
+         log: Callable[[str], None] = None) -> Dict:
+    """Time run() under every candidate (after one warm-up call) and return
+    {"best": params, "ms": best median ms, "table": [[params, ms], ...]}."""
+    import torch
+    table = []
+    for cand in candidates:
+        apply(ctx, cand)
+        run()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            run()
+            torch.cuda.synchronize()
+            times.append(1000.0 * (time.perf_counter() - t0))
+        times.sort()
+        ms = times[len(times) // 2]
+        table.append([cand, ms])
+        if log:
+            log(f"[autotune] {cand} -> {ms:.3f} ms")
+    best = min(table, key=lambda r: r[1])
+    apply(ctx, best[0])
+    return {"best": best[0], "ms": best[1], "table": table}
+
+
+def save(path: str, key: str, result: Dict) -> None:
+    data = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            data = json.load(f)
+    data[key] = result
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def load(path: str, key: str):
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f).get(key)

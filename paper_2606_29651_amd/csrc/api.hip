@@ -24,11 +24,12 @@ struct niorca_ctx {
     float thr_wave = 0.f, thr_block = 0.f;
     // where the last count left its counters and features (offsets in the workspace)
     int32_t last_n = -1;
-    uint64_t last_counters = 0, last_feat = 0, last_order = 0;
+    uint64_t last_counters = 0, last_feat = 0, last_order = 0, last_stats_dev = 0;
     char *last_ws = nullptr;
     GraphStats last{};
     // per-stage HIP events of the last call made with NIORCA_TIMING
     hipEvent_t ev[NIORCA_NUM_STAGES + 1] = {};
+    hipEvent_t kev[NUM_KERNEL_SLOTS] = {};
     bool ev_made = false;
     bool ev_valid = false;
     // tunable class thresholds and the size of the heavy 4-cycle key range
@@ -110,8 +111,10 @@ extern "C" niorca_status niorca_create(niorca_ctx **out, int device) {
 
 extern "C" void niorca_destroy(niorca_ctx *ctx) {
     if (!ctx) return;
-    if (ctx->ev_made)
+    if (ctx->ev_made) {
         for (auto &e : ctx->ev) (void)hipEventDestroy(e);
+        for (auto &e : ctx->kev) (void)hipEventDestroy(e);
+    }
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     if (ctx->mlp_dev) (void)hipFree(ctx->mlp_dev);
     if (ctx->ws) {
@@ -367,8 +370,11 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     ctx->ev_valid = false;
     if (timing && !ctx->ev_made) {
         for (auto &e : ctx->ev) HIP_TRY(hipEventCreate(&e));
+        for (auto &e : ctx->kev) HIP_TRY(hipEventCreate(&e));
         ctx->ev_made = true;
     }
+    const KernelEvents kev{timing ? ctx->kev : nullptr};
+    const KernelEvents nokev{nullptr};
 #define STAGE_MARK(i) \
     if (timing) HIP_TRY(hipEventRecord(ctx->ev[i], s))
     const int nthr = 256;
@@ -483,7 +489,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
         th.thr_block = ctx->thr_block;
     }
     DevGraph g{n, (i32)nnz, h0, nrp, nsplit, ncol, mirror, hstart, deg, val, wl, wh};
-    HIP_TRY(launch_classify(g, wl, wh, lists, dst, th, s));
+    HIP_TRY(launch_classify(g, wl, wh, probes, lists, dst, th, s));
     if (counters) {
         HIP_TRY(fill32(counters, (i64)sizeof(i64) * NUM_COUNTERS * n, 0u, s));
         hipLaunchKernelGGL(k_counters_base, dim3((n + nthr - 1) / nthr), dim3(nthr), 0, s, n, nrp, probes, wl, wh,
@@ -501,7 +507,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     HIP_TRY(fill32(tca.bump, sizeof(u64), 0u, s));
     STAGE_MARK(4);
     HIP_TRY(launch_probe(0, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, L.large_slice, L.large_cap,
-                         L.large_hc, L.large_blocks, cu * 8, cu * 2, counters, s));
+                         L.large_hc, L.large_blocks, cu * 8, cu * 2, counters, kev, s));
     STAGE_MARK(5);
     if (o.tri) {
         hipLaunchKernelGGL(k_tri_to_input, dim3(cu * 8), dim3(nthr), 0, s, n, rp, col, perm, g, t, o.tri);
@@ -517,11 +523,11 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     HIP_TRY(launch_sums(g, t, acc, cu * 8, s));
     STAGE_MARK(6);
     HIP_TRY(launch_probe(1, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, L.large_slice, L.large_cap,
-                         L.large_hc, L.large_blocks, cu * 8, cu * 2, nullptr, s));
+                         L.large_hc, L.large_blocks, cu * 8, cu * 2, nullptr, nokev, s));
     STAGE_MARK(7);
     if (n - h0 > 0) HIP_TRY(fill32(qpart, (i64)sizeof(i64) * L.part_rows * (n - h0), 0u, s));
     HIP_TRY(launch_q(g, lh, dst, acc.Q, gscratch, L.gslice, L.gblocks, cu * 4, cu * 4, cu * 2, qpart, L.part_rows,
-                     s));
+                     kev, s));
     STAGE_MARK(8);
     // ---- Stage III-b: equations ----
     HIP_TRY(launch_solve(g, acc, o.psi, o.fvars, dst, cu * 8, s));
@@ -532,6 +538,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
         HIP_TRY(hipGetLastError());
     }
     ctx->last = hs;
+    ctx->last_stats_dev = L.st;
     ctx->last_n = n;
     ctx->last_counters = counters ? L.counters : 0;
     ctx->last_feat = feat ? L.feat : 0;
@@ -840,6 +847,32 @@ extern "C" niorca_status niorca_stage_times(niorca_ctx *ctx, float *ms, int32_t 
     if (!ctx->ev_valid) return fail(ctx, NIORCA_EINVAL, "the last call did not record stage times");
     HIP_TRY(hipEventSynchronize(ctx->ev[NIORCA_NUM_STAGES]));
     for (int i = 0; i < NIORCA_NUM_STAGES; i++) HIP_TRY(hipEventElapsedTime(&ms[i], ctx->ev[i], ctx->ev[i + 1]));
+    return NIORCA_OK;
+}
+
+extern "C" niorca_status niorca_kernel_times(niorca_ctx *ctx, float *ms, int32_t count) {
+    if (!ctx || !ms || count < NIORCA_NUM_KERNEL_TIMES)
+        return fail(ctx, NIORCA_EINVAL, "need %d floats", NIORCA_NUM_KERNEL_TIMES);
+    if (!ctx->ev_valid) return fail(ctx, NIORCA_EINVAL, "the last call did not record kernel times");
+    HIP_TRY(hipEventSynchronize(ctx->ev[NIORCA_NUM_STAGES]));
+    // events 0..4 bracket the Stage I/II launches, 5..12 the 4-cycle launches
+    static const int first[NIORCA_NUM_KERNEL_TIMES] = {0, 1, 2, 3, 5, 6, 7, 8, 9, 10, 11};
+    for (int i = 0; i < NIORCA_NUM_KERNEL_TIMES; i++)
+        HIP_TRY(hipEventElapsedTime(&ms[i], ctx->kev[first[i]], ctx->kev[first[i] + 1]));
+    return NIORCA_OK;
+}
+
+extern "C" niorca_status niorca_class_stats(niorca_ctx *ctx, int64_t *out, int32_t count) {
+    if (!ctx || !out || count < 3 * WC_COUNT) return fail(ctx, NIORCA_EINVAL, "need %d int64", 3 * WC_COUNT);
+    if (ctx->last_n < 0 || ctx->last_ws != ctx->ws) return fail(ctx, NIORCA_EINVAL, "no count to report on");
+    GraphStats hs;
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(&hs, ctx->ws + ctx->last_stats_dev, sizeof hs, hipMemcpyDeviceToHost));
+    for (int c = 0; c < WC_COUNT; c++) {
+        out[c] = hs.cnt[c];
+        out[WC_COUNT + c] = hs.work[c];
+        out[2 * WC_COUNT + c] = hs.slots[c];
+    }
     return NIORCA_OK;
 }
 

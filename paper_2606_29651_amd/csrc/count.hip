@@ -76,18 +76,25 @@ __device__ __forceinline__ void item_scan(i32 *a, int len, int tid, i32 *red32) 
 // ---------------------------------------------------------------------------
 // Classification into work lists (wave-aggregated appends).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void list_push(bool take, int c, i32 y, const ListPtrs &lists, GraphStats *st) {
+__device__ __forceinline__ void list_push(bool take, int c, i32 y, const ListPtrs &lists, GraphStats *st, i64 work,
+                                          i64 slots) {
     u64 m = __ballot(take);
     if (!m) return;
     int leader = __ffsll((long long)m) - 1;
     i32 base = 0;
-    if (lane_id() == leader) base = atomicAdd(&st->cnt[c], __popcll(m));
+    i64 w = wave_sum64(take ? work : 0), sl = wave_sum64(take ? slots : 0);
+    if (lane_id() == leader) {
+        base = atomicAdd(&st->cnt[c], __popcll(m));
+        atomicAdd((unsigned long long *)&st->work[c], (unsigned long long)w);
+        atomicAdd((unsigned long long *)&st->slots[c], (unsigned long long)sl);
+    }
     base = __shfl(base, leader, WAVE);
     if (take) lists.l[c][base + __popcll(m & lanemask_lt())] = y;
 }
 
 __global__ void k_classify(DevGraph g, const i64 *__restrict__ wlight, const i64 *__restrict__ wheavy,
-                           ListPtrs lists, GraphStats *__restrict__ st, Thresholds th) {
+                           const i64 *__restrict__ probes, ListPtrs lists, GraphStats *__restrict__ st,
+                           Thresholds th) {
     i32 idx = blockIdx.x * blockDim.x + threadIdx.x;
     i32 y = g.n - 1 - idx;  // hubs first
     bool valid = y >= 0;
@@ -101,6 +108,7 @@ __global__ void k_classify(DevGraph g, const i64 *__restrict__ wlight, const i64
         wl = wlight[y];
         wh = wheavy[y];
     }
+    const i64 pr = valid ? probes[y] : 0;
     // Stage I/II items: capacity decides first (|N+| sizes the LDS structures); items
     // that fit a wave may move to one lane or to a whole workgroup by predicted work
     int tc = -1;
@@ -119,16 +127,16 @@ __global__ void k_classify(DevGraph g, const i64 *__restrict__ wlight, const i64
             }
         }
     }
-    list_push(tc == WC_TRI_THREAD, WC_TRI_THREAD, y, lists, st);
-    list_push(tc == WC_TRI_WAVE, WC_TRI_WAVE, y, lists, st);
-    list_push(tc == WC_TRI_BLOCK, WC_TRI_BLOCK, y, lists, st);
-    list_push(tc == WC_TRI_LARGE, WC_TRI_LARGE, y, lists, st);
+    list_push(tc == WC_TRI_THREAD, WC_TRI_THREAD, y, lists, st, pr, du);
+    list_push(tc == WC_TRI_WAVE, WC_TRI_WAVE, y, lists, st, pr, du);
+    list_push(tc == WC_TRI_BLOCK, WC_TRI_BLOCK, y, lists, st, pr, du);
+    list_push(tc == WC_TRI_LARGE, WC_TRI_LARGE, y, lists, st, pr, du);
     bool qlw = valid && wl > 0 && wl <= th.ql_wave;
     bool qlb = valid && wl > th.ql_wave && wl <= th.ql_block;
     bool qlg = valid && wl > th.ql_block;
-    list_push(qlw, WC_QL_WAVE, y, lists, st);
-    list_push(qlb, WC_QL_BLOCK, y, lists, st);
-    list_push(qlg, WC_QL_GLOBAL, y, lists, st);
+    list_push(qlw, WC_QL_WAVE, y, lists, st, wl, dm);
+    list_push(qlb, WC_QL_BLOCK, y, lists, st, wl, dm);
+    list_push(qlg, WC_QL_GLOBAL, y, lists, st, wl, dm);
     // packed 17-bit and dense 16-bit counters need every count below 2^16; a count
     // is at most d(x), so vertices of degree >= 2^16 use int32 global counters
     bool small_d = d < 65536;
@@ -136,11 +144,10 @@ __global__ void k_classify(DevGraph g, const i64 *__restrict__ wlight, const i64
     bool qhb = valid && small_d && wh > th.qh_wave && wh <= th.qh_block;
     bool qhd = valid && small_d && wh > th.qh_block;
     bool qhg = valid && !small_d && wh > 0;
-    list_push(qhw, WC_QH_WAVE, y, lists, st);
-    list_push(qhb, WC_QH_BLOCK, y, lists, st);
-    list_push(qhd, WC_QH_DENSE, y, lists, st);
-    list_push(qhg, WC_QH_GLOBAL, y, lists, st);
-    (void)dm;
+    list_push(qhw, WC_QH_WAVE, y, lists, st, wh, d);
+    list_push(qhb, WC_QH_BLOCK, y, lists, st, wh, d);
+    list_push(qhd, WC_QH_DENSE, y, lists, st, wh, d);
+    list_push(qhg, WC_QH_GLOBAL, y, lists, st, wh, d);
 }
 
 // ---------------------------------------------------------------------------
@@ -1104,30 +1111,37 @@ __global__ void __launch_bounds__(QG_NT) k_q_global(DevGraph g, const i32 *__res
 // ---------------------------------------------------------------------------
 // Host-side launch helpers (called from the API file).
 // ---------------------------------------------------------------------------
-hipError_t launch_classify(const DevGraph &g, const i64 *wl, const i64 *wh, const ListPtrs &lists, GraphStats *st,
-                           const Thresholds &th, hipStream_t s) {
+hipError_t launch_classify(const DevGraph &g, const i64 *wl, const i64 *wh, const i64 *probes, const ListPtrs &lists,
+                           GraphStats *st, const Thresholds &th, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_classify, dim3((g.n + 255) / 256), dim3(256), 0, s, g, wl, wh, lists, st, th);
+    hipLaunchKernelGGL(k_classify, dim3((g.n + 255) / 256), dim3(256), 0, s, g, wl, wh, probes, lists, st, th);
     return hipGetLastError();
 }
 
 hipError_t launch_probe(int mode, const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i32 *t,
                         i64 *K4, i64 *tau, const TriCacheArgs &tca, char *large_scratch, i64 large_slice,
                         int large_cap, int large_hc, int large_blocks, int grid_wave, int grid_block,
-                        i64 *counters, hipStream_t s) {
+                        i64 *counters, const KernelEvents &kev, hipStream_t s) {
+#define KMARK(i) \
+    if (kev.ev) (void)hipEventRecord(kev.ev[i], s)
     TriCache tw{tca.rec, tca.cap, tca.bump, tca.off, tca.cnt, tca.chunk_wave};
     TriCache tb{tca.rec, tca.cap, tca.bump, tca.off, tca.cnt, tca.chunk_block};
     if (mode == PROBE_TRI) {
+        KMARK(0);
         hipLaunchKernelGGL(k_probe_thread<PROBE_TRI>, dim3(grid_wave), dim3(256), 0, s, g,
                            lists_host[WC_TRI_THREAD], st, t, K4, tau, tw, counters);
+        KMARK(1);
         hipLaunchKernelGGL(k_probe_wave<PROBE_TRI>, dim3(grid_wave), dim3(256), 0, s, g, lists_host[WC_TRI_WAVE], st,
                            t, K4, tau, tw, counters);
+        KMARK(2);
         hipLaunchKernelGGL(k_probe_block<PROBE_TRI>, dim3(grid_block), dim3(PB_NT), 0, s, g,
                            lists_host[WC_TRI_BLOCK], st, t, K4, tau, tb, counters);
+        KMARK(3);
         if (large_blocks > 0)
             hipLaunchKernelGGL(k_probe_large<PROBE_TRI>, dim3(large_blocks), dim3(256), 0, s, g,
                                lists_host[WC_TRI_LARGE], st, t, K4, tau, tb, large_scratch, large_slice, large_cap,
                                large_hc, counters);
+        KMARK(4);
     } else {
         hipLaunchKernelGGL(k_probe_thread<PROBE_TAU>, dim3(grid_wave), dim3(256), 0, s, g,
                            lists_host[WC_TRI_THREAD], st, t, K4, tau, tw, (i64 *)nullptr);
@@ -1158,14 +1172,18 @@ hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvar
 
 hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i64 *Q, i32 *gscratch,
                     i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, i64 *part, int part_rows,
-                    hipStream_t s) {
+                    const KernelEvents &kev, hipStream_t s) {
+    KMARK(5);
     hipLaunchKernelGGL(k_q_wave<Q_LIGHT>, dim3(grid_wave), dim3(256), 0, s, g, lists_host[WC_QL_WAVE], st,
                        (int)WC_QL_WAVE, Q);
+    KMARK(6);
     hipLaunchKernelGGL(k_q_block<Q_LIGHT>, dim3(grid_block), dim3(256), 0, s, g, lists_host[WC_QL_BLOCK], st,
                        (int)WC_QL_BLOCK, Q);
+    KMARK(7);
     if (gblocks > 0)
         hipLaunchKernelGGL(k_q_global<Q_LIGHT>, dim3(gblocks), dim3(QG_NT), 0, s, g, lists_host[WC_QL_GLOBAL], st,
                            (int)WC_QL_GLOBAL, Q, gscratch, gslice);
+    KMARK(8);
     const i32 K = g.n - g.h0;
     if (K > 0) {
         // rows of `part` are per workgroup: each kernel's grid stays within part_rows
@@ -1173,12 +1191,20 @@ hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats 
         int gb = grid_block < part_rows ? grid_block : part_rows;
         int gd = grid_dense < part_rows ? grid_dense : part_rows;
         hipLaunchKernelGGL(k_qh_wave, dim3(gw), dim3(256), 0, s, g, lists_host[WC_QH_WAVE], st, Q, part, K);
+        KMARK(9);
         hipLaunchKernelGGL(k_qh_block, dim3(gb), dim3(QHB_NT), 0, s, g, lists_host[WC_QH_BLOCK], st, Q, part, K);
+        KMARK(10);
         hipLaunchKernelGGL(k_q_dense, dim3(gd), dim3(QD_NT), 0, s, g, lists_host[WC_QH_DENSE], st, Q, part, K);
+        KMARK(11);
         hipLaunchKernelGGL(k_qh_reduce, dim3((K + 255) / 256), dim3(256), 0, s, part, part_rows, K, g.h0, Q);
+    } else {
+        KMARK(9);
+        KMARK(10);
+        KMARK(11);
     }
     if (gblocks > 0)
         hipLaunchKernelGGL(k_q_global<Q_HEAVY>, dim3(gblocks), dim3(QG_NT), 0, s, g, lists_host[WC_QH_GLOBAL], st,
                            (int)WC_QH_GLOBAL, Q, gscratch, gslice);
+    KMARK(12);
     return hipGetLastError();
 }

@@ -17,7 +17,18 @@ struct GraphStats {
     int pad2[3];
     // work-class list sizes (filled by the classification kernel)
     int cnt[16];
+    // per class: work units (Stage I probes or 4-cycle wedges) and row slots handled
+    long long work[16];
+    long long slots[16];
 };
+
+// Optional HIP events around each kernel launch of the probe and 4-cycle stages
+// (NIORCA_TIMING): ev[k] before launch k, ev[k+1] after it.
+struct KernelEvents {
+    hipEvent_t *ev;   // nullptr: no events
+};
+#define NUM_KERNEL_SLOTS 13  // probe: thread, wave, block, large; q: ql wave, ql block,
+                             // ql global, qh wave, qh block, qh dense, qh global, reduce
 
 // Classes of work items (indices into GraphStats::cnt and the list table).
 enum WorkClass {
@@ -116,8 +127,8 @@ __global__ void k_mirror(i32 n, const i32 *nrp, const i32 *nsplit, const i32 *nc
 #define LSORT_CAP 16384
 
 // count.hip
-hipError_t launch_classify(const DevGraph &g, const i64 *wl, const i64 *wh, const ListPtrs &lists, GraphStats *st,
-                           const Thresholds &th, hipStream_t s);
+hipError_t launch_classify(const DevGraph &g, const i64 *wl, const i64 *wh, const i64 *probes, const ListPtrs &lists,
+                           GraphStats *st, const Thresholds &th, hipStream_t s);
 struct TriCacheArgs {
     u64 *rec;
     i64 cap;
@@ -129,7 +140,7 @@ struct TriCacheArgs {
 hipError_t launch_probe(int mode, const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i32 *t,
                         i64 *K4, i64 *tau, const TriCacheArgs &tca, char *large_scratch, i64 large_slice,
                         int large_cap, int large_hc, int large_blocks, int grid_wave, int grid_block,
-                        i64 *counters, hipStream_t s);
+                        i64 *counters, const KernelEvents &kev, hipStream_t s);
 
 // mlp.hip
 int mlp_num_trained();
@@ -148,5 +159,5 @@ hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvar
                         hipStream_t s);
 hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i64 *Q, i32 *gscratch,
                     i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, i64 *part, int part_rows,
-                    hipStream_t s);
+                    const KernelEvents &kev, hipStream_t s);
 i64 probe_large_slice_bytes(int cap, int hc);
