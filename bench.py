@@ -206,6 +206,22 @@ def forms(args, ni, ctx, g, rp, cl, out, base_ms):
     return res
 
 
+def copy_calibration(mib):
+    """A copy kernel of known traffic: 4 B read and 4 B written per element."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.arange(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty(n, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / 5
+    print(json.dumps({"copy_calibration": {"elements": n, "read_bytes": 4 * n, "write_bytes": 4 * n,
+                                           "ms": ms, "GBps": 8 * n / (ms * 1e-3) / 1e9}}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +233,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="all", choices=["all", "none"])
     ap.add_argument("--batch-graphs", type=int, default=50000)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain int32->float32 copy of MIB MiB five times (reads and writes "
+                         "MIB MiB each), to scale HBM byte counters taken under rocprofv3 --pmc")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
@@ -224,6 +243,9 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     import graphgen as gg
     import paper_2606_29651_amd as ni
 

@@ -82,15 +82,21 @@ uint64_t niorca_workspace_bytes(const niorca_ctx *ctx);
  *   "tri_block" 1..512   ... up to this one workgroup with LDS; above, global scratch
  *   "ql_wave"   0..256   4-cycle wedges (largest vertex light) up to this: wave hash
  *   "ql_block"  0..4096  ... up to this: workgroup hash; above: global counters
- *   "qh_wave"   0..256   4-cycle wedges opposite a heavy largest vertex: wave hash
+ *   "qh_wave"   0..2048  4-cycle wedges opposite a heavy largest vertex: wave hash
+ *                        (default 1024; the per-wave table is sized from it)
  *   "qh_block"  0..4096  ... workgroup hash; above: dense LDS counters
  *   "heavy_k"   0..32768 how many top-ranked vertices form the heavy range
  *   "bin_deg_thread" (NIORCA_BIN_DEGREE) degree up to which a vertex with |N+| <= 8
  *               goes to the one-lane Stage I class (default 16)
  *   "bin_deg_block"  (NIORCA_BIN_DEGREE) degree from which a vertex goes to the
  *               workgroup Stage I class (default 4096)
- *   "tri_cache" 0..2^34  triangles kept from Stage I for the tau pass (8 bytes each;
- *                        vertices whose triangles do not fit are probed again)
+ *   "tri_cache" 0..2^34  most triangles kept from Stage I for the tau pass (8 bytes
+ *                        each, default 2^32; a call reserves no more than the sum over
+ *                        vertices of C(|N+|, 2); vertices whose triangles do not fit
+ *                        are probed again)
+ *   "large_lds" 0..147456 LDS bytes the |N+| > tri_block class may use for its hash
+ *                        and per-slot arrays (default 147456; beyond it they live in
+ *                        global scratch)
  * Returns EINVAL for an unknown name or a value out of range. */
 niorca_status niorca_set_param(niorca_ctx *ctx, const char *name, int64_t value);
 

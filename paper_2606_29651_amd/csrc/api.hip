@@ -34,7 +34,7 @@ struct niorca_ctx {
     bool ev_valid = false;
     // tunable class thresholds and the size of the heavy 4-cycle key range
     Thresholds th{TRI_WAVE_CAP, TRI_BLOCK_CAP, 0, 16, 4096, 0.f, 0.f, nullptr,
-                  QL_WAVE_HC / 2, QL_BLOCK_HC / 2, QH_WAVE_HC / 2, QH_BLOCK_HC / 2};
+                  QL_WAVE_HC / 2, QL_BLOCK_HC / 2, 1024, QH_BLOCK_HC / 2};
     int32_t heavy_k = QH_DENSE_K;
     // the last captured batched sequence and the shape it was captured for
     hipGraphExec_t gexec = nullptr;
@@ -42,7 +42,8 @@ struct niorca_ctx {
     // the region of global 4-cycle counters last cleared (kernels leave it zero)
     char *gz_ws = nullptr;
     uint64_t gz_off = 0, gz_bytes = 0;
-    int64_t tri_cache_records = (int64_t)1 << 29;  // 4 GiB of kept triangles for the tau pass
+    int64_t tri_cache_records = (int64_t)1 << 32;  // at most 32 GiB of kept triangles for the tau pass
+    int64_t large_lds_max = PL_LDS_MAX;            // LDS bytes the large probe kernel may take
 };
 
 static niorca_status fail(niorca_ctx *c, niorca_status s, const char *fmt, ...) {
@@ -169,6 +170,9 @@ extern "C" niorca_status niorca_set_param(niorca_ctx *ctx, const char *name, int
     } else if (k == "qh_wave") {
         if (value < 0 || value > QH_WAVE_HC / 2) return bad(0, QH_WAVE_HC / 2);
         ctx->th.qh_wave = value;
+    } else if (k == "large_lds") {
+        if (value < 0 || value > PL_LDS_MAX) return bad(0, PL_LDS_MAX);
+        ctx->large_lds_max = value;
     } else if (k == "qh_block") {
         if (value < 0 || value > QH_BLOCK_HC / 2) return bad(0, QH_BLOCK_HC / 2);
         ctx->th.qh_block = value;
@@ -273,6 +277,10 @@ struct Outputs {
 
 // Bounds the host already knows (batched calls): with them the pipeline needs no
 // wait on the device, so the whole sequence can be captured into a hipGraph.
+// Triangle records kept in batched (bounded) runs, whose triangle bound is unknown
+// to the host: 4 GiB.
+#define BOUNDED_TRI_CACHE ((i64)1 << 29)
+
 struct HostBounds {
     int dmax;       // maximum degree
     int dplus_max;  // maximum |N+|
@@ -319,8 +327,6 @@ static void layout_base(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz
     for (int c = 0; c < WC_COUNT; c++) L.lists[c] = A.take<i32>(n);
     L.acc = A.take<i64>((uint64_t)n * 10);
     L.tcoff = A.take<i64>(n); L.tccnt = A.take<i32>(n); L.tcbump = A.take<u64>(1);
-    L.tc_cap = ctx->tri_cache_records;
-    L.tcrec = A.take<u64>((uint64_t)(L.tc_cap > 0 ? L.tc_cap : 1));
     L.probes = A.take<i64>(n);
     const bool feats = (flags & (NIORCA_BIN_MLP | NIORCA_COUNTERS)) != 0;
     L.feat = feats ? A.take<float>((uint64_t)n * 6) : 0;
@@ -329,15 +335,19 @@ static void layout_base(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz
     L.base_end = A.off;
 }
 
-static void layout_rest(Layout &L, const niorca_ctx *ctx, int32_t n, int dplus_max, bool bounded, Arena &A) {
+static void layout_rest(Layout &L, const niorca_ctx *ctx, int32_t n, int dplus_max, i64 pairs, bool bounded,
+                        Arena &A) {
     const int cu = ctx->num_cu;
+    // triangle records for the tau pass: no more than the graph can have
+    L.tc_cap = ctx->tri_cache_records < pairs ? ctx->tri_cache_records : pairs;
+    L.tcrec = A.take<u64>((uint64_t)(L.tc_cap > 0 ? L.tc_cap : 1));
     L.h0 = n > ctx->heavy_k ? n - ctx->heavy_k : 0;
     // vertices with |N+| above the workgroup threshold go to the global-scratch class
     L.large_cap = dplus_max > ctx->th.tri_block ? dplus_max : 0;
     L.large_hc = 1;
     while (L.large_hc < 2 * L.large_cap) L.large_hc <<= 1;
     L.large_blocks = L.large_cap ? 2 * cu : 0;
-    L.large_slice = L.large_cap ? probe_large_slice_bytes(L.large_cap, L.large_hc) : 0;
+    L.large_slice = L.large_cap ? probe_large_slice_bytes(L.large_cap, L.large_hc, ctx->large_lds_max) : 0;
     L.large = A.take<char>((uint64_t)L.large_slice * L.large_blocks);
     L.part_rows = QH_PART_ROWS;
     L.part = A.take<i64>((uint64_t)L.part_rows * (uint64_t)(n - L.h0));
@@ -382,7 +392,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     Layout L;
     Arena A;
     layout_base(L, ctx, n, nnz, flags, A);
-    if (hb) layout_rest(L, ctx, n, hb->dplus_max, true, A);
+    if (hb) layout_rest(L, ctx, n, hb->dplus_max, BOUNDED_TRI_CACHE, true, A);
     const uint64_t need_now = hb ? A.off : L.base_end;
 
     // Validation first (it reads only the input).
@@ -444,7 +454,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
             return fail(ctx, NIORCA_EOVERFLOW, "maximum degree %d could overflow int64 counts", hs.dmax);
         if (hs.dplus_max > LSORT_CAP)
             return fail(ctx, NIORCA_ENOTIMPL, "an oriented out-degree of %d exceeds %d", hs.dplus_max, LSORT_CAP);
-        layout_rest(L, ctx, n, hs.dplus_max, false, A);
+        layout_rest(L, ctx, n, hs.dplus_max, hs.pairs, false, A);
         niorca_status st = ensure_ws(ctx, A.off);
         if (st) return st;
         // The workspace grew and moved: start again; this time it is large enough.
@@ -507,7 +517,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     HIP_TRY(fill32(tca.bump, sizeof(u64), 0u, s));
     STAGE_MARK(4);
     HIP_TRY(launch_probe(0, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, L.large_slice, L.large_cap,
-                         L.large_hc, L.large_blocks, cu * 8, cu * 2, counters, kev, s));
+                         L.large_hc, L.large_blocks, ctx->large_lds_max, cu * 8, cu * 2, counters, kev, s));
     STAGE_MARK(5);
     if (o.tri) {
         hipLaunchKernelGGL(k_tri_to_input, dim3(cu * 8), dim3(nthr), 0, s, n, rp, col, perm, g, t, o.tri);
@@ -523,11 +533,11 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     HIP_TRY(launch_sums(g, t, acc, cu * 8, s));
     STAGE_MARK(6);
     HIP_TRY(launch_probe(1, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, L.large_slice, L.large_cap,
-                         L.large_hc, L.large_blocks, cu * 8, cu * 2, nullptr, nokev, s));
+                         L.large_hc, L.large_blocks, ctx->large_lds_max, cu * 8, cu * 2, nullptr, nokev, s));
     STAGE_MARK(7);
     if (n - h0 > 0) HIP_TRY(fill32(qpart, (i64)sizeof(i64) * L.part_rows * (n - h0), 0u, s));
     HIP_TRY(launch_q(g, lh, dst, acc.Q, gscratch, L.gslice, L.gblocks, cu * 4, cu * 4, cu * 2, qpart, L.part_rows,
-                     kev, s));
+                     th.qh_wave, kev, s));
     STAGE_MARK(8);
     // ---- Stage III-b: equations ----
     HIP_TRY(launch_solve(g, acc, o.psi, o.fvars, dst, cu * 8, s));
@@ -658,7 +668,7 @@ extern "C" niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graph
     Layout L;
     Arena A;
     layout_base(L, ctx, n, nnz, flags, A);
-    layout_rest(L, ctx, n, hb.dplus_max, true, A);
+    layout_rest(L, ctx, n, hb.dplus_max, BOUNDED_TRI_CACHE, true, A);
     L.colg = A.take<int32_t>(nnz + 64);
     L.voff = A.take<int64_t>(num_graphs + 1);
     st = ensure_ws(ctx, A.off);

@@ -17,14 +17,38 @@ __device__ __forceinline__ u64 lanemask_lt() {
     return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
-// Wave-wide inclusive sum (int32), all 64 lanes participate.
+// Wave-wide inclusive sum (int32), all 64 lanes active.  DPP row shifts build
+// the prefix inside each 16-lane row; row broadcasts of lanes 15 and 31 carry it
+// across rows (no LDS traffic).
 __device__ __forceinline__ int wave_incl_sum(int v) {
-#pragma unroll
-    for (int o = 1; o < WAVE; o <<= 1) {
-        int t = __shfl_up(v, o, WAVE);
-        if (lane_id() >= o) v += t;
-    }
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
     return v;
+}
+
+// Adds, for every run of consecutive lanes holding the same index si, the run's
+// total of val to dst[si] with one atomic (issued by the run's last lane).  All 64
+// lanes active; lanes with nothing to add pass val = 0.  Values of 2^24 or more are
+// added on their own, so that the 32-bit run sums cannot overflow.
+__device__ __forceinline__ void wave_run_add(i64 *dst, int si, int val) {
+    const int lane = lane_id();
+    if (val >= (1 << 24)) {
+        atomicAdd((unsigned long long *)&dst[si], (unsigned long long)(i64)val);
+        val = 0;
+    }
+    const int incl = wave_incl_sum(val);
+    const int prev = __shfl_up(si, 1, WAVE);
+    const u64 starts = __ballot(lane == 0 || prev != si);
+    const bool last = lane == WAVE - 1 || ((starts >> (lane + 1)) & 1ull);
+    const u64 upto = lane == WAVE - 1 ? starts : (starts & ((2ull << lane) - 1ull));
+    const int head = 63 - __clzll((long long)upto);
+    const int before = __shfl(incl, head > 0 ? head - 1 : 0, WAVE);
+    const int tot = incl - (head > 0 ? before : 0);
+    if (last && tot) atomicAdd((unsigned long long *)&dst[si], (unsigned long long)(i64)tot);
 }
 
 __device__ __forceinline__ i64 wave_sum64(i64 v) {

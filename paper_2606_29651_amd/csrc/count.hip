@@ -153,15 +153,37 @@ __global__ void k_classify(DevGraph g, const i64 *__restrict__ wlight, const i64
 // ---------------------------------------------------------------------------
 // Stage I / Stage II / tau probe kernels.
 // ---------------------------------------------------------------------------
+// Largest i in [0, len) with off[i] <= e, for the QK elements e = e0 + j*NT (j < nj)
+// of one thread, searched together (power-of-two steps, independent LDS reads in
+// flight).  off is non-decreasing with off[0] = 0 <= e.
+template <int NT, int QK>
+__device__ __forceinline__ void q_locate(const i32 *off, int len, i32 e0, int nj, int *lo) {
+#pragma unroll
+    for (int j = 0; j < QK; j++) lo[j] = 0;
+    int step = 1;
+    while (2 * step < len) step <<= 1;
+    for (; step > 0; step >>= 1) {
+#pragma unroll
+        for (int j = 0; j < QK; j++) {
+            if (j < nj) {
+                const i32 e = e0 + j * NT;
+                const int m = lo[j] + step;
+                if (m < len && off[m] <= e) lo[j] = m;
+            }
+        }
+    }
+}
+
 enum { PROBE_TRI = 0, PROBE_TAU = 1 };
 
-#define QU 4  // elements per thread per step in the flattened loops
+#define QS 8  // wedges per thread per step in the 4-cycle sweeps
 
 struct ProbeMem {
     i32 *hkey;   // [hc]
     i32 *hpos;   // [hc]
     i32 *off;    // [cap+1]
     i32 *nb;     // [cap]
+    i32 *beg;    // [cap]: first slot of N+(nb[i])
     i32 *tcnt;   // [cap]
     u32 *A;      // [cap*words]
     i64 *acc;    // [cap]
@@ -186,7 +208,7 @@ struct ItemState {  // per item group, in LDS
     i32 item_ok, item_cnt;
 };
 
-template <int NT, int MODE>
+template <int NT, int MODE, int QP>
 __device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, const ProbeMem &M, int hc,
                                            int words, i32 *__restrict__ t, i64 *__restrict__ K4,
                                            i64 *__restrict__ tau, i64 *red, i32 *red32, const TriCache &tc,
@@ -228,8 +250,10 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, co
     item_sync<NT>();
     for (int i = tid; i < du; i += NT) {
         i32 v = g.ncol[base + i];
+        const i32 b = g.nsplit[v];
         M.nb[i] = v;
-        M.off[i + 1] = g.nrp[v + 1] - g.nsplit[v];
+        M.beg[i] = b;
+        M.off[i + 1] = g.nrp[v + 1] - b;
         u32 sl = hslot((u32)v, hmask);
         while (atomicCAS(&M.hkey[sl], -1, v) != -1) sl = (sl + 1) & hmask;
         M.hpos[sl] = i;
@@ -267,24 +291,25 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, co
     const bool keep = MODE == PROBE_TRI && S->item_ok;
     const i64 item_base = keep ? S->item_base : 0;
     i64 tau_local = 0;
-    for (i32 eb = tid; eb < total; eb += NT * QU) {
-        int si[QU];
-        i32 qq[QU], ww[QU];
-        bool ok[QU];
+    // rounds of NT*QP probes: each thread locates its QP probes together, then
+    // issues all their loads before the first hash lookup
+    for (i32 eb = 0; eb < total; eb += NT * QP) {
+        const int nj = min(QP, (total - eb + NT - 1) / NT);
+        int lo[QP];
+        i32 qq[QP], ww[QP];
+        q_locate<NT, QP>(M.off, du, eb + tid, nj, lo);
 #pragma unroll
-        for (int u = 0; u < QU; u++) {
-            i32 e = eb + u * NT;
-            ok[u] = e < total;
-            si[u] = ok[u] ? upper_index<i32>(M.off, 0, du, e) : 0;
-            qq[u] = ok[u] ? g.nsplit[M.nb[si[u]]] + (e - M.off[si[u]]) : 0;
+        for (int j = 0; j < QP; j++) {
+            const i32 e = eb + tid + j * NT;
+            qq[j] = (j < nj && e < total) ? M.beg[lo[j]] + (e - M.off[lo[j]]) : -1;
         }
 #pragma unroll
-        for (int u = 0; u < QU; u++) ww[u] = ok[u] ? g.ncol[qq[u]] : -1;
+        for (int j = 0; j < QP; j++) ww[j] = qq[j] >= 0 ? g.ncol[qq[j]] : -1;
 #pragma unroll
-        for (int u = 0; u < QU; u++) {
-            if (!ok[u]) continue;
-            const int i = si[u];
-            const i32 q = qq[u], w = ww[u];
+        for (int j = 0; j < QP; j++) {
+            if (ww[j] < 0) continue;
+            const int i = lo[j];
+            const i32 q = qq[j], w = ww[j];
             u32 sl = hslot((u32)w, hmask);
             int p = -1;
             while (true) {
@@ -366,6 +391,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, co
 }
 
 // One wave per vertex, |N+(u)| <= 64, four items per 256-thread block.
+#define PW_QP 8
 template <int MODE>
 __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__restrict__ list,
                                                     const GraphStats *__restrict__ st, i32 *t, i64 *K4,
@@ -375,18 +401,20 @@ __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__res
     __shared__ i32 s_hpos[4][HC];
     __shared__ i32 s_off[4][CAP + 1];
     __shared__ i32 s_nb[4][CAP];
+    __shared__ i32 s_beg[4][CAP];
     __shared__ i32 s_tcnt[4][CAP];
     __shared__ u32 s_A[4][CAP * WORDS];
     __shared__ i64 s_acc[4][CAP];
     __shared__ ItemState s_st[4];
     const int w = threadIdx.x / WAVE, tid = lane_id();
-    ProbeMem M{s_hkey[w], s_hpos[w], s_off[w], s_nb[w], s_tcnt[w], s_A[w], s_acc[w]};
+    ProbeMem M{s_hkey[w], s_hpos[w], s_off[w], s_nb[w], s_beg[w], s_tcnt[w], s_A[w], s_acc[w]};
     if (tid == 0) s_st[w].chunk_cur = s_st[w].chunk_end = 0;
     item_sync<WAVE>();
     const i32 cnt = st->cnt[WC_TRI_WAVE];
     const int waves = gridDim.x * 4;
     for (i32 it = blockIdx.x * 4 + w; it < cnt; it += waves)
-        probe_item<WAVE, MODE>(g, list[it], tid, M, HC, WORDS, t, K4, tau, nullptr, nullptr, tc, &s_st[w], counters);
+        probe_item<WAVE, MODE, PW_QP>(g, list[it], tid, M, HC, WORDS, t, K4, tau, nullptr, nullptr, tc, &s_st[w],
+                                      counters);
 }
 
 // One 256-thread workgroup per vertex, 64 < |N+(u)| <= TRI_BLOCK_CAP.
@@ -400,18 +428,19 @@ __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__
     __shared__ i32 s_hpos[HC];
     __shared__ i32 s_off[CAP + 1];
     __shared__ i32 s_nb[CAP];
+    __shared__ i32 s_beg[CAP];
     __shared__ i32 s_tcnt[CAP];
     __shared__ u32 s_A[CAP * WORDS];
     __shared__ i64 s_acc[CAP];
     __shared__ i64 s_red[PB_NT / WAVE];
     __shared__ i32 s_red32[PB_NT / WAVE];
     __shared__ ItemState s_st;
-    ProbeMem M{s_hkey, s_hpos, s_off, s_nb, s_tcnt, s_A, s_acc};
+    ProbeMem M{s_hkey, s_hpos, s_off, s_nb, s_beg, s_tcnt, s_A, s_acc};
     if (threadIdx.x == 0) s_st.chunk_cur = s_st.chunk_end = 0;
     __syncthreads();
     const i32 cnt = st->cnt[WC_TRI_BLOCK];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
-        probe_item<PB_NT, MODE>(g, list[it], threadIdx.x, M, HC, WORDS, t, K4, tau, s_red, s_red32, tc, &s_st,
+        probe_item<PB_NT, MODE, 4>(g, list[it], threadIdx.x, M, HC, WORDS, t, K4, tau, s_red, s_red32, tc, &s_st,
                                 counters);
 }
 
@@ -502,36 +531,47 @@ __global__ void __launch_bounds__(256) k_probe_thread(DevGraph g, const i32 *__r
     }
 }
 
-// |N+(u)| > TRI_BLOCK_CAP: the same item code on per-workgroup global scratch.
-template <int MODE>
+// |N+(u)| > TRI_BLOCK_CAP: the same item code with larger structures.  The hash of
+// N+(u) and the per-slot arrays live in dynamic LDS when they fit (LDSH), else in
+// the workgroup's global scratch slice; the bitset of H_u and the tau sums always
+// live in the slice.
+__host__ __device__ inline i64 probe_large_lds_bytes(int cap, int hc) {
+    return (i64)sizeof(i32) * (2 * (i64)hc + 4 * (i64)cap + 1);
+}
+
+template <int MODE, bool LDSH>
 __global__ void __launch_bounds__(256) k_probe_large(DevGraph g, const i32 *__restrict__ list,
                                                      const GraphStats *__restrict__ st, i32 *t, i64 *K4,
                                                      i64 *tau, TriCache tc, char *scratch, i64 slice_bytes,
                                                      int cap, int hc, i64 *counters) {
+    extern __shared__ __align__(16) char s_dyn[];
     __shared__ i64 s_red[4];
     __shared__ i32 s_red32[4];
     const int words = (cap + 31) / 32;
     char *p = scratch + (i64)blockIdx.x * slice_bytes;
     ProbeMem M;
     M.acc = (i64 *)p; p += sizeof(i64) * cap;
-    M.hkey = (i32 *)p; p += sizeof(i32) * hc;
-    M.hpos = (i32 *)p; p += sizeof(i32) * hc;
-    M.off = (i32 *)p; p += sizeof(i32) * (cap + 1);
-    M.nb = (i32 *)p; p += sizeof(i32) * cap;
-    M.tcnt = (i32 *)p; p += sizeof(i32) * cap;
-    M.A = (u32 *)p;
+    M.A = (u32 *)p; p += sizeof(u32) * (i64)cap * words;
+    char *q = LDSH ? s_dyn : p;
+    M.hkey = (i32 *)q; q += sizeof(i32) * hc;
+    M.hpos = (i32 *)q; q += sizeof(i32) * hc;
+    M.off = (i32 *)q; q += sizeof(i32) * (cap + 1);
+    M.nb = (i32 *)q; q += sizeof(i32) * cap;
+    M.beg = (i32 *)q; q += sizeof(i32) * cap;
+    M.tcnt = (i32 *)q;
     __shared__ ItemState s_st;
     if (threadIdx.x == 0) s_st.chunk_cur = s_st.chunk_end = 0;
     __syncthreads();
     const i32 cnt = st->cnt[WC_TRI_LARGE];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
-        probe_item<256, MODE>(g, list[it], threadIdx.x, M, hc, words, t, K4, tau, s_red, s_red32, tc, &s_st,
-                              counters);
+        probe_item<256, MODE, 4>(g, list[it], threadIdx.x, M, hc, words, t, K4, tau, s_red, s_red32, tc, &s_st,
+                                 counters);
 }
 
-i64 probe_large_slice_bytes(int cap, int hc) {
+i64 probe_large_slice_bytes(int cap, int hc, i64 lds_max) {
     int words = (cap + 31) / 32;
-    i64 b = sizeof(i64) * cap + sizeof(i32) * (2 * (i64)hc + 3 * (i64)cap + 1) + sizeof(u32) * (i64)cap * words;
+    i64 b = sizeof(i64) * cap + sizeof(u32) * (i64)cap * words;
+    if (probe_large_lds_bytes(cap, hc) > lds_max) b += probe_large_lds_bytes(cap, hc);
     return (b + 255) & ~255ll;
 }
 
@@ -754,15 +794,56 @@ struct GlobalCounter {
     __device__ i32 get(i32 k) const { return c[k]; }
 };
 
-// Both sweeps over the item's wedges, chunk by chunk.  Each thread takes QU wedges
-// per step (independent loads in flight); the segment of a wedge is found by a
-// binary search over the chunk's prefix offsets in LDS.
-template <int NT, int MODE, typename Ctr>
+// Both sweeps over the item's wedges, chunk by chunk.  Each thread takes QS wedges
+// per step (independent loads in flight); their segments are found together by a
+// search over the chunk's prefix offsets in LDS.  When the whole item is one
+// chunk of at most NT*QK wedges, every thread keeps its wedges' keys and segments in
+// registers: the keys are read from memory once, all loads of a thread in flight
+// together, and the second sweep needs neither loads nor searches.
+template <int NT, int MODE, int QK = 0, typename Ctr>
 __device__ __forceinline__ void q_sweeps(const DevGraph &g, i32 x, const Ctr &ctr, const QChunk &C, int dc,
                                          int tid, i32 *red32, i64 *__restrict__ Q) {
     const i32 s0 = g.nrp[x], sp = g.nsplit[x];
     const i32 ns = (MODE == Q_LIGHT) ? sp - s0 : g.nrp[x + 1] - s0;
     const bool single = ns <= dc;
+    if constexpr (QK > 0) {
+        if (single) {
+            const i32 total = q_load_chunk<NT, MODE>(g, x, s0, sp, 0, ns, C, tid, red32);
+            if (total <= NT * QK) {
+                const int nj = (total + NT - 1) / NT;
+                int lo[QK];
+                i32 key[QK];
+                q_locate<NT, QK>(C.off, ns, tid, nj, lo);
+#pragma unroll
+                for (int j = 0; j < QK; j++) {
+                    const i32 e = tid + j * NT;
+                    key[j] = (j < nj && e < total) ? C.beg[lo[j]] + (e - C.off[lo[j]]) : -1;
+                }
+#pragma unroll
+                for (int j = 0; j < QK; j++) key[j] = key[j] >= 0 ? g.ncol[key[j]] : -1;
+#pragma unroll
+                for (int j = 0; j < QK; j++)
+                    if (key[j] >= 0) ctr.inc(key[j]);
+                item_sync<NT>();
+                // second sweep: each wedge's middle gains c - 1, summed over runs of
+                // lanes in the same segment before the LDS atomic
+#pragma unroll
+                for (int j = 0; j < QK; j++) {
+                    if (j < nj) {
+                        const i32 c = key[j] >= 0 ? ctr.get(key[j]) : 0;
+                        wave_run_add(C.mid, lo[j], c > 1 ? c - 1 : 0);
+                    }
+                }
+                item_sync<NT>();
+                for (int i = tid; i < ns; i += NT) {
+                    i64 m = C.mid[i];
+                    if (m) atomic_add_i64(&Q[C.vv[i]], m);
+                }
+                item_sync<NT>();
+                return;
+            }
+        }
+    }
     for (int pass = 0; pass < 2; pass++) {
         for (i32 c0 = 0; c0 < ns; c0 += dc) {
             i32 len = min(dc, ns - c0);
@@ -772,27 +853,28 @@ __device__ __forceinline__ void q_sweeps(const DevGraph &g, i32 x, const Ctr &ct
             } else {
                 total = C.off[len];
             }
-            for (i32 eb = tid; eb < total; eb += NT * QU) {
-                int si[QU];
-                i32 key[QU];
-                bool ok[QU];
+            for (i32 eb = 0; eb < total; eb += NT * QS) {
+                const int nj = min(QS, (total - eb + NT - 1) / NT);
+                int si[QS];
+                i32 key[QS];
+                bool ok[QS];
+                q_locate<NT, QS>(C.off, len, eb + tid, nj, si);
 #pragma unroll
-                for (int u = 0; u < QU; u++) {
-                    i32 e = eb + u * NT;
-                    ok[u] = e < total;
-                    si[u] = ok[u] ? upper_index<i32>(C.off, 0, len, e) : 0;
+                for (int u = 0; u < QS; u++) {
+                    i32 e = eb + tid + u * NT;
+                    ok[u] = u < nj && e < total;
                     key[u] = ok[u] ? C.beg[si[u]] + (e - C.off[si[u]]) : 0;
                 }
 #pragma unroll
-                for (int u = 0; u < QU; u++) key[u] = ok[u] ? g.ncol[key[u]] : 0;
+                for (int u = 0; u < QS; u++) key[u] = ok[u] ? g.ncol[key[u]] : 0;
 #pragma unroll
-                for (int u = 0; u < QU; u++) {
-                    if (!ok[u]) continue;
+                for (int u = 0; u < QS; u++) {
+                    if (u >= nj) continue;
                     if (pass == 0) {
-                        ctr.inc(key[u]);
+                        if (ok[u]) ctr.inc(key[u]);
                     } else {
-                        i32 c = ctr.get(key[u]);
-                        if (c > 1) atomicAdd((unsigned long long *)&C.mid[si[u]], (unsigned long long)(c - 1));
+                        const i32 c = ok[u] ? ctr.get(key[u]) : 0;
+                        wave_run_add(C.mid, si[u], c > 1 ? c - 1 : 0);
                     }
                 }
             }
@@ -808,11 +890,11 @@ __device__ __forceinline__ void q_sweeps(const DevGraph &g, i32 x, const Ctr &ct
     }
 }
 
-template <int NT, int MODE>
+template <int NT, int MODE, int QK>
 __device__ __forceinline__ void q_item_hash(const DevGraph &g, i32 x, const QHash &H, const QChunk &C, int dc,
                                             int tid, i64 *red, i32 *red32, i64 *__restrict__ Q) {
     HashCounter ctr{H};
-    q_sweeps<NT, MODE>(g, x, ctr, C, dc, tid, red32, Q);
+    q_sweeps<NT, MODE, QK>(g, x, ctr, C, dc, tid, red32, Q);
     const i32 nu = *H.nused;
     i64 local = 0;
     for (i32 j = tid; j < nu; j += NT) {
@@ -858,7 +940,7 @@ __global__ void __launch_bounds__(256) k_q_wave(DevGraph g, const i32 *__restric
     const i32 cnt = st->cnt[wc];
     const int waves = gridDim.x * 4;
     for (i32 it = blockIdx.x * 4 + w; it < cnt; it += waves)
-        q_item_hash<WAVE, MODE>(g, list[it], H, C, DC, tid, nullptr, nullptr, Q);
+        q_item_hash<WAVE, MODE, QL_WAVE_HC / 2 / WAVE>(g, list[it], H, C, DC, tid, nullptr, nullptr, Q);
 }
 
 template <int MODE>
@@ -885,15 +967,17 @@ __global__ void __launch_bounds__(256) k_q_block(DevGraph g, const i32 *__restri
     QChunk C{s_off, s_vv, s_beg, s_mid};
     const i32 cnt = st->cnt[wc];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
-        q_item_hash<256, MODE>(g, list[it], H, C, DC, threadIdx.x, s_red, s_red32, Q);
+        q_item_hash<256, MODE, QL_BLOCK_HC / 2 / 256>(g, list[it], H, C, DC, threadIdx.x, s_red, s_red32, Q);
 }
 
 // ---------------------------------------------------------------------------
 // Heavy largest vertices (keys u in [h0, n), at most QH_DENSE_K of them).
-// Credits C(c,2) to a heavy key go to the workgroup's own row of `part`
-// (int64[gridDim.x][K]), summed into Q by k_qh_reduce: every opposite vertex
+// Credits C(c,2) to a heavy key go to one of QH_PART_ROWS rows of `part`
+// (int64[QH_PART_ROWS][K]), summed into Q by k_qh_reduce: every opposite vertex
 // credits the same few thousand hubs, and one shared counter per hub would
-// serialise those updates.
+// serialise those updates.  Workgroups are dealt to the 8 XCDs round robin, so
+// row = blockIdx % QH_PART_ROWS keeps each XCD on its own 8 rows (2 MiB for
+// K = 32768), which stay in that XCD's L2.
 // ---------------------------------------------------------------------------
 #define PK_SHIFT 17
 #define PK_CMASK 0x1ffffu
@@ -933,7 +1017,7 @@ struct PackedHash {
     }
 };
 
-template <int NT>
+template <int NT, int QK>
 __device__ __forceinline__ void qh_item_packed(const DevGraph &g, i32 x, const PackedHash &H0, int hc_max,
                                                const QChunk &C, int dc, int tid, i64 *red, i32 *red32,
                                                i64 *__restrict__ Q, i64 *__restrict__ prow) {
@@ -941,7 +1025,7 @@ __device__ __forceinline__ void qh_item_packed(const DevGraph &g, i32 x, const P
     int hc = 64;
     while (hc < hc_max && (i64)hc < 2 * g.wheavy[x]) hc <<= 1;
     PackedHash H{H0.tab, (u32)hc - 1, H0.h0};
-    q_sweeps<NT, Q_HEAVY>(g, x, H, C, dc, tid, red32, Q);
+    q_sweeps<NT, Q_HEAVY, QK>(g, x, H, C, dc, tid, red32, Q);
     i64 local = 0;
     for (int j = tid; j < hc; j += NT) {
         u32 cur = H.tab[j];
@@ -949,7 +1033,7 @@ __device__ __forceinline__ void qh_item_packed(const DevGraph &g, i32 x, const P
             i64 c = cur & PK_CMASK;
             if (c >= 2) {
                 i64 cc = c * (c - 1) / 2;
-                atomicAdd((unsigned long long *)&prow[cur >> PK_SHIFT], (unsigned long long)cc);
+                atomic_add_i64(&prow[cur >> PK_SHIFT], cc);
                 local += cc;
             }
             H.tab[j] = PK_EMPTY;
@@ -960,25 +1044,33 @@ __device__ __forceinline__ void qh_item_packed(const DevGraph &g, i32 x, const P
     item_sync<NT>();
 }
 
-#define QHW_HC 1024
+// One wave per item; the per-wave table size hcw (a power of two, at least twice
+// the class's wedge bound) comes with the launch, in dynamic LDS.
 #define QHW_DC 64
+#define QHW_QK 16
+__host__ __device__ constexpr int qhw_wave_bytes(int hcw) {
+    return ((8 * QHW_DC + 4 * hcw + 4 * (3 * QHW_DC + 1)) + 15) / 16 * 16;
+}
 __global__ void __launch_bounds__(256) k_qh_wave(DevGraph g, const i32 *__restrict__ list,
-                                                 const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 K) {
-    __shared__ u32 s_tab[4][QHW_HC];
-    __shared__ i32 s_off[4][QHW_DC + 1];
-    __shared__ i32 s_vv[4][QHW_DC];
-    __shared__ i32 s_beg[4][QHW_DC];
-    __shared__ i64 s_mid[4][QHW_DC];
+                                                 const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 K,
+                                                 int hcw) {
+    extern __shared__ __align__(16) char s_dyn[];
     const int w = threadIdx.x / WAVE, tid = lane_id();
-    for (int i = tid; i < QHW_HC; i += WAVE) s_tab[w][i] = PK_EMPTY;
+    char *base = s_dyn + (size_t)w * qhw_wave_bytes(hcw);
+    i64 *s_mid = (i64 *)base;
+    u32 *s_tab = (u32 *)(base + 8 * QHW_DC);
+    i32 *s_off = (i32 *)(s_tab + hcw);
+    i32 *s_vv = s_off + QHW_DC + 1;
+    i32 *s_beg = s_vv + QHW_DC;
+    for (int i = tid; i < hcw; i += WAVE) s_tab[i] = PK_EMPTY;
     item_sync<WAVE>();
-    PackedHash H{s_tab[w], QHW_HC - 1, g.h0};
-    QChunk C{s_off[w], s_vv[w], s_beg[w], s_mid[w]};
-    i64 *prow = part + (i64)blockIdx.x * K;
+    PackedHash H{s_tab, (u32)hcw - 1, g.h0};
+    QChunk C{s_off, s_vv, s_beg, s_mid};
+    i64 *prow = part + (i64)(blockIdx.x % QH_PART_ROWS) * K;
     const i32 cnt = st->cnt[WC_QH_WAVE];
     const int waves = gridDim.x * 4;
     for (i32 it = blockIdx.x * 4 + w; it < cnt; it += waves)
-        qh_item_packed<WAVE>(g, list[it], H, QHW_HC, C, QHW_DC, tid, nullptr, nullptr, Q, prow);
+        qh_item_packed<WAVE, QHW_QK>(g, list[it], H, hcw, C, QHW_DC, tid, nullptr, nullptr, Q, prow);
 }
 
 #define QHB_HC 8192
@@ -997,10 +1089,11 @@ __global__ void __launch_bounds__(QHB_NT) k_qh_block(DevGraph g, const i32 *__re
     __syncthreads();
     PackedHash H{s_tab, QHB_HC - 1, g.h0};
     QChunk C{s_off, s_vv, s_beg, s_mid};
-    i64 *prow = part + (i64)blockIdx.x * K;
+    i64 *prow = part + (i64)(blockIdx.x % QH_PART_ROWS) * K;
     const i32 cnt = st->cnt[WC_QH_BLOCK];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
-        qh_item_packed<QHB_NT>(g, list[it], H, QHB_HC, C, QHB_DC, threadIdx.x, s_red, s_red32, Q, prow);
+        qh_item_packed<QHB_NT, QHB_HC / 2 / QHB_NT>(g, list[it], H, QHB_HC, C, QHB_DC, threadIdx.x, s_red, s_red32,
+                                                    Q, prow);
 }
 
 // part rows -> Q over the heavy range
@@ -1013,7 +1106,7 @@ __global__ void k_qh_reduce(const i64 *__restrict__ part, int rows, i32 K, i32 h
 }
 
 // Heavy largest vertices: dense 16-bit counters over [h0, n).
-#define QD_NT 1024
+#define QD_NT 512
 #define QD_DC 256
 __global__ void __launch_bounds__(QD_NT) k_q_dense(DevGraph g, const i32 *__restrict__ list,
                                                    const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 Kp) {
@@ -1030,25 +1123,24 @@ __global__ void __launch_bounds__(QD_NT) k_q_dense(DevGraph g, const i32 *__rest
     __syncthreads();
     DenseCounter ctr{s_w, g.h0};
     QChunk C{s_off, s_vv, s_beg, s_mid};
-    i64 *prow = part + (i64)blockIdx.x * Kp;
+    i64 *prow = part + (i64)(blockIdx.x % QH_PART_ROWS) * Kp;
     const i32 cnt = st->cnt[WC_QH_DENSE];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x) {
         i32 x = list[it];
-        q_sweeps<QD_NT, Q_HEAVY>(g, x, ctr, C, QD_DC, threadIdx.x, s_red32, Q);
+        q_sweeps<QD_NT, Q_HEAVY, 16>(g, x, ctr, C, QD_DC, threadIdx.x, s_red32, Q);
         i64 local = 0;
         for (i32 i = threadIdx.x; i < KW; i += QD_NT) {
             u32 word = s_w[i];
             if (word) {
                 i64 c0 = word & 0xffffu, c1 = word >> 16;
-                // key indices 2i and 2i+1 belong to this thread alone
                 if (c0 >= 2) {
                     i64 cc = c0 * (c0 - 1) / 2;
-                    prow[2 * i] += cc;
+                    atomic_add_i64(&prow[2 * i], cc);
                     local += cc;
                 }
                 if (c1 >= 2) {
                     i64 cc = c1 * (c1 - 1) / 2;
-                    prow[2 * i + 1] += cc;
+                    atomic_add_i64(&prow[2 * i + 1], cc);
                     local += cc;
                 }
                 s_w[i] = 0u;
@@ -1118,10 +1210,23 @@ hipError_t launch_classify(const DevGraph &g, const i64 *wl, const i64 *wh, cons
     return hipGetLastError();
 }
 
+template <int MODE>
+static void launch_large(const DevGraph &g, const i32 *list, const GraphStats *st, i32 *t, i64 *K4, i64 *tau,
+                         const TriCache &tc, char *scratch, i64 slice, int cap, int hc, int blocks, i64 lds_max,
+                         i64 *counters, hipStream_t s) {
+    const i64 lds = probe_large_lds_bytes(cap, hc);
+    if (lds <= lds_max)
+        hipLaunchKernelGGL((k_probe_large<MODE, true>), dim3(blocks), dim3(256), (size_t)lds, s, g, list, st, t, K4,
+                           tau, tc, scratch, slice, cap, hc, counters);
+    else
+        hipLaunchKernelGGL((k_probe_large<MODE, false>), dim3(blocks), dim3(256), 0, s, g, list, st, t, K4, tau, tc,
+                           scratch, slice, cap, hc, counters);
+}
+
 hipError_t launch_probe(int mode, const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i32 *t,
                         i64 *K4, i64 *tau, const TriCacheArgs &tca, char *large_scratch, i64 large_slice,
-                        int large_cap, int large_hc, int large_blocks, int grid_wave, int grid_block,
-                        i64 *counters, const KernelEvents &kev, hipStream_t s) {
+                        int large_cap, int large_hc, int large_blocks, i64 large_lds_max, int grid_wave,
+                        int grid_block, i64 *counters, const KernelEvents &kev, hipStream_t s) {
 #define KMARK(i) \
     if (kev.ev) (void)hipEventRecord(kev.ev[i], s)
     TriCache tw{tca.rec, tca.cap, tca.bump, tca.off, tca.cnt, tca.chunk_wave};
@@ -1138,9 +1243,8 @@ hipError_t launch_probe(int mode, const DevGraph &g, i32 *const *lists_host, con
                            lists_host[WC_TRI_BLOCK], st, t, K4, tau, tb, counters);
         KMARK(3);
         if (large_blocks > 0)
-            hipLaunchKernelGGL(k_probe_large<PROBE_TRI>, dim3(large_blocks), dim3(256), 0, s, g,
-                               lists_host[WC_TRI_LARGE], st, t, K4, tau, tb, large_scratch, large_slice, large_cap,
-                               large_hc, counters);
+            launch_large<PROBE_TRI>(g, lists_host[WC_TRI_LARGE], st, t, K4, tau, tb, large_scratch, large_slice,
+                                 large_cap, large_hc, large_blocks, large_lds_max, counters, s);
         KMARK(4);
     } else {
         hipLaunchKernelGGL(k_probe_thread<PROBE_TAU>, dim3(grid_wave), dim3(256), 0, s, g,
@@ -1150,9 +1254,8 @@ hipError_t launch_probe(int mode, const DevGraph &g, i32 *const *lists_host, con
         hipLaunchKernelGGL(k_probe_block<PROBE_TAU>, dim3(grid_block), dim3(PB_NT), 0, s, g,
                            lists_host[WC_TRI_BLOCK], st, t, K4, tau, tb, (i64 *)nullptr);
         if (large_blocks > 0)
-            hipLaunchKernelGGL(k_probe_large<PROBE_TAU>, dim3(large_blocks), dim3(256), 0, s, g,
-                               lists_host[WC_TRI_LARGE], st, t, K4, tau, tb, large_scratch, large_slice, large_cap,
-                               large_hc, (i64 *)nullptr);
+            launch_large<PROBE_TAU>(g, lists_host[WC_TRI_LARGE], st, t, K4, tau, tb, large_scratch, large_slice,
+                                 large_cap, large_hc, large_blocks, large_lds_max, (i64 *)nullptr, s);
     }
     return hipGetLastError();
 }
@@ -1172,7 +1275,7 @@ hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvar
 
 hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i64 *Q, i32 *gscratch,
                     i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, i64 *part, int part_rows,
-                    const KernelEvents &kev, hipStream_t s) {
+                    i64 qh_wave_bound, const KernelEvents &kev, hipStream_t s) {
     KMARK(5);
     hipLaunchKernelGGL(k_q_wave<Q_LIGHT>, dim3(grid_wave), dim3(256), 0, s, g, lists_host[WC_QL_WAVE], st,
                        (int)WC_QL_WAVE, Q);
@@ -1186,15 +1289,17 @@ hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats 
     KMARK(8);
     const i32 K = g.n - g.h0;
     if (K > 0) {
-        // rows of `part` are per workgroup: each kernel's grid stays within part_rows
-        int gw = grid_wave < part_rows ? grid_wave : part_rows;
-        int gb = grid_block < part_rows ? grid_block : part_rows;
-        int gd = grid_dense < part_rows ? grid_dense : part_rows;
-        hipLaunchKernelGGL(k_qh_wave, dim3(gw), dim3(256), 0, s, g, lists_host[WC_QH_WAVE], st, Q, part, K);
+        (void)part_rows;
+        int hcw = 64;
+        while ((i64)hcw < 2 * qh_wave_bound) hcw <<= 1;
+        hipLaunchKernelGGL(k_qh_wave, dim3(grid_wave), dim3(256), 4 * qhw_wave_bytes(hcw), s, g,
+                           lists_host[WC_QH_WAVE], st, Q, part, K, hcw);
         KMARK(9);
-        hipLaunchKernelGGL(k_qh_block, dim3(gb), dim3(QHB_NT), 0, s, g, lists_host[WC_QH_BLOCK], st, Q, part, K);
+        hipLaunchKernelGGL(k_qh_block, dim3(grid_block), dim3(QHB_NT), 0, s, g, lists_host[WC_QH_BLOCK], st, Q, part,
+                           K);
         KMARK(10);
-        hipLaunchKernelGGL(k_q_dense, dim3(gd), dim3(QD_NT), 0, s, g, lists_host[WC_QH_DENSE], st, Q, part, K);
+        hipLaunchKernelGGL(k_q_dense, dim3(grid_dense), dim3(QD_NT), 0, s, g, lists_host[WC_QH_DENSE], st, Q, part,
+                           K);
         KMARK(11);
         hipLaunchKernelGGL(k_qh_reduce, dim3((K + 255) / 256), dim3(256), 0, s, part, part_rows, K, g.h0, Q);
     } else {

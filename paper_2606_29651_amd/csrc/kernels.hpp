@@ -14,7 +14,8 @@ struct GraphStats {
     int err;         // device-side consistency flag (odd numerator)
     int pad;         // counter of long N+ rows queued for the workgroup sort
     int bad_input;   // row_ptr or col out of range (checked before any use)
-    int pad2[3];
+    int pad2;
+    long long pairs; // sum over vertices of C(|N+|, 2): a bound on the triangle count
     // work-class list sizes (filled by the classification kernel)
     int cnt[16];
     // per class: work units (Stage I probes or 4-cycle wedges) and row slots handled
@@ -76,9 +77,9 @@ struct Thresholds {
 #define QL_WAVE_DC 64       // segment (row slot) capacity per wave item
 #define QL_BLOCK_HC 8192
 #define QL_BLOCK_DC 1024
-#define QH_WAVE_HC 1024     // packed (key, count) entries per wave
+#define QH_WAVE_HC 4096     // largest packed (key, count) table per wave (sized per launch)
 #define QH_BLOCK_HC 8192    // packed entries per workgroup
-#define QH_PART_ROWS 1024   // per-workgroup rows of heavy-key credits
+#define QH_PART_ROWS 64     // rows of heavy-key credits (8 per XCD)
 #define QH_DENSE_K 32768    // size of the heavy key range (top-ranked vertices)
 #define QH_DENSE_DC 4096    // middles accumulated in LDS by the dense kernel (else global)
 
@@ -139,8 +140,8 @@ struct TriCacheArgs {
 };
 hipError_t launch_probe(int mode, const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i32 *t,
                         i64 *K4, i64 *tau, const TriCacheArgs &tca, char *large_scratch, i64 large_slice,
-                        int large_cap, int large_hc, int large_blocks, int grid_wave, int grid_block,
-                        i64 *counters, const KernelEvents &kev, hipStream_t s);
+                        int large_cap, int large_hc, int large_blocks, i64 large_lds_max, int grid_wave,
+                        int grid_block, i64 *counters, const KernelEvents &kev, hipStream_t s);
 
 // mlp.hip
 int mlp_num_trained();
@@ -159,5 +160,6 @@ hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvar
                         hipStream_t s);
 hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i64 *Q, i32 *gscratch,
                     i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, i64 *part, int part_rows,
-                    const KernelEvents &kev, hipStream_t s);
-i64 probe_large_slice_bytes(int cap, int hc);
+                    i64 qh_wave_bound, const KernelEvents &kev, hipStream_t s);
+i64 probe_large_slice_bytes(int cap, int hc, i64 lds_max);
+#define PL_LDS_MAX (144 * 1024)  // largest dynamic LDS of the large probe kernel

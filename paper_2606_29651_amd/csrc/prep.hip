@@ -272,6 +272,7 @@ __global__ void k_relabel(i32 n, const i64 *__restrict__ rp, const i32 *__restri
     int waves = gridDim.x * (blockDim.x / WAVE);
     int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     int dplus_max = 0, bad = 0;
+    long long pairs = 0;
     for (i32 y = n - 1 - wid; y >= 0; y -= waves) {
         i32 x = (i32)order[y];
         i64 beg = rp[x];
@@ -287,6 +288,7 @@ __global__ void k_relabel(i32 n, const i64 *__restrict__ rp, const i32 *__restri
         i32 lowpos = ybase, uppos = ybase + nlow;
         if (lane_id() == 0) nsplit[y] = uppos;
         dplus_max = max(dplus_max, len - nlow);
+        pairs += (long long)(len - nlow) * (len - nlow - 1) / 2;
         for (i32 c = 0; c < len; c += WAVE) {
             i32 j = c + lane_id();
             bool valid = j < len;
@@ -300,6 +302,7 @@ __global__ void k_relabel(i32 n, const i64 *__restrict__ rp, const i32 *__restri
         }
     }
     if (lane_id() == 0 && dplus_max > 0) atomicMax(&st->dplus_max, dplus_max);
+    if (lane_id() == 0 && pairs > 0) atomicAdd((unsigned long long *)&st->pairs, (unsigned long long)pairs);
     if (bad) atomicOr(&st->bad_input, 1);
 }
 

@@ -132,6 +132,11 @@ def test_stage_intermediates(ni, ora, name):
 FORCED = {
     "all_block": dict(tri_wave=1),
     "all_large": dict(tri_wave=1, tri_block=1),
+    "all_large_global": dict(tri_wave=1, tri_block=1, large_lds=0),
+    "tri_cache_none": dict(tri_cache=0),
+    "tri_cache_small": dict(tri_cache=2000, tri_wave=8),
+    "qh_wave_small": dict(qh_wave=64, heavy_k=32768),
+    "qh_wave_max": dict(qh_wave=2048, heavy_k=32768),
     "q_global_light": dict(ql_wave=0, ql_block=0, heavy_k=0),
     "q_block_light": dict(ql_wave=0, heavy_k=0),
     "q_dense_heavy": dict(qh_wave=0, qh_block=0, heavy_k=32768),
