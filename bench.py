@@ -37,11 +37,11 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-# Algorithmic bytes per unit, per kernel ("Measurement"):
+# Algorithmic bytes per unit, per kernel:
 #   Stage I/II probe kernels: 4 B per probe (one N+(v) entry), 12 B per N+(u) entry
 #     (the entry and the two row offsets of v);
-#   4-cycle kernels: 8 B per wedge (its key is read in each of the two sweeps) and
-#     16 B per row slot (neighbour id, segment bounds).
+#   4-cycle kernels: 4 B per wedge (the key, one N+(v) entry) and 16 B per row slot
+#     (neighbour id, segment bounds, the middle's credit).
 KERNEL_CLASS = {"probe_thread": "tri_thread", "probe_wave": "tri_wave", "probe_block": "tri_block",
                 "probe_large": "tri_large", "ql_wave": "ql_wave", "ql_block": "ql_block",
                 "ql_global": "ql_global", "qh_wave": "qh_wave", "qh_block": "qh_block",
@@ -52,7 +52,7 @@ def kernel_bytes(kernel, stats):
     cnt, work, slots = stats[KERNEL_CLASS[kernel]]
     if kernel.startswith("probe"):
         return 4 * work + 12 * slots
-    return 8 * work + 16 * slots
+    return 4 * work + 16 * slots
 
 
 def time_count(ni, ctx, rp, cl, out, flags, steps, warmup):
@@ -117,6 +117,43 @@ def train_work_model(ni, ctx, graphs):
     model, mse = ni.mlp_train(X, y, epochs=3, batch=8192, lr=3e-3, seed=1, ctx=ctx)
     var = float(torch.var(y.double()))
     return model, {"rows": int(X.shape[0]), "mse": mse, "target_var": var}
+
+
+ER_DEFAULT = ["er_4m_8", "er_4m_16", "er_4m_32"]
+ER_FULL = [f"er_{n}m_{d}" for n in (1, 2, 4, 8, 16) for d in (8, 16, 32)]
+
+
+def roofline_of(kernel_ms, stats):
+    dom = max(kernel_ms, key=kernel_ms.get)
+    b = kernel_bytes(dom, stats)
+    ach = b / (kernel_ms[dom] * 1e-3) / 1e9 if kernel_ms[dom] > 0 else 0.0
+    return dom, b, ach
+
+
+def er_series(args, ni, names):
+    """Plain form on the Erdos-Renyi scaling series: edges/s and the dominant
+    kernel's algorithmic GB/s per point."""
+    import torch
+    import graphgen as gg
+    res = {}
+    ctx = ni.Context(0)
+    for name in names:
+        t0 = time.time()
+        g = gg.config_graph(name, seed=args.seed)
+        gen_s = time.time() - t0
+        rp, cl = torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda()
+        out = torch.empty((g.n, 15), dtype=torch.int64, device="cuda")
+        ms, st, km = time_count(ni, ctx, rp, cl, out, 0, 3, 1)
+        dom, b, ach = roofline_of(km, ctx.class_stats())
+        res[name] = {"n": g.n, "m": g.m, "ms": round(ms, 3), "value": g.m / (ms * 1e-3),
+                     "stage_ms": {k: round(v, 3) for k, v in st.items()},
+                     "dominant": dom, "dominant_ms": round(km[dom], 3), "dominant_GBps": round(ach, 1)}
+        log(f"[bench] {name} m={g.m} gen {gen_s:.1f}s: {ms:.2f} ms/count, {g.m / (ms * 1e-3):.3e} edges/s, "
+            f"{dom} {ach:.0f} GB/s")
+        del rp, cl, out
+        torch.cuda.empty_cache()
+    ctx.close()
+    return res
 
 
 def forms(args, ni, ctx, g, rp, cl, out, base_ms):
@@ -233,6 +270,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="all", choices=["all", "none"])
     ap.add_argument("--batch-graphs", type=int, default=50000)
+    ap.add_argument("--er-series", default="default", choices=["default", "full", "none"],
+                    help="Erdos-Renyi points timed with the forms: n = 4M at average degree 8, 16, 32 "
+                         "(default), all of n in {1,2,4,8,16}M x degree {8,16,32} (full), or none")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain int32->float32 copy of MIB MiB five times (reads and writes "
                          "MIB MiB each), to scale HBM byte counters taken under rocprofv3 --pmc")
@@ -261,9 +301,7 @@ def main():
     stats = ctx.class_stats()
     log("[bench] stage ms " + json.dumps({k: round(v, 3) for k, v in stage_ms.items()}))
     log("[bench] kernel ms " + json.dumps({k: round(v, 3) for k, v in kernel_ms.items()}))
-    dom = max(kernel_ms, key=kernel_ms.get)
-    bytes_dom = kernel_bytes(dom, stats)
-    ach = bytes_dom / (kernel_ms[dom] * 1e-3) / 1e9 if kernel_ms[dom] > 0 else 0.0
+    dom, bytes_dom, ach = roofline_of(kernel_ms, stats)
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel_ms": round(kernel_ms[dom], 4), "algorithmic_bytes": int(bytes_dom),
@@ -289,6 +327,8 @@ def main():
     }
     if args.forms == "all":
         rec["forms"] = forms(args, ni, ctx, g, rp, cl, out, ms)
+        if args.er_series != "none":
+            rec["forms"]["er_series"] = er_series(args, ni, ER_FULL if args.er_series == "full" else ER_DEFAULT)
     rec["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(g, args.cpu_budget)
     print(json.dumps(rec))
     ctx.close()

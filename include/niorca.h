@@ -80,8 +80,10 @@ uint64_t niorca_workspace_bytes(const niorca_ctx *ctx);
  * never a count).  Names and ranges:
  *   "tri_wave"  1..64    vertices with |N+| up to this use one wave (Stage I/II, tau)
  *   "tri_block" 1..512   ... up to this one workgroup with LDS; above, global scratch
- *   "ql_wave"   0..256   4-cycle wedges (largest vertex light) up to this: wave hash
- *   "ql_block"  0..4096  ... up to this: workgroup hash; above: global counters
+ *   "ql_wave"   0..2048  4-cycle wedges (largest vertex light) up to this: wave hash
+ *                        (default 512; the per-wave table is sized from it)
+ *   "ql_block"  0..8192  ... up to this: workgroup hash (default 4096, table sized
+ *                        from it); above: global counters
  *   "qh_wave"   0..2048  4-cycle wedges opposite a heavy largest vertex: wave hash
  *                        (default 1024; the per-wave table is sized from it)
  *   "qh_block"  0..4096  ... workgroup hash; above: dense LDS counters

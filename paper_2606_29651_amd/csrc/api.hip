@@ -34,7 +34,7 @@ struct niorca_ctx {
     bool ev_valid = false;
     // tunable class thresholds and the size of the heavy 4-cycle key range
     Thresholds th{TRI_WAVE_CAP, TRI_BLOCK_CAP, 0, 16, 4096, 0.f, 0.f, nullptr,
-                  QL_WAVE_HC / 2, QL_BLOCK_HC / 2, 1024, QH_BLOCK_HC / 2};
+                  512, 4096, 1024, QH_BLOCK_HC / 2};
     int32_t heavy_k = QH_DENSE_K;
     // the last captured batched sequence and the shape it was captured for
     hipGraphExec_t gexec = nullptr;
@@ -512,8 +512,16 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     // ---- Stage I (t) and Stage II (K4) ----
     HIP_TRY(fill32(t, sizeof(i32) * nnz, 0u, s));
     HIP_TRY(fill32(accb, sizeof(i64) * 10 * (i64)n, 0u, s));
+    // records are handed out in chunks: about two per wave (workgroup) of the Stage I
+    // grid, but never less than the largest item of the class needs, C(64, 2)
+    // (C(512, 2)), and never more than 2^14 (2^18)
+    auto chunk_for = [&](i64 holders, i64 lo, i64 hi) {
+        i64 c = L.tc_cap / (2 * holders);
+        return c < lo ? lo : (c > hi ? hi : c);
+    };
     TriCacheArgs tca{L.tc_cap > 0 ? (u64 *)(W + L.tcrec) : nullptr, L.tc_cap, (u64 *)(W + L.tcbump),
-                     (i64 *)(W + L.tcoff), (i32 *)(W + L.tccnt), 1 << 14, 1 << 18};
+                     (i64 *)(W + L.tcoff), (i32 *)(W + L.tccnt), chunk_for((i64)cu * 8 * 4, 2048, 1 << 14),
+                     chunk_for((i64)cu * 2, 1 << 17, 1 << 18)};
     HIP_TRY(fill32(tca.bump, sizeof(u64), 0u, s));
     STAGE_MARK(4);
     HIP_TRY(launch_probe(0, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, L.large_slice, L.large_cap,
@@ -537,7 +545,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     STAGE_MARK(7);
     if (n - h0 > 0) HIP_TRY(fill32(qpart, (i64)sizeof(i64) * L.part_rows * (n - h0), 0u, s));
     HIP_TRY(launch_q(g, lh, dst, acc.Q, gscratch, L.gslice, L.gblocks, cu * 4, cu * 4, cu * 2, qpart, L.part_rows,
-                     th.qh_wave, kev, s));
+                     th.ql_wave, th.ql_block, th.qh_wave, kev, s));
     STAGE_MARK(8);
     // ---- Stage III-b: equations ----
     HIP_TRY(launch_solve(g, acc, o.psi, o.fvars, dst, cu * 8, s));

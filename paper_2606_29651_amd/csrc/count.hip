@@ -206,17 +206,38 @@ struct TriCache {
 struct ItemState {  // per item group, in LDS
     i64 chunk_cur, chunk_end, item_base;
     i32 item_ok, item_cnt;
+    i32 full;       // the record space ran out: stop asking for chunks
 };
 
+// Row bounds of a Stage I / tau item (and its kept triangles), loaded together so
+// that the kernels can fetch them one item ahead.
+struct PMeta {
+    i32 u, base, du, tcnt;
+    i64 toff;
+};
+
+template <int MODE>
+__device__ __forceinline__ PMeta p_meta(const DevGraph &g, const TriCache &tc, i32 u) {
+    PMeta m{u, 0, 0, -1, 0};
+    if (u >= 0) {
+        m.base = g.nsplit[u];
+        m.du = g.nrp[u + 1] - m.base;
+        if (MODE == PROBE_TAU) {
+            m.tcnt = tc.cnt[u];
+            m.toff = tc.off[u];
+        }
+    }
+    return m;
+}
+
 template <int NT, int MODE, int QP>
-__device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, const ProbeMem &M, int hc,
+__device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, int tid, const ProbeMem &M, int hc,
                                            int words, i32 *__restrict__ t, i64 *__restrict__ K4,
                                            i64 *__restrict__ tau, i64 *red, i32 *red32, const TriCache &tc,
                                            ItemState *S, i64 *__restrict__ counters) {
     const i64 t_start = (counters && MODE == PROBE_TRI) ? (i64)clock64() : 0;
-    const i32 base = g.nsplit[u];
-    const i32 du = g.nrp[u + 1] - base;
-    if (MODE == PROBE_TAU && tc.cnt[u] >= 0) {
+    const i32 u = pm.u, base = pm.base, du = pm.du;
+    if (MODE == PROBE_TAU && pm.tcnt >= 0) {
         // cached triangles: tau from the records and the final t values
         for (int i = tid; i < du; i += NT) {
             M.nb[i] = g.ncol[base + i];
@@ -224,7 +245,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, co
             M.acc[i] = 0;
         }
         item_sync<NT>();
-        const i64 r0 = tc.off[u], r1 = r0 + tc.cnt[u];
+        const i64 r0 = pm.toff, r1 = r0 + pm.tcnt;
         i64 tau_local = 0;
         for (i64 r = r0 + tid; r < r1; r += NT) {
             u64 rec = tc.rec[r];
@@ -271,7 +292,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, co
         i64 ub = min((i64)total, (i64)du * (du - 1) / 2);
         S->item_ok = 0;
         S->item_cnt = 0;
-        if (tc.rec && ub <= tc.chunk) {
+        if (tc.rec && ub <= tc.chunk && !S->full) {
             if (S->chunk_end - S->chunk_cur < ub) {
                 u64 b = atomicAdd((unsigned long long *)tc.bump, (unsigned long long)tc.chunk);
                 if ((i64)b + tc.chunk <= tc.cap) {
@@ -279,6 +300,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, i32 u, int tid, co
                     S->chunk_end = (i64)b + tc.chunk;
                 } else {
                     S->chunk_cur = S->chunk_end = 0;
+                    S->full = 1;
                 }
             }
             if (S->chunk_end - S->chunk_cur >= ub) {
@@ -408,13 +430,24 @@ __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__res
     __shared__ ItemState s_st[4];
     const int w = threadIdx.x / WAVE, tid = lane_id();
     ProbeMem M{s_hkey[w], s_hpos[w], s_off[w], s_nb[w], s_beg[w], s_tcnt[w], s_A[w], s_acc[w]};
-    if (tid == 0) s_st[w].chunk_cur = s_st[w].chunk_end = 0;
+    if (tid == 0) {
+        s_st[w].chunk_cur = s_st[w].chunk_end = 0;
+        s_st[w].full = 0;
+    }
     item_sync<WAVE>();
     const i32 cnt = st->cnt[WC_TRI_WAVE];
     const int waves = gridDim.x * 4;
-    for (i32 it = blockIdx.x * 4 + w; it < cnt; it += waves)
-        probe_item<WAVE, MODE, PW_QP>(g, list[it], tid, M, HC, WORDS, t, K4, tau, nullptr, nullptr, tc, &s_st[w],
+    i32 it = blockIdx.x * 4 + w;
+    PMeta cur = p_meta<MODE>(g, tc, it < cnt ? list[it] : -1);
+    i32 un = it + waves < cnt ? list[it + waves] : -1;
+    for (; it < cnt; it += waves) {
+        // the next item's row bounds and the one after's id load while this one runs
+        const PMeta nxt = p_meta<MODE>(g, tc, un);
+        un = it + 2 * waves < cnt ? list[it + 2 * waves] : -1;
+        probe_item<WAVE, MODE, PW_QP>(g, cur, tid, M, HC, WORDS, t, K4, tau, nullptr, nullptr, tc, &s_st[w],
                                       counters);
+        cur = nxt;
+    }
 }
 
 // One 256-thread workgroup per vertex, 64 < |N+(u)| <= TRI_BLOCK_CAP.
@@ -436,12 +469,22 @@ __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__
     __shared__ i32 s_red32[PB_NT / WAVE];
     __shared__ ItemState s_st;
     ProbeMem M{s_hkey, s_hpos, s_off, s_nb, s_beg, s_tcnt, s_A, s_acc};
-    if (threadIdx.x == 0) s_st.chunk_cur = s_st.chunk_end = 0;
+    if (threadIdx.x == 0) {
+        s_st.chunk_cur = s_st.chunk_end = 0;
+        s_st.full = 0;
+    }
     __syncthreads();
     const i32 cnt = st->cnt[WC_TRI_BLOCK];
-    for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
-        probe_item<PB_NT, MODE, 4>(g, list[it], threadIdx.x, M, HC, WORDS, t, K4, tau, s_red, s_red32, tc, &s_st,
-                                counters);
+    i32 it = blockIdx.x;
+    PMeta cur = p_meta<MODE>(g, tc, it < cnt ? list[it] : -1);
+    i32 un = it + (i32)gridDim.x < cnt ? list[it + gridDim.x] : -1;
+    for (; it < cnt; it += gridDim.x) {
+        const PMeta nxt = p_meta<MODE>(g, tc, un);
+        un = it + 2 * (i32)gridDim.x < cnt ? list[it + 2 * gridDim.x] : -1;
+        probe_item<PB_NT, MODE, 4>(g, cur, threadIdx.x, M, HC, WORDS, t, K4, tau, s_red, s_red32, tc, &s_st,
+                                   counters);
+        cur = nxt;
+    }
 }
 
 // One lane per vertex for tiny items (|N+(u)| <= 8): N+(u) in registers, the
@@ -560,11 +603,15 @@ __global__ void __launch_bounds__(256) k_probe_large(DevGraph g, const i32 *__re
     M.beg = (i32 *)q; q += sizeof(i32) * cap;
     M.tcnt = (i32 *)q;
     __shared__ ItemState s_st;
-    if (threadIdx.x == 0) s_st.chunk_cur = s_st.chunk_end = 0;
+    if (threadIdx.x == 0) {
+        s_st.chunk_cur = s_st.chunk_end = 0;
+        s_st.full = 0;
+    }
     __syncthreads();
     const i32 cnt = st->cnt[WC_TRI_LARGE];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
-        probe_item<256, MODE, 4>(g, list[it], threadIdx.x, M, hc, words, t, K4, tau, s_red, s_red32, tc, &s_st,
+        probe_item<256, MODE, 4>(g, p_meta<MODE>(g, tc, list[it]), threadIdx.x, M, hc, words, t, K4, tau, s_red,
+                                 s_red32, tc, &s_st,
                                  counters);
 }
 
@@ -726,50 +773,10 @@ __device__ __forceinline__ i32 q_load_chunk(const DevGraph &g, i32 x, i32 s0, i3
     return C.off[len];
 }
 
-// Hash counter in LDS: keys with counts; used[] lists occupied slots.
-struct QHash {
-    i32 *key;
-    i32 *cnt;
-    i32 *used;
-    i32 *nused;
-    u32 mask;
-};
-
-__device__ __forceinline__ void qhash_inc(const QHash &H, i32 k) {
-    u32 sl = hslot((u32)k, H.mask);
-    while (true) {
-        i32 cur = H.key[sl];
-        if (cur == k) break;
-        if (cur == -1) {
-            i32 prev = atomicCAS(&H.key[sl], -1, k);
-            if (prev == -1) {
-                H.used[atomicAdd(H.nused, 1)] = (i32)sl;
-                break;
-            }
-            if (prev == k) break;
-        }
-        sl = (sl + 1) & H.mask;
-    }
-    atomicAdd(&H.cnt[sl], 1);
-}
-
-__device__ __forceinline__ i32 qhash_get(const QHash &H, i32 k) {
-    u32 sl = hslot((u32)k, H.mask);
-    while (true) {
-        i32 cur = H.key[sl];
-        if (cur == k) return H.cnt[sl];
-        if (cur == -1) return 0;
-        sl = (sl + 1) & H.mask;
-    }
-}
-
-// Counter policies: HashCounter (LDS hash), DenseCounter (16-bit LDS counters over
-// [h0, h0+K)), GlobalCounter (int32 counters over [0, n) in global scratch).
-struct HashCounter {
-    QHash H;
-    __device__ void inc(i32 k) const { qhash_inc(H, k); }
-    __device__ i32 get(i32 k) const { return qhash_get(H, k); }
-};
+// Counter policies (inc / get of a key's count): LightHash (LDS hash of keys and
+// counts), PackedHash (LDS hash of heavy key index and count in one word),
+// DenseCounter (16-bit LDS counters over [h0, h0+K)), GlobalCounter (int32 counters
+// over [0, n) in global scratch).
 
 struct DenseCounter {
     u32 *w;   // K/2 words
@@ -794,6 +801,25 @@ struct GlobalCounter {
     __device__ i32 get(i32 k) const { return c[k]; }
 };
 
+// Row bounds of a 4-cycle item and its wedge count, loaded together so that the
+// kernels can fetch them one item ahead.
+struct QMeta {
+    i32 x, s0, sp, s1;
+    i64 w;
+};
+
+template <int MODE>
+__device__ __forceinline__ QMeta q_meta(const DevGraph &g, i32 x) {
+    QMeta m{x, 0, 0, 0, 0};
+    if (x >= 0) {
+        m.s0 = g.nrp[x];
+        m.sp = g.nsplit[x];
+        m.s1 = g.nrp[x + 1];
+        m.w = (MODE == Q_LIGHT) ? g.wlight[x] : g.wheavy[x];
+    }
+    return m;
+}
+
 // Both sweeps over the item's wedges, chunk by chunk.  Each thread takes QS wedges
 // per step (independent loads in flight); their segments are found together by a
 // search over the chunk's prefix offsets in LDS.  When the whole item is one
@@ -801,10 +827,10 @@ struct GlobalCounter {
 // registers: the keys are read from memory once, all loads of a thread in flight
 // together, and the second sweep needs neither loads nor searches.
 template <int NT, int MODE, int QK = 0, typename Ctr>
-__device__ __forceinline__ void q_sweeps(const DevGraph &g, i32 x, const Ctr &ctr, const QChunk &C, int dc,
+__device__ __forceinline__ void q_sweeps(const DevGraph &g, const QMeta &mt, const Ctr &ctr, const QChunk &C, int dc,
                                          int tid, i32 *red32, i64 *__restrict__ Q) {
-    const i32 s0 = g.nrp[x], sp = g.nsplit[x];
-    const i32 ns = (MODE == Q_LIGHT) ? sp - s0 : g.nrp[x + 1] - s0;
+    const i32 x = mt.x, s0 = mt.s0, sp = mt.sp;
+    const i32 ns = (MODE == Q_LIGHT) ? sp - s0 : mt.s1 - s0;
     const bool single = ns <= dc;
     if constexpr (QK > 0) {
         if (single) {
@@ -890,84 +916,152 @@ __device__ __forceinline__ void q_sweeps(const DevGraph &g, i32 x, const Ctr &ct
     }
 }
 
-template <int NT, int MODE, int QK>
-__device__ __forceinline__ void q_item_hash(const DevGraph &g, i32 x, const QHash &H, const QChunk &C, int dc,
-                                            int tid, i64 *red, i32 *red32, i64 *__restrict__ Q) {
-    HashCounter ctr{H};
-    q_sweeps<NT, MODE, QK>(g, x, ctr, C, dc, tid, red32, Q);
-    const i32 nu = *H.nused;
-    i64 local = 0;
-    for (i32 j = tid; j < nu; j += NT) {
-        i32 sl = H.used[j];
-        i64 c = H.cnt[sl];
-        if (c >= 2) {
-            i64 cc = c * (c - 1) / 2;
-            atomic_add_i64(&Q[H.key[sl]], cc);
-            local += cc;
+
+// Light items on one wave: an LDS hash (key, count) sized per item to twice its
+// wedge count (at most hcw entries, given with the launch in dynamic LDS), harvested
+// by scanning the item's part of the table.
+struct LightHash {
+    i32 *key;
+    i32 *cnt;
+    u32 mask;
+    __device__ void inc(i32 k) const {
+        u32 sl = hslot((u32)k, mask);
+        while (true) {
+            i32 cur = key[sl];
+            if (cur == k) break;
+            if (cur == -1) {
+                i32 prev = atomicCAS(&key[sl], -1, k);
+                if (prev == -1 || prev == k) break;
+            }
+            sl = (sl + 1) & mask;
         }
-        H.key[sl] = -1;
-        H.cnt[sl] = 0;
+        atomicAdd(&cnt[sl], 1);
     }
-    i64 s = item_sum<NT>(local, red, tid);
-    if (tid == 0) {
-        if (s) atomic_add_i64(&Q[x], s);
-        *H.nused = 0;
+    __device__ i32 get(i32 k) const {
+        u32 sl = hslot((u32)k, mask);
+        while (true) {
+            i32 cur = key[sl];
+            if (cur == k) return cnt[sl];
+            if (cur == -1) return 0;
+            sl = (sl + 1) & mask;
+        }
     }
-    item_sync<NT>();
+};
+
+#define QLW_DC 64
+#define QLW_QK 8
+__host__ __device__ constexpr int qlw_wave_bytes(int hcw) {
+    return ((8 * QLW_DC + 8 * hcw + 4 * (3 * QLW_DC + 1)) + 15) / 16 * 16;
 }
 
 template <int MODE>
 __global__ void __launch_bounds__(256) k_q_wave(DevGraph g, const i32 *__restrict__ list,
-                                                const GraphStats *__restrict__ st, int wc, i64 *Q) {
-    constexpr int HC = QL_WAVE_HC, DC = QL_WAVE_DC;
-    __shared__ i32 s_key[4][HC];
-    __shared__ i32 s_cnt[4][HC];
-    __shared__ i32 s_used[4][HC / 2];
-    __shared__ i32 s_nused[4];
-    __shared__ i32 s_off[4][DC + 1];
-    __shared__ i32 s_vv[4][DC];
-    __shared__ i32 s_beg[4][DC];
-    __shared__ i64 s_mid[4][DC];
+                                                const GraphStats *__restrict__ st, int wc, i64 *Q, int hcw) {
+    extern __shared__ __align__(16) char s_dyn[];
     const int w = threadIdx.x / WAVE, tid = lane_id();
-    for (int i = tid; i < HC; i += WAVE) {
-        s_key[w][i] = -1;
-        s_cnt[w][i] = 0;
-    }
-    if (tid == 0) s_nused[w] = 0;
-    item_sync<WAVE>();
-    QHash H{s_key[w], s_cnt[w], s_used[w], &s_nused[w], HC - 1};
-    QChunk C{s_off[w], s_vv[w], s_beg[w], s_mid[w]};
-    const i32 cnt = st->cnt[wc];
-    const int waves = gridDim.x * 4;
-    for (i32 it = blockIdx.x * 4 + w; it < cnt; it += waves)
-        q_item_hash<WAVE, MODE, QL_WAVE_HC / 2 / WAVE>(g, list[it], H, C, DC, tid, nullptr, nullptr, Q);
-}
-
-template <int MODE>
-__global__ void __launch_bounds__(256) k_q_block(DevGraph g, const i32 *__restrict__ list,
-                                                 const GraphStats *__restrict__ st, int wc, i64 *Q) {
-    constexpr int HC = QL_BLOCK_HC, DC = QL_BLOCK_DC;
-    __shared__ i32 s_key[HC];
-    __shared__ i32 s_cnt[HC];
-    __shared__ i32 s_used[HC / 2];
-    __shared__ i32 s_nused;
-    __shared__ i32 s_off[DC + 1];
-    __shared__ i32 s_vv[DC];
-    __shared__ i32 s_beg[DC];
-    __shared__ i64 s_mid[DC];
-    __shared__ i64 s_red[4];
-    __shared__ i32 s_red32[4];
-    for (int i = threadIdx.x; i < HC; i += 256) {
+    char *base = s_dyn + (size_t)w * qlw_wave_bytes(hcw);
+    i64 *s_mid = (i64 *)base;
+    i32 *s_key = (i32 *)(base + 8 * QLW_DC);
+    i32 *s_cnt = s_key + hcw;
+    i32 *s_off = s_cnt + hcw;
+    i32 *s_vv = s_off + QLW_DC + 1;
+    i32 *s_beg = s_vv + QLW_DC;
+    for (int i = tid; i < hcw; i += WAVE) {
         s_key[i] = -1;
         s_cnt[i] = 0;
     }
-    if (threadIdx.x == 0) s_nused = 0;
-    __syncthreads();
-    QHash H{s_key, s_cnt, s_used, &s_nused, HC - 1};
+    item_sync<WAVE>();
     QChunk C{s_off, s_vv, s_beg, s_mid};
     const i32 cnt = st->cnt[wc];
-    for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
-        q_item_hash<256, MODE, QL_BLOCK_HC / 2 / 256>(g, list[it], H, C, DC, threadIdx.x, s_red, s_red32, Q);
+    const int waves = gridDim.x * 4;
+    i32 it = blockIdx.x * 4 + w;
+    QMeta cur = q_meta<MODE>(g, it < cnt ? list[it] : -1);
+    i32 xn = it + waves < cnt ? list[it + waves] : -1;
+    for (; it < cnt; it += waves) {
+        // the next item's row bounds and the one after's id load while this one runs
+        const QMeta nxt = q_meta<MODE>(g, xn);
+        xn = it + 2 * waves < cnt ? list[it + 2 * waves] : -1;
+        const i64 need = 2 * cur.w;
+        const int hc = need >= hcw ? hcw : (need <= 64 ? 64 : (int)(1u << (32 - __clz((u32)(need - 1)))));
+        LightHash H{s_key, s_cnt, (u32)hc - 1};
+        q_sweeps<WAVE, MODE, QLW_QK>(g, cur, H, C, QLW_DC, tid, nullptr, Q);
+        i64 local = 0;
+        for (int j = tid; j < hc; j += WAVE) {
+            const i32 k = s_key[j];
+            if (k >= 0) {
+                const i64 c = s_cnt[j];
+                if (c >= 2) {
+                    const i64 cc = c * (c - 1) / 2;
+                    atomic_add_i64(&Q[k], cc);
+                    local += cc;
+                }
+                s_key[j] = -1;
+                s_cnt[j] = 0;
+            }
+        }
+        local = wave_sum64(local);
+        if (tid == 0 && local) atomic_add_i64(&Q[cur.x], local);
+        item_sync<WAVE>();
+        cur = nxt;
+    }
+}
+
+// Light items on one 256-thread workgroup: the same hash as the wave class, sized
+// per item, at most hcb entries (dynamic LDS given with the launch).
+#define QLB_DC 256
+#define QLB_NT 256
+__host__ __device__ constexpr int qlb_bytes(int hcb) {
+    return ((8 * QLB_DC + 8 * hcb + 4 * (3 * QLB_DC + 1)) + 15) / 16 * 16;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(QLB_NT) k_q_block(DevGraph g, const i32 *__restrict__ list,
+                                                    const GraphStats *__restrict__ st, int wc, i64 *Q, int hcb) {
+    extern __shared__ __align__(16) char s_dyn[];
+    __shared__ i64 s_red[QLB_NT / WAVE];
+    __shared__ i32 s_red32[QLB_NT / WAVE];
+    i64 *s_mid = (i64 *)s_dyn;
+    i32 *s_key = (i32 *)(s_dyn + 8 * QLB_DC);
+    i32 *s_cnt = s_key + hcb;
+    i32 *s_off = s_cnt + hcb;
+    i32 *s_vv = s_off + QLB_DC + 1;
+    i32 *s_beg = s_vv + QLB_DC;
+    for (int i = threadIdx.x; i < hcb; i += QLB_NT) {
+        s_key[i] = -1;
+        s_cnt[i] = 0;
+    }
+    __syncthreads();
+    QChunk C{s_off, s_vv, s_beg, s_mid};
+    const i32 cnt = st->cnt[wc];
+    i32 it = blockIdx.x;
+    QMeta cur = q_meta<MODE>(g, it < cnt ? list[it] : -1);
+    i32 xn = it + (i32)gridDim.x < cnt ? list[it + gridDim.x] : -1;
+    for (; it < cnt; it += gridDim.x) {
+        const QMeta nxt = q_meta<MODE>(g, xn);
+        xn = it + 2 * (i32)gridDim.x < cnt ? list[it + 2 * gridDim.x] : -1;
+        const i64 need = 2 * cur.w;
+        const int hc = need >= hcb ? hcb : (need <= 64 ? 64 : (int)(1u << (32 - __clz((u32)(need - 1)))));
+        LightHash H{s_key, s_cnt, (u32)hc - 1};
+        q_sweeps<QLB_NT, MODE, 16>(g, cur, H, C, QLB_DC, threadIdx.x, s_red32, Q);
+        i64 local = 0;
+        for (int j = threadIdx.x; j < hc; j += QLB_NT) {
+            const i32 k = s_key[j];
+            if (k >= 0) {
+                const i64 c = s_cnt[j];
+                if (c >= 2) {
+                    const i64 cc = c * (c - 1) / 2;
+                    atomic_add_i64(&Q[k], cc);
+                    local += cc;
+                }
+                s_key[j] = -1;
+                s_cnt[j] = 0;
+            }
+        }
+        local = item_sum<QLB_NT>(local, s_red, threadIdx.x);
+        if (threadIdx.x == 0 && local) atomic_add_i64(&Q[cur.x], local);
+        __syncthreads();
+        cur = nxt;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1018,14 +1112,16 @@ struct PackedHash {
 };
 
 template <int NT, int QK>
-__device__ __forceinline__ void qh_item_packed(const DevGraph &g, i32 x, const PackedHash &H0, int hc_max,
+__device__ __forceinline__ void qh_item_packed(const DevGraph &g, const QMeta &mt, const PackedHash &H0, int hc_max,
                                                const QChunk &C, int dc, int tid, i64 *red, i32 *red32,
                                                i64 *__restrict__ Q, i64 *__restrict__ prow) {
+    const i32 x = mt.x;
     // the table used is the smallest power of two holding twice the item's wedges
-    int hc = 64;
-    while (hc < hc_max && (i64)hc < 2 * g.wheavy[x]) hc <<= 1;
+    // (at least 64, at most hc_max)
+    const i64 need = 2 * mt.w;
+    const int hc = need >= hc_max ? hc_max : (need <= 64 ? 64 : (int)(1u << (32 - __clz((u32)(need - 1)))));
     PackedHash H{H0.tab, (u32)hc - 1, H0.h0};
-    q_sweeps<NT, Q_HEAVY, QK>(g, x, H, C, dc, tid, red32, Q);
+    q_sweeps<NT, Q_HEAVY, QK>(g, mt, H, C, dc, tid, red32, Q);
     i64 local = 0;
     for (int j = tid; j < hc; j += NT) {
         u32 cur = H.tab[j];
@@ -1069,8 +1165,15 @@ __global__ void __launch_bounds__(256) k_qh_wave(DevGraph g, const i32 *__restri
     i64 *prow = part + (i64)(blockIdx.x % QH_PART_ROWS) * K;
     const i32 cnt = st->cnt[WC_QH_WAVE];
     const int waves = gridDim.x * 4;
-    for (i32 it = blockIdx.x * 4 + w; it < cnt; it += waves)
-        qh_item_packed<WAVE, QHW_QK>(g, list[it], H, hcw, C, QHW_DC, tid, nullptr, nullptr, Q, prow);
+    i32 it = blockIdx.x * 4 + w;
+    QMeta cur = q_meta<Q_HEAVY>(g, it < cnt ? list[it] : -1);
+    i32 xn = it + waves < cnt ? list[it + waves] : -1;
+    for (; it < cnt; it += waves) {
+        const QMeta nxt = q_meta<Q_HEAVY>(g, xn);
+        xn = it + 2 * waves < cnt ? list[it + 2 * waves] : -1;
+        qh_item_packed<WAVE, QHW_QK>(g, cur, H, hcw, C, QHW_DC, tid, nullptr, nullptr, Q, prow);
+        cur = nxt;
+    }
 }
 
 #define QHB_HC 8192
@@ -1091,9 +1194,16 @@ __global__ void __launch_bounds__(QHB_NT) k_qh_block(DevGraph g, const i32 *__re
     QChunk C{s_off, s_vv, s_beg, s_mid};
     i64 *prow = part + (i64)(blockIdx.x % QH_PART_ROWS) * K;
     const i32 cnt = st->cnt[WC_QH_BLOCK];
-    for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
-        qh_item_packed<QHB_NT, QHB_HC / 2 / QHB_NT>(g, list[it], H, QHB_HC, C, QHB_DC, threadIdx.x, s_red, s_red32,
-                                                    Q, prow);
+    i32 it = blockIdx.x;
+    QMeta cur = q_meta<Q_HEAVY>(g, it < cnt ? list[it] : -1);
+    i32 xn = it + (i32)gridDim.x < cnt ? list[it + gridDim.x] : -1;
+    for (; it < cnt; it += gridDim.x) {
+        const QMeta nxt = q_meta<Q_HEAVY>(g, xn);
+        xn = it + 2 * (i32)gridDim.x < cnt ? list[it + 2 * gridDim.x] : -1;
+        qh_item_packed<QHB_NT, QHB_HC / 2 / QHB_NT>(g, cur, H, QHB_HC, C, QHB_DC, threadIdx.x, s_red, s_red32, Q,
+                                                    prow);
+        cur = nxt;
+    }
 }
 
 // part rows -> Q over the heavy range
@@ -1127,7 +1237,7 @@ __global__ void __launch_bounds__(QD_NT) k_q_dense(DevGraph g, const i32 *__rest
     const i32 cnt = st->cnt[WC_QH_DENSE];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x) {
         i32 x = list[it];
-        q_sweeps<QD_NT, Q_HEAVY, 16>(g, x, ctr, C, QD_DC, threadIdx.x, s_red32, Q);
+        q_sweeps<QD_NT, Q_HEAVY, 16>(g, q_meta<Q_HEAVY>(g, x), ctr, C, QD_DC, threadIdx.x, s_red32, Q);
         i64 local = 0;
         for (i32 i = threadIdx.x; i < KW; i += QD_NT) {
             u32 word = s_w[i];
@@ -1176,7 +1286,7 @@ __global__ void __launch_bounds__(QG_NT) k_q_global(DevGraph g, const i32 *__res
     const i32 cnt = st->cnt[wc];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x) {
         i32 x = list[it];
-        q_sweeps<QG_NT, MODE>(g, x, ctr, C, QG_DC, threadIdx.x, s_red32, Q);
+        q_sweeps<QG_NT, MODE>(g, q_meta<MODE>(g, x), ctr, C, QG_DC, threadIdx.x, s_red32, Q);
         __threadfence_block();
         const i32 nu = s_nused;
         i64 local = 0;
@@ -1275,13 +1385,22 @@ hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvar
 
 hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i64 *Q, i32 *gscratch,
                     i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, i64 *part, int part_rows,
-                    i64 qh_wave_bound, const KernelEvents &kev, hipStream_t s) {
+                    i64 ql_wave_bound, i64 ql_block_bound, i64 qh_wave_bound, const KernelEvents &kev,
+                    hipStream_t s) {
     KMARK(5);
-    hipLaunchKernelGGL(k_q_wave<Q_LIGHT>, dim3(grid_wave), dim3(256), 0, s, g, lists_host[WC_QL_WAVE], st,
-                       (int)WC_QL_WAVE, Q);
+    {
+        int hcw = 64;
+        while ((i64)hcw < 2 * ql_wave_bound) hcw <<= 1;
+        hipLaunchKernelGGL(k_q_wave<Q_LIGHT>, dim3(grid_wave), dim3(256), 4 * qlw_wave_bytes(hcw), s, g,
+                           lists_host[WC_QL_WAVE], st, (int)WC_QL_WAVE, Q, hcw);
+    }
     KMARK(6);
-    hipLaunchKernelGGL(k_q_block<Q_LIGHT>, dim3(grid_block), dim3(256), 0, s, g, lists_host[WC_QL_BLOCK], st,
-                       (int)WC_QL_BLOCK, Q);
+    {
+        int hcb = 64;
+        while ((i64)hcb < 2 * ql_block_bound) hcb <<= 1;
+        hipLaunchKernelGGL(k_q_block<Q_LIGHT>, dim3(grid_block), dim3(QLB_NT), qlb_bytes(hcb), s, g,
+                           lists_host[WC_QL_BLOCK], st, (int)WC_QL_BLOCK, Q, hcb);
+    }
     KMARK(7);
     if (gblocks > 0)
         hipLaunchKernelGGL(k_q_global<Q_LIGHT>, dim3(gblocks), dim3(QG_NT), 0, s, g, lists_host[WC_QL_GLOBAL], st,

@@ -73,10 +73,9 @@ struct Thresholds {
 // Class capacities (shared by classification and kernels).
 #define TRI_WAVE_CAP 64
 #define TRI_BLOCK_CAP 512
-#define QL_WAVE_HC 512      // hash entries per wave, light 4-cycle items (W <= HC/2)
+#define QL_WAVE_HC 4096     // largest hash per wave, light 4-cycle items (sized per launch)
 #define QL_WAVE_DC 64       // segment (row slot) capacity per wave item
-#define QL_BLOCK_HC 8192
-#define QL_BLOCK_DC 1024
+#define QL_BLOCK_HC 16384    // largest hash per workgroup, light 4-cycle items (sized per launch)
 #define QH_WAVE_HC 4096     // largest packed (key, count) table per wave (sized per launch)
 #define QH_BLOCK_HC 8192    // packed entries per workgroup
 #define QH_PART_ROWS 64     // rows of heavy-key credits (8 per XCD)
@@ -160,6 +159,7 @@ hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvar
                         hipStream_t s);
 hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i64 *Q, i32 *gscratch,
                     i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, i64 *part, int part_rows,
-                    i64 qh_wave_bound, const KernelEvents &kev, hipStream_t s);
+                    i64 ql_wave_bound, i64 ql_block_bound, i64 qh_wave_bound, const KernelEvents &kev,
+                    hipStream_t s);
 i64 probe_large_slice_bytes(int cap, int hc, i64 lds_max);
 #define PL_LDS_MAX (144 * 1024)  // largest dynamic LDS of the large probe kernel
