@@ -48,6 +48,79 @@ KERNEL_CLASS = {"probe_thread": "tri_thread", "probe_wave": "tri_wave", "probe_b
                 "qh_dense": "qh_dense", "qh_global": "qh_global"}
 
 
+# kernel names of the bench's per-kernel timings -> device symbol prefixes under rocprofv3
+PROF_NAME = {"probe_thread": "k_probe_thread<0>", "probe_wave": "k_probe_wave<0>", "probe_block": "k_probe_block<0>",
+             "probe_large": "k_probe_large<0,", "ql_wave": "k_q_wave<0>", "ql_block": "k_q_block<0>",
+             "ql_global": "k_q_global<0>", "qh_wave": "k_qh_wave", "qh_block": "k_qh_block",
+             "qh_dense": "k_q_dense", "qh_global": "k_q_global<1>"}
+CSRC = os.path.join(ROOT, "paper_2606_29651_amd", "csrc")
+
+
+def source_digest():
+    """sha256 over the kernel sources: byte counters taken on other sources are stale."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def _pmc_per_kernel(path):
+    """Counter sum and dispatch count per device symbol from a rocprofv3 counter CSV."""
+    import csv
+    tot, calls = {}, {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            name = r["Kernel_Name"].replace("void ", "", 1)
+            tot[name] = tot.get(name, 0.0) + float(r["Counter_Value"])
+            calls.setdefault(name, set()).add(r["Dispatch_Id"])
+    return {k: (tot[k], len(calls[k])) for k in tot}
+
+
+def traffic_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib):
+    """Text summary of HBM bytes per launch for each timed kernel, the counters scaled
+    by what they read for a copy of known size (copy_mib MiB read and written)."""
+    f, w = _pmc_per_kernel(fetch_csv), _pmc_per_kernel(write_csv)
+    cf, cw = _pmc_per_kernel(copy_fetch_csv), _pmc_per_kernel(copy_write_csv)
+    pick = lambda d: next(v for k, v in d.items() if "direct_copy_kernel" in k)
+    known_kib = copy_mib * 1024.0
+    (cfs, cfn), (cws, cwn) = pick(cf), pick(cw)
+    fscale, wscale = known_kib / (cfs / cfn), known_kib / (cws / cwn)
+    lines = [f"source_digest {source_digest()}", f"fetch_scale {fscale:.4f}", f"write_scale {wscale:.4f}"]
+    for short, sym in PROF_NAME.items():
+        fk = [v for k, v in f.items() if k.startswith(sym)]
+        wk = [v for k, v in w.items() if k.startswith(sym)]
+        if not fk or not wk:
+            continue
+        fb = fscale * 1024.0 * sum(x[0] for x in fk) / sum(x[1] for x in fk)
+        wb = wscale * 1024.0 * sum(x[0] for x in wk) / sum(x[1] for x in wk)
+        lines.append(f"kernel {short} fetch_bytes {fb:.0f} write_bytes {wb:.0f}")
+    return "\n".join(lines)
+
+
+def traffic_for(workload, kernel):
+    """HBM bytes per launch of kernel from profiles/traffic_<workload>.txt, or None when
+    there is no such summary or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    digest, rows = None, {}
+    with open(path) as fh:
+        for line in fh:
+            p = line.split()
+            if not p or p[0].startswith("#"):
+                continue
+            if p[0] == "source_digest":
+                digest = p[1]
+            elif p[0] == "kernel":
+                rows[p[1]] = int(p[3]) + int(p[5])
+    if digest != source_digest():
+        return None
+    return rows.get(kernel)
+
+
 def kernel_bytes(kernel, stats):
     cnt, work, slots = stats[KERNEL_CLASS[kernel]]
     if kernel.startswith("probe"):
@@ -273,10 +346,17 @@ def main():
     ap.add_argument("--er-series", default="default", choices=["default", "full", "none"],
                     help="Erdos-Renyi points timed with the forms: n = 4M at average degree 8, 16, 32 "
                          "(default), all of n in {1,2,4,8,16}M x degree {8,16,32} (full), or none")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV",
+                                                            "COPY_WRITE_CSV"),
+                    help="print the per-kernel HBM traffic summary from rocprofv3 --pmc counter CSVs of the "
+                         "bench (FETCH_SIZE, WRITE_SIZE) and of --copy-calibration 1024, then exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain int32->float32 copy of MIB MiB five times (reads and writes "
                          "MIB MiB each), to scale HBM byte counters taken under rocprofv3 --pmc")
     args = ap.parse_args()
+    if args.traffic_summary:
+        print(traffic_summary(*args.traffic_summary, copy_mib=1024))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
               file=sys.stderr)
@@ -303,7 +383,7 @@ def main():
     log("[bench] kernel ms " + json.dumps({k: round(v, 3) for k, v in kernel_ms.items()}))
     dom, bytes_dom, ach = roofline_of(kernel_ms, stats)
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_for(args.workload, dom),
             "kernel_ms": round(kernel_ms[dom], 4), "algorithmic_bytes": int(bytes_dom),
             "units": {"class": KERNEL_CLASS[dom], "items": stats[KERNEL_CLASS[dom]][0],
                       "work": stats[KERNEL_CLASS[dom]][1], "slots": stats[KERNEL_CLASS[dom]][2]}}
