@@ -287,7 +287,7 @@ def forms(args, ni, ctx, g, rp, cl, out, base_ms):
     d_srp, d_scol = torch.from_numpy(s_rp).cuda(), torch.from_numpy(s_col).cuda()
     s_out = torch.empty((int(s_off[-1]), 15), dtype=torch.int64, device="cuda")
     tctx = ni.Context(0)
-    cands = autotune.grid(heavy_k=[0, 4096, 32768], tri_wave=[32, 64], qh_wave=[256, 512], ql_wave=[128, 256])
+    cands = autotune.grid(heavy_k=[0, 4096, 32768], tri_wave=[32, 64], qh_wave=[256, 512, 1024], ql_wave=[256, 512])
     tuned = autotune.tune(tctx, lambda: ni.count_batched(s_off, d_srp, d_scol, out=s_out, ctx=tctx), cands,
                           repeats=2)
     autotune.save(TUNE_FILE, "batch_mix", {"best": tuned["best"], "ms_on_tenth": tuned["ms"]})

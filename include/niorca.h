@@ -82,12 +82,16 @@ uint64_t niorca_workspace_bytes(const niorca_ctx *ctx);
  *   "tri_block" 1..512   ... up to this one workgroup with LDS; above, global scratch
  *   "ql_wave"   0..2048  4-cycle wedges (largest vertex light) up to this: wave hash
  *                        (default 512; the per-wave table is sized from it)
- *   "ql_block"  0..8192  ... up to this: workgroup hash (default 4096, table sized
+ *   "ql_block"  0..8192  ... up to this: workgroup hash (default 8192, table sized
  *                        from it); above: global counters
+ *   "ql_split"  0..8192  workgroup items up to this many wedges run in a launch of
+ *                        their own with smaller tables (default 2048)
  *   "qh_wave"   0..2048  4-cycle wedges opposite a heavy largest vertex: wave hash
  *                        (default 1024; the per-wave table is sized from it)
- *   "qh_block"  0..4096  ... workgroup hash; above: dense LDS counters
- *   "heavy_k"   0..32768 how many top-ranked vertices form the heavy range
+ *   "qh_block"  0..4096  ... workgroup hash (default 2048); above: dense LDS counters
+ *   "heavy_k"   -1..32768 how many top-ranked vertices form the heavy range; -1
+ *                        (default): 32768 when the maximum degree exceeds 8x the
+ *                        mean degree, else 0; 4096 in niorca_count_batched
  *   "bin_deg_thread" (NIORCA_BIN_DEGREE) degree up to which a vertex with |N+| <= 8
  *               goes to the one-lane Stage I class (default 16)
  *   "bin_deg_block"  (NIORCA_BIN_DEGREE) degree from which a vertex goes to the

@@ -34,8 +34,9 @@ struct niorca_ctx {
     bool ev_valid = false;
     // tunable class thresholds and the size of the heavy 4-cycle key range
     Thresholds th{TRI_WAVE_CAP, TRI_BLOCK_CAP, 0, 16, 4096, 0.f, 0.f, nullptr,
-                  512, 4096, 1024, QH_BLOCK_HC / 2};
-    int32_t heavy_k = QH_DENSE_K;
+                  512, 8192, 1024, 2048, 2048};
+    // size of the heavy 4-cycle key range; -1 = chosen per call from the degrees
+    int32_t heavy_k = -1;
     // the last captured batched sequence and the shape it was captured for
     hipGraphExec_t gexec = nullptr;
     uint64_t gkey = 0;
@@ -144,7 +145,7 @@ extern "C" niorca_status niorca_set_param(niorca_ctx *ctx, const char *name, int
                     (long long)lo, (long long)hi);
     };
     if (k == "heavy_k") {
-        if (value < 0 || value > QH_DENSE_K) return bad(0, QH_DENSE_K);
+        if (value < -1 || value > QH_DENSE_K) return bad(-1, QH_DENSE_K);
         ctx->heavy_k = (int32_t)value;
     } else if (k == "tri_cache") {
         if (value < 0 || value > ((int64_t)1 << 34)) return bad(0, (int64_t)1 << 34);
@@ -170,6 +171,9 @@ extern "C" niorca_status niorca_set_param(niorca_ctx *ctx, const char *name, int
     } else if (k == "qh_wave") {
         if (value < 0 || value > QH_WAVE_HC / 2) return bad(0, QH_WAVE_HC / 2);
         ctx->th.qh_wave = value;
+    } else if (k == "ql_split") {
+        if (value < 0 || value > QL_BLOCK_HC / 2) return bad(0, QL_BLOCK_HC / 2);
+        ctx->th.ql_split = value;
     } else if (k == "large_lds") {
         if (value < 0 || value > PL_LDS_MAX) return bad(0, PL_LDS_MAX);
         ctx->large_lds_max = value;
@@ -335,13 +339,23 @@ static void layout_base(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz
     L.base_end = A.off;
 }
 
-static void layout_rest(Layout &L, const niorca_ctx *ctx, int32_t n, int dplus_max, i64 pairs, bool bounded,
-                        Arena &A) {
+// The heavy 4-cycle range: the top QH_DENSE_K ranks when the graph has hubs (maximum
+// degree above 8x the mean), none otherwise; batched runs (no statistics) use 4096.
+static int32_t heavy_range(const niorca_ctx *ctx, int32_t n, int64_t nnz, int dmax, bool bounded) {
+    if (ctx->heavy_k >= 0) return ctx->heavy_k;
+    if (bounded) return 4096;
+    const int64_t mean = n > 0 ? nnz / n : 0;
+    return (int64_t)dmax > 8 * (mean > 1 ? mean : 1) ? QH_DENSE_K : 0;
+}
+
+static void layout_rest(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz, int dmax, int dplus_max,
+                        i64 pairs, bool bounded, Arena &A) {
     const int cu = ctx->num_cu;
     // triangle records for the tau pass: no more than the graph can have
     L.tc_cap = ctx->tri_cache_records < pairs ? ctx->tri_cache_records : pairs;
     L.tcrec = A.take<u64>((uint64_t)(L.tc_cap > 0 ? L.tc_cap : 1));
-    L.h0 = n > ctx->heavy_k ? n - ctx->heavy_k : 0;
+    const int32_t hk = heavy_range(ctx, n, nnz, dmax, bounded);
+    L.h0 = n > hk ? n - hk : 0;
     // vertices with |N+| above the workgroup threshold go to the global-scratch class
     L.large_cap = dplus_max > ctx->th.tri_block ? dplus_max : 0;
     L.large_hc = 1;
@@ -392,7 +406,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     Layout L;
     Arena A;
     layout_base(L, ctx, n, nnz, flags, A);
-    if (hb) layout_rest(L, ctx, n, hb->dplus_max, BOUNDED_TRI_CACHE, true, A);
+    if (hb) layout_rest(L, ctx, n, nnz, hb->dmax, hb->dplus_max, BOUNDED_TRI_CACHE, true, A);
     const uint64_t need_now = hb ? A.off : L.base_end;
 
     // Validation first (it reads only the input).
@@ -454,7 +468,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
             return fail(ctx, NIORCA_EOVERFLOW, "maximum degree %d could overflow int64 counts", hs.dmax);
         if (hs.dplus_max > LSORT_CAP)
             return fail(ctx, NIORCA_ENOTIMPL, "an oriented out-degree of %d exceeds %d", hs.dplus_max, LSORT_CAP);
-        layout_rest(L, ctx, n, hs.dplus_max, hs.pairs, false, A);
+        layout_rest(L, ctx, n, nnz, hs.dmax, hs.dplus_max, hs.pairs, false, A);
         niorca_status st = ensure_ws(ctx, A.off);
         if (st) return st;
         // The workspace grew and moved: start again; this time it is large enough.
@@ -545,7 +559,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     STAGE_MARK(7);
     if (n - h0 > 0) HIP_TRY(fill32(qpart, (i64)sizeof(i64) * L.part_rows * (n - h0), 0u, s));
     HIP_TRY(launch_q(g, lh, dst, acc.Q, gscratch, L.gslice, L.gblocks, cu * 4, cu * 4, cu * 2, qpart, L.part_rows,
-                     th.ql_wave, th.ql_block, th.qh_wave, kev, s));
+                     th.ql_wave, th.ql_block, th.ql_split, th.qh_wave, kev, s));
     STAGE_MARK(8);
     // ---- Stage III-b: equations ----
     HIP_TRY(launch_solve(g, acc, o.psi, o.fvars, dst, cu * 8, s));
@@ -676,7 +690,7 @@ extern "C" niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graph
     Layout L;
     Arena A;
     layout_base(L, ctx, n, nnz, flags, A);
-    layout_rest(L, ctx, n, hb.dplus_max, BOUNDED_TRI_CACHE, true, A);
+    layout_rest(L, ctx, n, nnz, hb.dmax, hb.dplus_max, BOUNDED_TRI_CACHE, true, A);
     L.colg = A.take<int32_t>(nnz + 64);
     L.voff = A.take<int64_t>(num_graphs + 1);
     st = ensure_ws(ctx, A.off);
@@ -698,7 +712,8 @@ extern "C" niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graph
                        (uint64_t)(uintptr_t)col, (uint64_t)(uintptr_t)out, (uint64_t)(uintptr_t)ctx->ws,
                        ctx->ws_bytes, vh, (uint64_t)ctx->heavy_k, (uint64_t)ctx->tri_cache_records,
                        (uint64_t)ctx->th.tri_wave, (uint64_t)ctx->th.tri_block, (uint64_t)ctx->th.ql_wave,
-                       (uint64_t)ctx->th.ql_block, (uint64_t)ctx->th.qh_wave, (uint64_t)ctx->th.qh_block})
+                       (uint64_t)ctx->th.ql_block, (uint64_t)ctx->th.qh_wave, (uint64_t)ctx->th.qh_block,
+                       (uint64_t)ctx->th.ql_split, (uint64_t)ctx->large_lds_max})
         key = mix64(key, v);
     if (!ctx->gexec || ctx->gkey != key) {
         if (ctx->gexec) {

@@ -1014,9 +1014,12 @@ __host__ __device__ constexpr int qlb_bytes(int hcb) {
     return ((8 * QLB_DC + 8 * hcb + 4 * (3 * QLB_DC + 1)) + 15) / 16 * 16;
 }
 
+// Items of the list with wlo < wedges <= whi only (the class is split into two
+// launches with different table sizes, so that small items keep a high occupancy).
 template <int MODE>
 __global__ void __launch_bounds__(QLB_NT) k_q_block(DevGraph g, const i32 *__restrict__ list,
-                                                    const GraphStats *__restrict__ st, int wc, i64 *Q, int hcb) {
+                                                    const GraphStats *__restrict__ st, int wc, i64 *Q, int hcb,
+                                                    i64 wlo, i64 whi) {
     extern __shared__ __align__(16) char s_dyn[];
     __shared__ i64 s_red[QLB_NT / WAVE];
     __shared__ i32 s_red32[QLB_NT / WAVE];
@@ -1039,6 +1042,10 @@ __global__ void __launch_bounds__(QLB_NT) k_q_block(DevGraph g, const i32 *__res
     for (; it < cnt; it += gridDim.x) {
         const QMeta nxt = q_meta<MODE>(g, xn);
         xn = it + 2 * (i32)gridDim.x < cnt ? list[it + 2 * gridDim.x] : -1;
+        if (cur.w <= wlo || cur.w > whi) {
+            cur = nxt;
+            continue;
+        }
         const i64 need = 2 * cur.w;
         const int hc = need >= hcb ? hcb : (need <= 64 ? 64 : (int)(1u << (32 - __clz((u32)(need - 1)))));
         LightHash H{s_key, s_cnt, (u32)hc - 1};
@@ -1385,8 +1392,8 @@ hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvar
 
 hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i64 *Q, i32 *gscratch,
                     i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, i64 *part, int part_rows,
-                    i64 ql_wave_bound, i64 ql_block_bound, i64 qh_wave_bound, const KernelEvents &kev,
-                    hipStream_t s) {
+                    i64 ql_wave_bound, i64 ql_block_bound, i64 ql_split, i64 qh_wave_bound,
+                    const KernelEvents &kev, hipStream_t s) {
     KMARK(5);
     {
         int hcw = 64;
@@ -1396,10 +1403,24 @@ hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats 
     }
     KMARK(6);
     {
-        int hcb = 64;
-        while ((i64)hcb < 2 * ql_block_bound) hcb <<= 1;
-        hipLaunchKernelGGL(k_q_block<Q_LIGHT>, dim3(grid_block), dim3(QLB_NT), qlb_bytes(hcb), s, g,
-                           lists_host[WC_QL_BLOCK], st, (int)WC_QL_BLOCK, Q, hcb);
+        // two launches: items up to ql_split wedges with small tables (several
+        // workgroups per CU), the larger ones with tables for ql_block wedges
+        const i64 split = ql_split < ql_block_bound ? ql_split : ql_block_bound;
+        auto table_for = [](i64 w) {
+            int h = 64;
+            while ((i64)h < 2 * w) h <<= 1;
+            return h;
+        };
+        if (split > 0) {
+            const int hcb = table_for(split);
+            hipLaunchKernelGGL(k_q_block<Q_LIGHT>, dim3(grid_block), dim3(QLB_NT), qlb_bytes(hcb), s, g,
+                               lists_host[WC_QL_BLOCK], st, (int)WC_QL_BLOCK, Q, hcb, (i64)-1, split);
+        }
+        if (split < ql_block_bound) {
+            const int hcb = table_for(ql_block_bound);
+            hipLaunchKernelGGL(k_q_block<Q_LIGHT>, dim3(grid_block), dim3(QLB_NT), qlb_bytes(hcb), s, g,
+                               lists_host[WC_QL_BLOCK], st, (int)WC_QL_BLOCK, Q, hcb, split, ql_block_bound);
+        }
     }
     KMARK(7);
     if (gblocks > 0)

@@ -66,6 +66,7 @@ struct Thresholds {
     i64 ql_block;    // wedges <= ql_block -> workgroup hash (<= QL_BLOCK_HC/2)
     i64 qh_wave;
     i64 qh_block;
+    i64 ql_split;    // light workgroup items up to this many wedges use the small-table launch
 };
 
 #define NUM_COUNTERS 7   // per-vertex work counters (see include/niorca.h)
@@ -159,7 +160,7 @@ hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvar
                         hipStream_t s);
 hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i64 *Q, i32 *gscratch,
                     i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, i64 *part, int part_rows,
-                    i64 ql_wave_bound, i64 ql_block_bound, i64 qh_wave_bound, const KernelEvents &kev,
-                    hipStream_t s);
+                    i64 ql_wave_bound, i64 ql_block_bound, i64 ql_split, i64 qh_wave_bound,
+                    const KernelEvents &kev, hipStream_t s);
 i64 probe_large_slice_bytes(int cap, int hc, i64 lds_max);
 #define PL_LDS_MAX (144 * 1024)  // largest dynamic LDS of the large probe kernel

@@ -140,6 +140,7 @@ FORCED = {
     "q_global_light": dict(ql_wave=0, ql_block=0, heavy_k=0),
     "q_block_light": dict(ql_wave=0, heavy_k=0),
     "q_block_light_max": dict(ql_wave=0, ql_block=8192, heavy_k=0),
+    "q_block_light_split": dict(ql_wave=0, ql_block=8192, ql_split=64, heavy_k=0),
     "q_wave_light_max": dict(ql_wave=2048, heavy_k=0),
     "q_dense_heavy": dict(qh_wave=0, qh_block=0, heavy_k=32768),
     "q_block_heavy": dict(qh_wave=0, heavy_k=32768),
