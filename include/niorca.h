@@ -100,9 +100,10 @@ uint64_t niorca_workspace_bytes(const niorca_ctx *ctx);
  *                        each, default 2^32; a call reserves no more than the sum over
  *                        vertices of C(|N+|, 2); vertices whose triangles do not fit
  *                        are probed again)
- *   "large_lds" 0..147456 LDS bytes the |N+| > tri_block class may use for its hash
- *                        and per-slot arrays (default 147456; beyond it they live in
- *                        global scratch)
+ *   "large_lds" 0..153600 LDS bytes the |N+| > tri_block class may use (default
+ *                        153600): hash and per-slot arrays, and for the 4-clique pass
+ *                        a copy of the bitset of H_u when that fits too; what does not
+ *                        fit lives in global scratch
  * Returns EINVAL for an unknown name or a value out of range. */
 niorca_status niorca_set_param(niorca_ctx *ctx, const char *name, int64_t value);
 

@@ -365,9 +365,14 @@ static void layout_rest(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz
     L.large = A.take<char>((uint64_t)L.large_slice * L.large_blocks);
     L.part_rows = QH_PART_ROWS;
     L.part = A.take<i64>((uint64_t)L.part_rows * (uint64_t)(n - L.h0));
-    // int32 counters over all vertices for the rare 4-cycle items that overflow LDS;
-    // fewer workgroups on very large graphs keep this region small
-    L.gblocks = bounded ? 2 : (n <= (1 << 22) ? 32 : 8);
+    // int32 counters over all vertices for the rare 4-cycle items that overflow LDS
+    if (bounded) {
+        L.gblocks = 2;
+    } else {
+        // one slice per CU, within 8 GiB of the 288 GB
+        const i64 fit = ((i64)8 << 30) / ((2 * (i64)n + 64) * 4);
+        L.gblocks = (int)(fit < cu ? (fit < 8 ? 8 : fit) : cu);
+    }
     L.gslice = 2 * (i64)n + 64;
     L.gcnt = A.take<i32>((uint64_t)L.gslice * L.gblocks);
     L.total = A.off;

@@ -33,11 +33,14 @@ __device__ __forceinline__ int wave_incl_sum(int v) {
 // Adds, for every run of consecutive lanes holding the same index si, the run's
 // total of val to dst[si] with one atomic (issued by the run's last lane).  All 64
 // lanes active; lanes with nothing to add pass val = 0.  Values of 2^24 or more are
-// added on their own, so that the 32-bit run sums cannot overflow.
-__device__ __forceinline__ void wave_run_add(i64 *dst, int si, int val) {
+// added on their own, so that the 32-bit run sums cannot overflow.  dst is int64 or
+// int32 (then the caller keeps every sum within int32).
+template <typename T>
+__device__ __forceinline__ void wave_run_add(T *dst, int si, int val) {
     const int lane = lane_id();
     if (val >= (1 << 24)) {
-        atomicAdd((unsigned long long *)&dst[si], (unsigned long long)(i64)val);
+        if constexpr (sizeof(T) == 8) atomicAdd((unsigned long long *)&dst[si], (unsigned long long)(i64)val);
+        else atomicAdd(&dst[si], (T)val);
         val = 0;
     }
     const int incl = wave_incl_sum(val);
@@ -48,7 +51,10 @@ __device__ __forceinline__ void wave_run_add(i64 *dst, int si, int val) {
     const int head = 63 - __clzll((long long)upto);
     const int before = __shfl(incl, head > 0 ? head - 1 : 0, WAVE);
     const int tot = incl - (head > 0 ? before : 0);
-    if (last && tot) atomicAdd((unsigned long long *)&dst[si], (unsigned long long)(i64)tot);
+    if (last && tot) {
+        if constexpr (sizeof(T) == 8) atomicAdd((unsigned long long *)&dst[si], (unsigned long long)(i64)tot);
+        else atomicAdd(&dst[si], (T)tot);
+    }
 }
 
 __device__ __forceinline__ i64 wave_sum64(i64 v) {

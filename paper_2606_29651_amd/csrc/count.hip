@@ -187,6 +187,8 @@ struct ProbeMem {
     i32 *tcnt;   // [cap]
     u32 *A;      // [cap*words]
     i64 *acc;    // [cap]
+    u32 *A_k4;   // where the 4-clique pass reads the bitset: A itself, or an LDS copy
+                 // taken after the probes (over the then unused hash and slot arrays)
 };
 
 // Triangle records kept by Stage I for the tau pass: one u64 per triangle found at
@@ -247,13 +249,26 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
         item_sync<NT>();
         const i64 r0 = pm.toff, r1 = r0 + pm.tcnt;
         i64 tau_local = 0;
-        for (i64 r = r0 + tid; r < r1; r += NT) {
-            u64 rec = tc.rec[r];
-            int i = (int)(rec & 0xffffu), p = (int)((rec >> 16) & 0xffffu);
-            i32 q = (i32)(rec >> 32);
-            tau_local += t[q];
-            atomicAdd((unsigned long long *)&M.acc[i], (unsigned long long)M.tcnt[p]);
-            atomicAdd((unsigned long long *)&M.acc[p], (unsigned long long)M.tcnt[i]);
+        // four records per thread in flight; records of one probe batch are stored
+        // in lane order, so runs of lanes share i and add to acc[i] once per run
+        for (i64 rb = r0; rb < r1; rb += (i64)NT * 4) {
+            u64 rec[4];
+            i32 tq[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const i64 r = rb + tid + (i64)k * NT;
+                rec[k] = r < r1 ? tc.rec[r] : ~0ull;
+            }
+#pragma unroll
+            for (int k = 0; k < 4; k++) tq[k] = rec[k] != ~0ull ? t[(i32)(rec[k] >> 32)] : 0;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const bool ok = rec[k] != ~0ull;
+                const int i = ok ? (int)(rec[k] & 0xffffu) : 0, p = ok ? (int)((rec[k] >> 16) & 0xffffu) : 0;
+                tau_local += tq[k];
+                wave_run_add(M.acc, i, ok ? M.tcnt[p] : 0);
+                if (ok) atomicAdd((unsigned long long *)&M.acc[p], (unsigned long long)M.tcnt[i]);
+            }
         }
         item_sync<NT>();
         for (int j = tid; j < du; j += NT) {
@@ -329,16 +344,18 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
         for (int j = 0; j < QP; j++) ww[j] = qq[j] >= 0 ? g.ncol[qq[j]] : -1;
 #pragma unroll
         for (int j = 0; j < QP; j++) {
-            if (ww[j] < 0) continue;
+            if (j >= nj) break;
             const int i = lo[j];
             const i32 q = qq[j], w = ww[j];
-            u32 sl = hslot((u32)w, hmask);
             int p = -1;
-            while (true) {
-                i32 k = M.hkey[sl];
-                if (k == w) { p = M.hpos[sl]; break; }
-                if (k == -1) break;
-                sl = (sl + 1) & hmask;
+            if (w >= 0) {
+                u32 sl = hslot((u32)w, hmask);
+                while (true) {
+                    i32 k = M.hkey[sl];
+                    if (k == w) { p = M.hpos[sl]; break; }
+                    if (k == -1) break;
+                    sl = (sl + 1) & hmask;
+                }
             }
             if (p < 0) continue;
             if (MODE == PROBE_TRI) {
@@ -374,15 +391,23 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
             i32 c = M.tcnt[j];
             tri2 += c;
             if (c) atomicAdd(&t[base + j], c);
+        }
+        const u32 *A = M.A_k4;
+        if (A != M.A) {
+            item_sync<NT>();
+            for (int i = tid; i < du * words; i += NT) M.A_k4[i] = M.A[i];
+            item_sync<NT>();
+        }
+        for (int j = tid; j < du; j += NT) {
             i64 sj = 0;
             for (int wd = 0; wd < nw; wd++) {
-                u32 bits = M.A[j * words + wd];
+                u32 bits = A[j * words + wd];
                 while (bits) {
                     int b = __ffs(bits) - 1;
                     bits &= bits - 1;
                     int i = wd * 32 + b;
                     words_scanned += nw;
-                    for (int k = 0; k < nw; k++) sj += __popc(M.A[i * words + k] & M.A[j * words + k]);
+                    for (int k = 0; k < nw; k++) sj += __popc(A[i * words + k] & A[j * words + k]);
                 }
             }
             // sj = 2 x (triangles of H_u through j) = 2 x (4-cliques containing u and nb[j])
@@ -429,7 +454,7 @@ __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__res
     __shared__ i64 s_acc[4][CAP];
     __shared__ ItemState s_st[4];
     const int w = threadIdx.x / WAVE, tid = lane_id();
-    ProbeMem M{s_hkey[w], s_hpos[w], s_off[w], s_nb[w], s_beg[w], s_tcnt[w], s_A[w], s_acc[w]};
+    ProbeMem M{s_hkey[w], s_hpos[w], s_off[w], s_nb[w], s_beg[w], s_tcnt[w], s_A[w], s_acc[w], s_A[w]};
     if (tid == 0) {
         s_st[w].chunk_cur = s_st[w].chunk_end = 0;
         s_st[w].full = 0;
@@ -468,7 +493,7 @@ __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__
     __shared__ i64 s_red[PB_NT / WAVE];
     __shared__ i32 s_red32[PB_NT / WAVE];
     __shared__ ItemState s_st;
-    ProbeMem M{s_hkey, s_hpos, s_off, s_nb, s_beg, s_tcnt, s_A, s_acc};
+    ProbeMem M{s_hkey, s_hpos, s_off, s_nb, s_beg, s_tcnt, s_A, s_acc, s_A};
     if (threadIdx.x == 0) {
         s_st.chunk_cur = s_st.chunk_end = 0;
         s_st.full = 0;
@@ -574,34 +599,54 @@ __global__ void __launch_bounds__(256) k_probe_thread(DevGraph g, const i32 *__r
     }
 }
 
-// |N+(u)| > TRI_BLOCK_CAP: the same item code with larger structures.  The hash of
-// N+(u) and the per-slot arrays live in dynamic LDS when they fit (LDSH), else in
-// the workgroup's global scratch slice; the bitset of H_u and the tau sums always
-// live in the slice.
+// |N+(u)| > TRI_BLOCK_CAP: the same item code with larger structures, 1024 threads.
+// Layouts (LAY): 2 -- hash and per-slot arrays in dynamic LDS during the probes, the
+// bitset of H_u built in the global slice and copied into the same LDS (over the
+// hash) for the 4-clique pass; 1 -- as 2 but the 4-clique pass reads the global
+// bitset; 0 -- everything but the reductions in the global slice.
+#define PL_NT 1024
 __host__ __device__ inline i64 probe_large_lds_bytes(int cap, int hc) {
     return (i64)sizeof(i32) * (2 * (i64)hc + 4 * (i64)cap + 1);
 }
+__host__ __device__ inline i64 probe_large_k4_bytes(int cap, int hc) {
+    const i64 words = (cap + 31) / 32;
+    const i64 probe = (i64)sizeof(i32) * (2 * (i64)hc + 3 * (i64)cap + 1);
+    const i64 k4 = (i64)sizeof(u32) * cap * words;
+    return (i64)sizeof(i32) * cap + (probe > k4 ? probe : k4);
+}
 
-template <int MODE, bool LDSH>
-__global__ void __launch_bounds__(256) k_probe_large(DevGraph g, const i32 *__restrict__ list,
-                                                     const GraphStats *__restrict__ st, i32 *t, i64 *K4,
-                                                     i64 *tau, TriCache tc, char *scratch, i64 slice_bytes,
-                                                     int cap, int hc, i64 *counters) {
+template <int MODE, int LAY>
+__global__ void __launch_bounds__(PL_NT) k_probe_large(DevGraph g, const i32 *__restrict__ list,
+                                                       const GraphStats *__restrict__ st, i32 *t, i64 *K4,
+                                                       i64 *tau, TriCache tc, char *scratch, i64 slice_bytes,
+                                                       int cap, int hc, i64 *counters) {
     extern __shared__ __align__(16) char s_dyn[];
-    __shared__ i64 s_red[4];
-    __shared__ i32 s_red32[4];
+    __shared__ i64 s_red[PL_NT / WAVE];
+    __shared__ i32 s_red32[PL_NT / WAVE];
     const int words = (cap + 31) / 32;
     char *p = scratch + (i64)blockIdx.x * slice_bytes;
     ProbeMem M;
     M.acc = (i64 *)p; p += sizeof(i64) * cap;
     M.A = (u32 *)p; p += sizeof(u32) * (i64)cap * words;
-    char *q = LDSH ? s_dyn : p;
-    M.hkey = (i32 *)q; q += sizeof(i32) * hc;
-    M.hpos = (i32 *)q; q += sizeof(i32) * hc;
-    M.off = (i32 *)q; q += sizeof(i32) * (cap + 1);
-    M.nb = (i32 *)q; q += sizeof(i32) * cap;
-    M.beg = (i32 *)q; q += sizeof(i32) * cap;
-    M.tcnt = (i32 *)q;
+    M.A_k4 = M.A;
+    if (LAY == 2) {
+        M.nb = (i32 *)s_dyn;
+        char *q = s_dyn + sizeof(i32) * cap;
+        M.A_k4 = (u32 *)q;
+        M.hkey = (i32 *)q; q += sizeof(i32) * hc;
+        M.hpos = (i32 *)q; q += sizeof(i32) * hc;
+        M.off = (i32 *)q; q += sizeof(i32) * (cap + 1);
+        M.beg = (i32 *)q; q += sizeof(i32) * cap;
+        M.tcnt = (i32 *)q;
+    } else {
+        char *q = LAY == 1 ? s_dyn : p;
+        M.hkey = (i32 *)q; q += sizeof(i32) * hc;
+        M.hpos = (i32 *)q; q += sizeof(i32) * hc;
+        M.off = (i32 *)q; q += sizeof(i32) * (cap + 1);
+        M.nb = (i32 *)q; q += sizeof(i32) * cap;
+        M.beg = (i32 *)q; q += sizeof(i32) * cap;
+        M.tcnt = (i32 *)q;
+    }
     __shared__ ItemState s_st;
     if (threadIdx.x == 0) {
         s_st.chunk_cur = s_st.chunk_end = 0;
@@ -610,9 +655,8 @@ __global__ void __launch_bounds__(256) k_probe_large(DevGraph g, const i32 *__re
     __syncthreads();
     const i32 cnt = st->cnt[WC_TRI_LARGE];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
-        probe_item<256, MODE, 4>(g, p_meta<MODE>(g, tc, list[it]), threadIdx.x, M, hc, words, t, K4, tau, s_red,
-                                 s_red32, tc, &s_st,
-                                 counters);
+        probe_item<PL_NT, MODE, 4>(g, p_meta<MODE>(g, tc, list[it]), threadIdx.x, M, hc, words, t, K4, tau, s_red,
+                                   s_red32, tc, &s_st, counters);
 }
 
 i64 probe_large_slice_bytes(int cap, int hc, i64 lds_max) {
@@ -1331,12 +1375,16 @@ template <int MODE>
 static void launch_large(const DevGraph &g, const i32 *list, const GraphStats *st, i32 *t, i64 *K4, i64 *tau,
                          const TriCache &tc, char *scratch, i64 slice, int cap, int hc, int blocks, i64 lds_max,
                          i64 *counters, hipStream_t s) {
-    const i64 lds = probe_large_lds_bytes(cap, hc);
-    if (lds <= lds_max)
-        hipLaunchKernelGGL((k_probe_large<MODE, true>), dim3(blocks), dim3(256), (size_t)lds, s, g, list, st, t, K4,
+    const i64 k4 = probe_large_k4_bytes(cap, hc), lds = probe_large_lds_bytes(cap, hc);
+    if (k4 <= lds_max)  // one workgroup per CU fits: launch no more than that
+        hipLaunchKernelGGL((k_probe_large<MODE, 2>), dim3((blocks + 1) / 2), dim3(PL_NT), (size_t)k4, s, g, list, st,
+                           t, K4,
+                           tau, tc, scratch, slice, cap, hc, counters);
+    else if (lds <= lds_max)
+        hipLaunchKernelGGL((k_probe_large<MODE, 1>), dim3(blocks), dim3(PL_NT), (size_t)lds, s, g, list, st, t, K4,
                            tau, tc, scratch, slice, cap, hc, counters);
     else
-        hipLaunchKernelGGL((k_probe_large<MODE, false>), dim3(blocks), dim3(256), 0, s, g, list, st, t, K4, tau, tc,
+        hipLaunchKernelGGL((k_probe_large<MODE, 0>), dim3(blocks), dim3(PL_NT), 0, s, g, list, st, t, K4, tau, tc,
                            scratch, slice, cap, hc, counters);
 }
 

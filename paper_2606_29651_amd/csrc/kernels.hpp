@@ -163,4 +163,4 @@ hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats 
                     i64 ql_wave_bound, i64 ql_block_bound, i64 ql_split, i64 qh_wave_bound,
                     const KernelEvents &kev, hipStream_t s);
 i64 probe_large_slice_bytes(int cap, int hc, i64 lds_max);
-#define PL_LDS_MAX (144 * 1024)  // largest dynamic LDS of the large probe kernel
+#define PL_LDS_MAX (150 * 1024)  // largest dynamic LDS of the large probe kernel

@@ -187,13 +187,24 @@ def kn_row(n):
             d * comb(d - 1, 2), comb(d, 3)]
 
 
-@pytest.mark.parametrize("n", [600, 1500])
-def test_complete_graph_closed_form(ni, n):
-    """K_n: every vertex has the same 15 counts, derived by counting (no oracle)."""
+@pytest.mark.parametrize("n,large_lds", [(600, None), (1500, None), (600, 30000), (600, 0)])
+def test_complete_graph_closed_form(ni, n, large_lds):
+    """K_n: every vertex has the same 15 counts, derived by counting (no oracle).
+    |N+| reaches n-1 > 512, so the top vertices use the large class; large_lds picks
+    its layout (default: bitset copied to LDS for the 4-clique pass; 30000: hash in
+    LDS, bitset in global memory; 0: all in global memory)."""
     g = gg.complete(n)
-    _say(f"[gpu] K{n} closed form")
-    rp, cl = _dev(g)
-    got = ni.count(rp, cl).cpu().numpy()
+    _say(f"[gpu] K{n} closed form, large_lds={large_lds}")
+    ctx = ni.Context(0)
+    try:
+        if large_lds is not None:
+            ctx.set_param("large_lds", large_lds)
+        rp, cl = _dev(g)
+        got = ni.count(rp, cl, ctx=ctx).cpu().numpy()
+    finally:
+        import torch
+        torch.cuda.synchronize()
+        ctx.close()
     assert (got == np.array(kn_row(n), dtype=np.int64)).all()
 
 
