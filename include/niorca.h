@@ -84,8 +84,9 @@ uint64_t niorca_workspace_bytes(const niorca_ctx *ctx);
  *                        (default 512; the per-wave table is sized from it)
  *   "ql_block"  0..8192  ... up to this: workgroup hash (default 8192, table sized
  *                        from it); above: global counters
- *   "ql_split"  0..8192  workgroup items up to this many wedges run in a launch of
- *                        their own with smaller tables (default 2048)
+ *   "ql_split"  0..8192  the workgroup class runs in launches by wedge count:
+ *                        up to ql_split, then windows doubling up to ql_block, each
+ *                        with tables sized for its window (default 2048)
  *   "qh_wave"   0..2048  4-cycle wedges opposite a heavy largest vertex: wave hash
  *                        (default 1024; the per-wave table is sized from it)
  *   "qh_block"  0..4096  ... workgroup hash (default 2048); above: dense LDS counters

@@ -176,7 +176,9 @@ __device__ __forceinline__ void q_locate(const i32 *off, int len, i32 e0, int nj
 
 enum { PROBE_TRI = 0, PROBE_TAU = 1 };
 
+#ifndef QS
 #define QS 8  // wedges per thread per step in the 4-cycle sweeps
+#endif
 
 struct ProbeMem {
     i32 *hkey;   // [hc]
@@ -438,7 +440,15 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
 }
 
 // One wave per vertex, |N+(u)| <= 64, four items per 256-thread block.
-#define PW_QP 8
+#ifndef PW_QP
+#define PW_QP 4   // probes per thread and round, wave items
+#endif
+#ifndef PB_QP
+#define PB_QP 4   // probes per thread and round, workgroup items
+#endif
+#ifndef PL_QP
+#define PL_QP 4   // probes per thread and round, large items
+#endif
 template <int MODE>
 __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__restrict__ list,
                                                     const GraphStats *__restrict__ st, i32 *t, i64 *K4,
@@ -506,7 +516,7 @@ __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__
     for (; it < cnt; it += gridDim.x) {
         const PMeta nxt = p_meta<MODE>(g, tc, un);
         un = it + 2 * (i32)gridDim.x < cnt ? list[it + 2 * gridDim.x] : -1;
-        probe_item<PB_NT, MODE, 4>(g, cur, threadIdx.x, M, HC, WORDS, t, K4, tau, s_red, s_red32, tc, &s_st,
+        probe_item<PB_NT, MODE, PB_QP>(g, cur, threadIdx.x, M, HC, WORDS, t, K4, tau, s_red, s_red32, tc, &s_st,
                                    counters);
         cur = nxt;
     }
@@ -655,7 +665,7 @@ __global__ void __launch_bounds__(PL_NT) k_probe_large(DevGraph g, const i32 *__
     __syncthreads();
     const i32 cnt = st->cnt[WC_TRI_LARGE];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x)
-        probe_item<PL_NT, MODE, 4>(g, p_meta<MODE>(g, tc, list[it]), threadIdx.x, M, hc, words, t, K4, tau, s_red,
+        probe_item<PL_NT, MODE, PL_QP>(g, p_meta<MODE>(g, tc, list[it]), threadIdx.x, M, hc, words, t, K4, tau, s_red,
                                    s_red32, tc, &s_st, counters);
 }
 
@@ -993,7 +1003,9 @@ struct LightHash {
 };
 
 #define QLW_DC 64
+#ifndef QLW_QK
 #define QLW_QK 8
+#endif
 __host__ __device__ constexpr int qlw_wave_bytes(int hcw) {
     return ((8 * QLW_DC + 8 * hcw + 4 * (3 * QLW_DC + 1)) + 15) / 16 * 16;
 }
@@ -1194,7 +1206,9 @@ __device__ __forceinline__ void qh_item_packed(const DevGraph &g, const QMeta &m
 // One wave per item; the per-wave table size hcw (a power of two, at least twice
 // the class's wedge bound) comes with the launch, in dynamic LDS.
 #define QHW_DC 64
+#ifndef QHW_QK
 #define QHW_QK 16
+#endif
 __host__ __device__ constexpr int qhw_wave_bytes(int hcw) {
     return ((8 * QHW_DC + 4 * hcw + 4 * (3 * QHW_DC + 1)) + 15) / 16 * 16;
 }
@@ -1229,7 +1243,9 @@ __global__ void __launch_bounds__(256) k_qh_wave(DevGraph g, const i32 *__restri
 
 #define QHB_HC 8192
 #define QHB_DC 256
-#define QHB_NT 512
+#ifndef QHB_NT
+#define QHB_NT 256
+#endif
 __global__ void __launch_bounds__(QHB_NT) k_qh_block(DevGraph g, const i32 *__restrict__ list,
                                                      const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 K) {
     __shared__ u32 s_tab[QHB_HC];
@@ -1267,7 +1283,12 @@ __global__ void k_qh_reduce(const i64 *__restrict__ part, int rows, i32 K, i32 h
 }
 
 // Heavy largest vertices: dense 16-bit counters over [h0, n).
+#ifndef QD_NT
 #define QD_NT 512
+#endif
+#ifndef QD_QK
+#define QD_QK 16  // wedges per thread kept in registers by the dense kernel
+#endif
 #define QD_DC 256
 __global__ void __launch_bounds__(QD_NT) k_q_dense(DevGraph g, const i32 *__restrict__ list,
                                                    const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 Kp) {
@@ -1288,7 +1309,7 @@ __global__ void __launch_bounds__(QD_NT) k_q_dense(DevGraph g, const i32 *__rest
     const i32 cnt = st->cnt[WC_QH_DENSE];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x) {
         i32 x = list[it];
-        q_sweeps<QD_NT, Q_HEAVY, 16>(g, q_meta<Q_HEAVY>(g, x), ctr, C, QD_DC, threadIdx.x, s_red32, Q);
+        q_sweeps<QD_NT, Q_HEAVY, QD_QK>(g, q_meta<Q_HEAVY>(g, x), ctr, C, QD_DC, threadIdx.x, s_red32, Q);
         i64 local = 0;
         for (i32 i = threadIdx.x; i < KW; i += QD_NT) {
             u32 word = s_w[i];
@@ -1451,23 +1472,22 @@ hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats 
     }
     KMARK(6);
     {
-        // two launches: items up to ql_split wedges with small tables (several
-        // workgroups per CU), the larger ones with tables for ql_block wedges
-        const i64 split = ql_split < ql_block_bound ? ql_split : ql_block_bound;
+        // one launch per window of wedge counts (ql_wave, ql_split], then doubling up to
+        // ql_block, each with tables for its window only: small items keep many
+        // workgroups per CU, large ones get the LDS they need
         auto table_for = [](i64 w) {
             int h = 64;
             while ((i64)h < 2 * w) h <<= 1;
             return h;
         };
-        if (split > 0) {
-            const int hcb = table_for(split);
+        i64 lo = -1, hi = ql_split < ql_block_bound ? ql_split : ql_block_bound;
+        if (hi <= 0) hi = ql_block_bound;
+        while (lo < ql_block_bound && hi > 0) {
+            const int hcb = table_for(hi);
             hipLaunchKernelGGL(k_q_block<Q_LIGHT>, dim3(grid_block), dim3(QLB_NT), qlb_bytes(hcb), s, g,
-                               lists_host[WC_QL_BLOCK], st, (int)WC_QL_BLOCK, Q, hcb, (i64)-1, split);
-        }
-        if (split < ql_block_bound) {
-            const int hcb = table_for(ql_block_bound);
-            hipLaunchKernelGGL(k_q_block<Q_LIGHT>, dim3(grid_block), dim3(QLB_NT), qlb_bytes(hcb), s, g,
-                               lists_host[WC_QL_BLOCK], st, (int)WC_QL_BLOCK, Q, hcb, split, ql_block_bound);
+                               lists_host[WC_QL_BLOCK], st, (int)WC_QL_BLOCK, Q, hcb, lo, hi);
+            lo = hi;
+            hi = 2 * hi < ql_block_bound ? 2 * hi : ql_block_bound;
         }
     }
     KMARK(7);
