@@ -835,13 +835,22 @@ __device__ __forceinline__ i32 q_load_chunk(const DevGraph &g, i32 x, i32 s0, i3
 struct DenseCounter {
     u32 *w;   // K/2 words
     i32 h0;
-    __device__ void inc(i32 k) const {
+    // returns the counter index when this call took it from 0 (its owner), else -1
+    __device__ int inc(i32 k) const {
         i32 i = k - h0;
-        atomicAdd(&w[i >> 1], 1u << ((i & 1) << 4));
+        const u32 old = atomicAdd(&w[i >> 1], 1u << ((i & 1) << 4));
+        return ((old >> ((i & 1) << 4)) & 0xffffu) == 0 ? i : -1;
     }
     __device__ i32 get(i32 k) const {
         i32 i = k - h0;
         return (i32)((w[i >> 1] >> ((i & 1) << 4)) & 0xffffu);
+    }
+    // count of an owned counter, which is returned to zero (the word's other half may
+    // be taken at the same time)
+    __device__ i32 take(int i) const {
+        const int sh = (i & 1) << 4;
+        const u32 old = atomicAnd(&w[i >> 1], ~(0xffffu << sh));
+        return (i32)((old >> sh) & 0xffffu);
     }
 };
 
@@ -849,10 +858,23 @@ struct GlobalCounter {
     i32 *c;       // [n] zero between items
     i32 *used;    // list of touched keys
     i32 *nused;   // LDS counter
-    __device__ void inc(i32 k) const {
+    __device__ int inc(i32 k) const {
         if (atomicAdd(&c[k], 1) == 0) used[atomicAdd(nused, 1)] = k;
+        return -1;
     }
     __device__ i32 get(i32 k) const { return c[k]; }
+};
+
+// Where C(c, 2) for a key with count c goes: Q of the key itself (light items, keys
+// are vertices) or the heavy key's credit row.
+struct CreditLight {
+    i64 *Q;
+    __device__ void operator()(i32 k, i64 cc) const { atomic_add_i64(&Q[k], cc); }
+};
+struct CreditHeavy {
+    i64 *prow;
+    i32 h0;
+    __device__ void operator()(i32 k, i64 cc) const { atomic_add_i64(&prow[k - h0], cc); }
 };
 
 // Row bounds of a 4-cycle item and its wedge count, loaded together so that the
@@ -879,10 +901,13 @@ __device__ __forceinline__ QMeta q_meta(const DevGraph &g, i32 x) {
 // search over the chunk's prefix offsets in LDS.  When the whole item is one
 // chunk of at most NT*QK wedges, every thread keeps its wedges' keys and segments in
 // registers: the keys are read from memory once, all loads of a thread in flight
-// together, and the second sweep needs neither loads nor searches.
-template <int NT, int MODE, int QK = 0, typename Ctr>
-__device__ __forceinline__ void q_sweeps(const DevGraph &g, const QMeta &mt, const Ctr &ctr, const QChunk &C, int dc,
-                                         int tid, i32 *red32, i64 *__restrict__ Q) {
+// together, and the second sweep needs neither loads nor searches; the thread that
+// created a key's counter then credits C(c, 2) through cr, adds it to *local and
+// empties the counter, and the call returns true.  Otherwise (false) the counters
+// are left for the caller to harvest.
+template <int NT, int MODE, int QK = 0, typename Ctr, typename Credit>
+__device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, const Ctr &ctr, const QChunk &C, int dc,
+                                         int tid, i32 *red32, i64 *__restrict__ Q, const Credit &cr, i64 *local) {
     const i32 x = mt.x, s0 = mt.s0, sp = mt.sp;
     const i32 ns = (MODE == Q_LIGHT) ? sp - s0 : mt.s1 - s0;
     const bool single = ns <= dc;
@@ -901,9 +926,9 @@ __device__ __forceinline__ void q_sweeps(const DevGraph &g, const QMeta &mt, con
                 }
 #pragma unroll
                 for (int j = 0; j < QK; j++) key[j] = key[j] >= 0 ? g.ncol[key[j]] : -1;
+                int own[QK];
 #pragma unroll
-                for (int j = 0; j < QK; j++)
-                    if (key[j] >= 0) ctr.inc(key[j]);
+                for (int j = 0; j < QK; j++) own[j] = key[j] >= 0 ? ctr.inc(key[j]) : -1;
                 item_sync<NT>();
                 // second sweep: each wedge's middle gains c - 1, summed over runs of
                 // lanes in the same segment before the LDS atomic
@@ -915,12 +940,25 @@ __device__ __forceinline__ void q_sweeps(const DevGraph &g, const QMeta &mt, con
                     }
                 }
                 item_sync<NT>();
+                i64 acc = 0;
+#pragma unroll
+                for (int j = 0; j < QK; j++) {
+                    if (own[j] >= 0) {
+                        const i64 c = ctr.take(own[j]);
+                        if (c >= 2) {
+                            const i64 cc = c * (c - 1) / 2;
+                            cr(key[j], cc);
+                            acc += cc;
+                        }
+                    }
+                }
+                *local += acc;
                 for (int i = tid; i < ns; i += NT) {
                     i64 m = C.mid[i];
                     if (m) atomic_add_i64(&Q[C.vv[i]], m);
                 }
                 item_sync<NT>();
-                return;
+                return true;
             }
         }
     }
@@ -968,6 +1006,7 @@ __device__ __forceinline__ void q_sweeps(const DevGraph &g, const QMeta &mt, con
             }
         }
     }
+    return false;
 }
 
 
@@ -978,18 +1017,32 @@ struct LightHash {
     i32 *key;
     i32 *cnt;
     u32 mask;
-    __device__ void inc(i32 k) const {
+    // returns the slot when this call inserted the key (its owner), else -1
+    __device__ int inc(i32 k) const {
         u32 sl = hslot((u32)k, mask);
+        int own = -1;
         while (true) {
             i32 cur = key[sl];
             if (cur == k) break;
             if (cur == -1) {
                 i32 prev = atomicCAS(&key[sl], -1, k);
-                if (prev == -1 || prev == k) break;
+                if (prev == -1) {
+                    own = (int)sl;
+                    break;
+                }
+                if (prev == k) break;
             }
             sl = (sl + 1) & mask;
         }
         atomicAdd(&cnt[sl], 1);
+        return own;
+    }
+    // count of an owned slot, which is emptied
+    __device__ i32 take(int sl) const {
+        const i32 c = cnt[sl];
+        key[sl] = -1;
+        cnt[sl] = 0;
+        return c;
     }
     __device__ i32 get(i32 k) const {
         u32 sl = hslot((u32)k, mask);
@@ -1040,9 +1093,9 @@ __global__ void __launch_bounds__(256) k_q_wave(DevGraph g, const i32 *__restric
         const i64 need = 2 * cur.w;
         const int hc = need >= hcw ? hcw : (need <= 64 ? 64 : (int)(1u << (32 - __clz((u32)(need - 1)))));
         LightHash H{s_key, s_cnt, (u32)hc - 1};
-        q_sweeps<WAVE, MODE, QLW_QK>(g, cur, H, C, QLW_DC, tid, nullptr, Q);
         i64 local = 0;
-        for (int j = tid; j < hc; j += WAVE) {
+        const bool taken = q_sweeps<WAVE, MODE, QLW_QK>(g, cur, H, C, QLW_DC, tid, nullptr, Q, CreditLight{Q}, &local);
+        for (int j = tid; !taken && j < hc; j += WAVE) {
             const i32 k = s_key[j];
             if (k >= 0) {
                 const i64 c = s_cnt[j];
@@ -1105,9 +1158,10 @@ __global__ void __launch_bounds__(QLB_NT) k_q_block(DevGraph g, const i32 *__res
         const i64 need = 2 * cur.w;
         const int hc = need >= hcb ? hcb : (need <= 64 ? 64 : (int)(1u << (32 - __clz((u32)(need - 1)))));
         LightHash H{s_key, s_cnt, (u32)hc - 1};
-        q_sweeps<QLB_NT, MODE, 16>(g, cur, H, C, QLB_DC, threadIdx.x, s_red32, Q);
         i64 local = 0;
-        for (int j = threadIdx.x; j < hc; j += QLB_NT) {
+        const bool taken =
+            q_sweeps<QLB_NT, MODE, 16>(g, cur, H, C, QLB_DC, threadIdx.x, s_red32, Q, CreditLight{Q}, &local);
+        for (int j = threadIdx.x; !taken && j < hc; j += QLB_NT) {
             const i32 k = s_key[j];
             if (k >= 0) {
                 const i64 c = s_cnt[j];
@@ -1145,22 +1199,29 @@ struct PackedHash {
     u32 *tab;
     u32 mask;
     i32 h0;
-    __device__ void inc(i32 k) const {
+    // returns the slot when this call inserted the key (its owner), else -1
+    __device__ int inc(i32 k) const {
         const u32 idx = (u32)(k - h0);
         u32 sl = hslot(idx, mask);
         while (true) {
             u32 cur = tab[sl];
             if (cur == PK_EMPTY) {
                 u32 prev = atomicCAS(&tab[sl], PK_EMPTY, (idx << PK_SHIFT) | 1u);
-                if (prev == PK_EMPTY) return;
+                if (prev == PK_EMPTY) return (int)sl;
                 cur = prev;
             }
             if ((cur >> PK_SHIFT) == idx) {
                 atomicAdd(&tab[sl], 1u);
-                return;
+                return -1;
             }
             sl = (sl + 1) & mask;
         }
+    }
+    // count of an owned slot, which is emptied
+    __device__ i32 take(int sl) const {
+        const u32 cur = tab[sl];
+        tab[sl] = PK_EMPTY;
+        return (i32)(cur & PK_CMASK);
     }
     __device__ i32 get(i32 k) const {
         const u32 idx = (u32)(k - h0);
@@ -1184,9 +1245,9 @@ __device__ __forceinline__ void qh_item_packed(const DevGraph &g, const QMeta &m
     const i64 need = 2 * mt.w;
     const int hc = need >= hc_max ? hc_max : (need <= 64 ? 64 : (int)(1u << (32 - __clz((u32)(need - 1)))));
     PackedHash H{H0.tab, (u32)hc - 1, H0.h0};
-    q_sweeps<NT, Q_HEAVY, QK>(g, mt, H, C, dc, tid, red32, Q);
     i64 local = 0;
-    for (int j = tid; j < hc; j += NT) {
+    const bool taken = q_sweeps<NT, Q_HEAVY, QK>(g, mt, H, C, dc, tid, red32, Q, CreditHeavy{prow, H0.h0}, &local);
+    for (int j = tid; !taken && j < hc; j += NT) {
         u32 cur = H.tab[j];
         if (cur != PK_EMPTY) {
             i64 c = cur & PK_CMASK;
@@ -1309,9 +1370,10 @@ __global__ void __launch_bounds__(QD_NT) k_q_dense(DevGraph g, const i32 *__rest
     const i32 cnt = st->cnt[WC_QH_DENSE];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x) {
         i32 x = list[it];
-        q_sweeps<QD_NT, Q_HEAVY, QD_QK>(g, q_meta<Q_HEAVY>(g, x), ctr, C, QD_DC, threadIdx.x, s_red32, Q);
         i64 local = 0;
-        for (i32 i = threadIdx.x; i < KW; i += QD_NT) {
+        const bool taken = q_sweeps<QD_NT, Q_HEAVY, QD_QK>(g, q_meta<Q_HEAVY>(g, x), ctr, C, QD_DC, threadIdx.x,
+                                                           s_red32, Q, CreditHeavy{prow, g.h0}, &local);
+        for (i32 i = threadIdx.x; !taken && i < KW; i += QD_NT) {
             u32 word = s_w[i];
             if (word) {
                 i64 c0 = word & 0xffffu, c1 = word >> 16;
@@ -1358,7 +1420,8 @@ __global__ void __launch_bounds__(QG_NT) k_q_global(DevGraph g, const i32 *__res
     const i32 cnt = st->cnt[wc];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x) {
         i32 x = list[it];
-        q_sweeps<QG_NT, MODE>(g, q_meta<MODE>(g, x), ctr, C, QG_DC, threadIdx.x, s_red32, Q);
+        i64 unused = 0;
+        q_sweeps<QG_NT, MODE>(g, q_meta<MODE>(g, x), ctr, C, QG_DC, threadIdx.x, s_red32, Q, CreditLight{Q}, &unused);
         __threadfence_block();
         const i32 nu = s_nused;
         i64 local = 0;
