@@ -443,8 +443,9 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     ListPtrs lists;
     for (int c = 0; c < WC_COUNT; c++) lists.l[c] = (i32 *)(W + L.lists[c]);
     i64 *accb = (i64 *)(W + L.acc);
-    Accum acc{accb, accb + n, accb + 2 * (i64)n, accb + 3 * (i64)n, accb + 4 * (i64)n,
-              accb + 5 * (i64)n, accb + 6 * (i64)n, accb + 7 * (i64)n, accb + 8 * (i64)n, accb + 9 * (i64)n};
+    // (T, psi1) pairs first, so that they are 16-byte aligned
+    Accum acc{accb + 2 * (i64)n, accb + 3 * (i64)n, accb + 4 * (i64)n, accb + 5 * (i64)n, accb + 6 * (i64)n,
+              accb, accb + 7 * (i64)n, accb + 8 * (i64)n, accb + 9 * (i64)n};
     i32 *longcount = &dst->pad;
 
     STAGE_MARK(0);

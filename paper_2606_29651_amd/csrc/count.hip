@@ -74,45 +74,28 @@ __device__ __forceinline__ void item_scan(i32 *a, int len, int tid, i32 *red32) 
 }
 
 // ---------------------------------------------------------------------------
-// Classification into work lists (wave-aggregated appends).
+// Classification into work lists (workgroup-aggregated appends).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void list_push(bool take, int c, i32 y, const ListPtrs &lists, GraphStats *st, i64 work,
-                                          i64 slots) {
-    u64 m = __ballot(take);
-    if (!m) return;
-    int leader = __ffsll((long long)m) - 1;
-    i32 base = 0;
-    i64 w = wave_sum64(take ? work : 0), sl = wave_sum64(take ? slots : 0);
-    if (lane_id() == leader) {
-        base = atomicAdd(&st->cnt[c], __popcll(m));
-        atomicAdd((unsigned long long *)&st->work[c], (unsigned long long)w);
-        atomicAdd((unsigned long long *)&st->slots[c], (unsigned long long)sl);
-    }
-    base = __shfl(base, leader, WAVE);
-    if (take) lists.l[c][base + __popcll(m & lanemask_lt())] = y;
-}
+// The classes of one vertex: Stage I class (or -1) and the two 4-cycle classes
+// (light: largest vertex u = y; heavy: opposite vertex y), with the work and row
+// slots each one adds to the class statistics.
+struct VertexClasses {
+    int c[3];
+    i64 work[3], slots[3];
+};
 
-__global__ void k_classify(DevGraph g, const i64 *__restrict__ wlight, const i64 *__restrict__ wheavy,
-                           const i64 *__restrict__ probes, ListPtrs lists, GraphStats *__restrict__ st,
-                           Thresholds th) {
-    i32 idx = blockIdx.x * blockDim.x + threadIdx.x;
-    i32 y = g.n - 1 - idx;  // hubs first
-    bool valid = y >= 0;
-    i32 du = 0, d = 0, dm = 0;
-    i64 wl = 0, wh = 0;
-    if (valid) {
-        i32 b = g.nrp[y], sp = g.nsplit[y], e = g.nrp[y + 1];
-        du = e - sp;
-        d = e - b;
-        dm = sp - b;
-        wl = wlight[y];
-        wh = wheavy[y];
-    }
-    const i64 pr = valid ? probes[y] : 0;
+__device__ __forceinline__ VertexClasses classify_vertex(const DevGraph &g, const i64 *__restrict__ wlight,
+                                                         const i64 *__restrict__ wheavy,
+                                                         const i64 *__restrict__ probes, const Thresholds &th,
+                                                         i32 y) {
+    VertexClasses v{{-1, -1, -1}, {0, 0, 0}, {0, 0, 0}};
+    const i32 b = g.nrp[y], sp = g.nsplit[y], e = g.nrp[y + 1];
+    const i32 du = e - sp, d = e - b, dm = sp - b;
+    const i64 wl = wlight[y], wh = wheavy[y];
     // Stage I/II items: capacity decides first (|N+| sizes the LDS structures); items
     // that fit a wave may move to one lane or to a whole workgroup by predicted work
-    int tc = -1;
-    if (valid && du >= 2) {
+    if (du >= 2) {
+        int tc;
         if (du > th.tri_block) tc = WC_TRI_LARGE;
         else if (du > th.tri_wave) tc = WC_TRI_BLOCK;
         else {
@@ -126,28 +109,80 @@ __global__ void k_classify(DevGraph g, const i64 *__restrict__ wlight, const i64
                 else if (p >= th.thr_block) tc = WC_TRI_BLOCK;
             }
         }
+        v.c[0] = tc;
+        v.work[0] = probes[y];
+        v.slots[0] = du;
     }
-    list_push(tc == WC_TRI_THREAD, WC_TRI_THREAD, y, lists, st, pr, du);
-    list_push(tc == WC_TRI_WAVE, WC_TRI_WAVE, y, lists, st, pr, du);
-    list_push(tc == WC_TRI_BLOCK, WC_TRI_BLOCK, y, lists, st, pr, du);
-    list_push(tc == WC_TRI_LARGE, WC_TRI_LARGE, y, lists, st, pr, du);
-    bool qlw = valid && wl > 0 && wl <= th.ql_wave;
-    bool qlb = valid && wl > th.ql_wave && wl <= th.ql_block;
-    bool qlg = valid && wl > th.ql_block;
-    list_push(qlw, WC_QL_WAVE, y, lists, st, wl, dm);
-    list_push(qlb, WC_QL_BLOCK, y, lists, st, wl, dm);
-    list_push(qlg, WC_QL_GLOBAL, y, lists, st, wl, dm);
+    if (wl > 0) {
+        v.c[1] = wl <= th.ql_wave ? WC_QL_WAVE : (wl <= th.ql_block ? WC_QL_BLOCK : WC_QL_GLOBAL);
+        v.work[1] = wl;
+        v.slots[1] = dm;
+    }
     // packed 17-bit and dense 16-bit counters need every count below 2^16; a count
     // is at most d(x), so vertices of degree >= 2^16 use int32 global counters
-    bool small_d = d < 65536;
-    bool qhw = valid && small_d && wh > 0 && wh <= th.qh_wave;
-    bool qhb = valid && small_d && wh > th.qh_wave && wh <= th.qh_block;
-    bool qhd = valid && small_d && wh > th.qh_block;
-    bool qhg = valid && !small_d && wh > 0;
-    list_push(qhw, WC_QH_WAVE, y, lists, st, wh, d);
-    list_push(qhb, WC_QH_BLOCK, y, lists, st, wh, d);
-    list_push(qhd, WC_QH_DENSE, y, lists, st, wh, d);
-    list_push(qhg, WC_QH_GLOBAL, y, lists, st, wh, d);
+    if (wh > 0) {
+        v.c[2] = d >= 65536 ? WC_QH_GLOBAL
+                            : (wh <= th.qh_wave ? WC_QH_WAVE : (wh <= th.qh_block ? WC_QH_BLOCK : WC_QH_DENSE));
+        v.work[2] = wh;
+        v.slots[2] = d;
+    }
+    return v;
+}
+
+// Work lists per class.  A workgroup classifies CL_PER_THREAD vertices per thread
+// per tile (hubs first), counts each class's members, work and slots in LDS, and
+// reserves the class's list space with one global atomic per class and tile.
+#define CL_NT 256
+#define CL_PER_THREAD 4
+__global__ void __launch_bounds__(CL_NT) k_classify(DevGraph g, const i64 *__restrict__ wlight,
+                                                    const i64 *__restrict__ wheavy, const i64 *__restrict__ probes,
+                                                    ListPtrs lists, GraphStats *__restrict__ st, Thresholds th) {
+    __shared__ i32 s_cnt[WC_COUNT], s_base[WC_COUNT];
+    __shared__ unsigned long long s_work[WC_COUNT], s_slots[WC_COUNT];
+    constexpr int TILE = CL_NT * CL_PER_THREAD;
+    const i32 tiles = (g.n + TILE - 1) / TILE;
+    for (i32 tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        if (threadIdx.x < WC_COUNT) {
+            s_cnt[threadIdx.x] = 0;
+            s_work[threadIdx.x] = 0;
+            s_slots[threadIdx.x] = 0;
+        }
+        __syncthreads();
+        i32 ys[CL_PER_THREAD];
+        int cls[CL_PER_THREAD][3], pos[CL_PER_THREAD][3];
+#pragma unroll
+        for (int k = 0; k < CL_PER_THREAD; k++) {
+            const i32 idx = tile * TILE + k * CL_NT + threadIdx.x;
+            const i32 y = g.n - 1 - idx;  // hubs first
+            ys[k] = y;
+            VertexClasses v{{-1, -1, -1}, {0, 0, 0}, {0, 0, 0}};
+            if (y >= 0) v = classify_vertex(g, wlight, wheavy, probes, th, y);
+#pragma unroll
+            for (int j = 0; j < 3; j++) {
+                cls[k][j] = v.c[j];
+                pos[k][j] = -1;
+                if (v.c[j] >= 0) {
+                    pos[k][j] = atomicAdd(&s_cnt[v.c[j]], 1);
+                    atomicAdd(&s_work[v.c[j]], (unsigned long long)v.work[j]);
+                    atomicAdd(&s_slots[v.c[j]], (unsigned long long)v.slots[j]);
+                }
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < WC_COUNT && s_cnt[threadIdx.x] > 0) {
+            const int c = threadIdx.x;
+            s_base[c] = atomicAdd(&st->cnt[c], s_cnt[c]);
+            atomicAdd((unsigned long long *)&st->work[c], s_work[c]);
+            atomicAdd((unsigned long long *)&st->slots[c], s_slots[c]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < CL_PER_THREAD; k++)
+#pragma unroll
+            for (int j = 0; j < 3; j++)
+                if (cls[k][j] >= 0) lists.l[cls[k][j]][s_base[cls[k][j]] + pos[k][j]] = ys[k];
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -486,7 +521,9 @@ __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__res
 }
 
 // One 256-thread workgroup per vertex, 64 < |N+(u)| <= TRI_BLOCK_CAP.
+#ifndef PB_NT
 #define PB_NT 512
+#endif
 template <int MODE>
 __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__restrict__ list,
                                                      const GraphStats *__restrict__ st, i32 *t, i64 *K4,
@@ -706,8 +743,8 @@ __global__ void __launch_bounds__(256) k_sums(DevGraph g, const i32 *__restrict_
             acc.Std[x] = Std;
             acc.Sd[x] = Sd;
             acc.Sdd[x] = Sdd;
-            acc.T[x] = St >> 1;
-            acc.psi1[x] = Sd - (e0 - b0);
+            acc.Tp[2 * (i64)x] = St >> 1;
+            acc.Tp[2 * (i64)x + 1] = Sd - (e0 - b0);
         }
     }
 }
@@ -758,14 +795,15 @@ __global__ void __launch_bounds__(256) k_solve(DevGraph g, Accum acc, i64 *__res
         i64 ST = 0, Sp = 0;
         for (i32 s = b0 + lane_id(); s < e0; s += WAVE) {
             i32 a = g.ncol[s];
-            ST += acc.T[a];
-            Sp += acc.psi1[a];
+            const longlong2 tp = *reinterpret_cast<const longlong2 *>(acc.Tp + 2 * (i64)a);
+            ST += tp.x;
+            Sp += tp.y;
         }
         ST = wave_sum64(ST);
         Sp = wave_sum64(Sp);
         // lanes 0..14 each write one column; all compute the same row
         i64 f[9], psi[15];
-        solve_vertex(e0 - b0, acc.T[x], acc.psi1[x], acc.St[x], acc.Stt[x], acc.Std[x], acc.Sd[x], acc.Sdd[x], ST,
+        solve_vertex(e0 - b0, acc.Tp[2 * (i64)x], acc.Tp[2 * (i64)x + 1], acc.St[x], acc.Stt[x], acc.Std[x], acc.Sd[x], acc.Sdd[x], ST,
                      Sp, acc.tau[x], acc.Q[x], acc.K4[x], f, psi, &err);
         i64 xo = g.order[x];
         int l = lane_id();
@@ -1451,7 +1489,9 @@ __global__ void __launch_bounds__(QG_NT) k_q_global(DevGraph g, const i32 *__res
 hipError_t launch_classify(const DevGraph &g, const i64 *wl, const i64 *wh, const i64 *probes, const ListPtrs &lists,
                            GraphStats *st, const Thresholds &th, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_classify, dim3((g.n + 255) / 256), dim3(256), 0, s, g, wl, wh, probes, lists, st, th);
+    const i32 tiles = (g.n + CL_NT * CL_PER_THREAD - 1) / (CL_NT * CL_PER_THREAD);
+    hipLaunchKernelGGL(k_classify, dim3(tiles < 2048 ? tiles : 2048), dim3(CL_NT), 0, s, g, wl, wh, probes, lists, st,
+                       th);
     return hipGetLastError();
 }
 

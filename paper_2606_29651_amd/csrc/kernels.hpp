@@ -86,7 +86,8 @@ struct Thresholds {
 // Per-vertex accumulators (new vertex ids), all int64[n].
 struct Accum {
     i64 *St, *Stt, *Std, *Sd, *Sdd;  // neighbour sums of t, t^2, t*d(a), d(a), d(a)^2
-    i64 *T, *psi1;                   // triangles at x; non-induced 3-path ends
+    i64 *Tp;                         // pairs (T, psi1) per vertex: triangles at x, non-induced
+                                     // 3-path ends (one 16-byte load per neighbour)
     i64 *tau;                        // sum over triangles at x of t(opposite edge)
     i64 *Q;                          // 4-cycles through x
     i64 *K4;                         // 4-cliques containing x
