@@ -507,8 +507,8 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     float *feat = L.feat ? (float *)(W + L.feat) : nullptr;
     float *pred = L.pred ? (float *)(W + L.pred) : nullptr;
     i64 *counters = L.counters ? (i64 *)(W + L.counters) : nullptr;
-    hipLaunchKernelGGL(k_mirror, dim3(cu * 8), dim3(nthr), 0, s, n, nrp, nsplit, ncol, hstart, h0, mirror, wl, wh,
-                       probes, feat);
+    hipLaunchKernelGGL(k_mirror, dim3(cu * 8), dim3(nthr), 0, s, n, deg, nrp, nsplit, ncol, hstart, h0, mirror, wl,
+                       wh, probes, feat);
     HIP_TRY(hipGetLastError());
     Thresholds th = ctx->th;
     th.bin_mode = (flags & NIORCA_BIN_MLP) ? 2 : ((flags & NIORCA_BIN_DEGREE) ? 1 : 0);

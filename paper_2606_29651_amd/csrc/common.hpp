@@ -150,4 +150,35 @@ __device__ __forceinline__ i64 wave_run_sum(i64 v, int key, bool *last) {
     return v;
 }
 
+// Per-vertex passes: vertices of degree <= SG_MAXDEG (the ranks below a cut, since
+// degrees ascend with rank) are handled by SG-lane groups, several per wave; the
+// rest one per wave.
+#define SG 16
+#define SG_MAXDEG 64
+
+// Smallest rank whose degree exceeds d (n if none): a binary search over the
+// non-decreasing degrees by rank.
+__device__ __forceinline__ i32 first_above(const u32 *__restrict__ ndeg, i32 n, u32 d) {
+    i32 lo = 0, hi = n;
+    while (lo < hi) {
+        const i32 mid = lo + ((hi - lo) >> 1);
+        if (ndeg[mid] <= d) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+template <int W>
+__device__ __forceinline__ i64 group_sum64(i64 v) {
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+    return v;
+}
+
+template <int W>
+__device__ __forceinline__ int group_max32(int v) {
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, W));
+    return v;
+}
+
 #define HIP_CHECK_LAUNCH() (hipGetLastError())

@@ -713,40 +713,56 @@ i64 probe_large_slice_bytes(int cap, int hc, i64 lds_max) {
     return (b + 255) & ~255ll;
 }
 
+
+template <int W>
+__device__ __forceinline__ void sums_vertex(const DevGraph &g, const i32 *__restrict__ t, const Accum &acc, i32 x,
+                                            bool active, int l) {
+    i32 b0 = 0, sp = 0, e0 = 0;
+    if (active) {
+        b0 = g.nrp[x];
+        sp = g.nsplit[x];
+        e0 = g.nrp[x + 1];
+    }
+    i64 St = 0, Stt = 0, Std = 0, Sd = 0, Sdd = 0;
+    for (i32 s = b0 + l; s < e0; s += W) {
+        i32 a = g.ncol[s];
+        i64 ta = (s < sp) ? t[g.mirror[s]] : t[s];
+        i64 da = g.ndeg[a];
+        St += ta;
+        Stt += ta * ta;
+        Std += ta * da;
+        Sd += da;
+        Sdd += da * da;
+    }
+    St = group_sum64<W>(St);
+    Stt = group_sum64<W>(Stt);
+    Std = group_sum64<W>(Std);
+    Sd = group_sum64<W>(Sd);
+    Sdd = group_sum64<W>(Sdd);
+    if (active && l == 0) {
+        acc.St[x] = St;
+        acc.Stt[x] = Stt;
+        acc.Std[x] = Std;
+        acc.Sd[x] = Sd;
+        acc.Sdd[x] = Sdd;
+        acc.Tp[2 * (i64)x] = St >> 1;
+        acc.Tp[2 * (i64)x + 1] = Sd - (e0 - b0);
+    }
+}
+
 // ---------------------------------------------------------------------------
-// Neighbour sums over full rows (one wave per vertex, hubs first).
+// Neighbour sums over full rows.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_sums(DevGraph g, const i32 *__restrict__ t, Accum acc) {
-    int waves = gridDim.x * (blockDim.x / WAVE);
-    int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    for (i32 x = g.n - 1 - wid; x >= 0; x -= waves) {
-        i32 b0 = g.nrp[x], sp = g.nsplit[x], e0 = g.nrp[x + 1];
-        i64 St = 0, Stt = 0, Std = 0, Sd = 0, Sdd = 0;
-        for (i32 s = b0 + lane_id(); s < e0; s += WAVE) {
-            i32 a = g.ncol[s];
-            i64 ta = (s < sp) ? t[g.mirror[s]] : t[s];
-            i64 da = g.ndeg[a];
-            St += ta;
-            Stt += ta * ta;
-            Std += ta * da;
-            Sd += da;
-            Sdd += da * da;
-        }
-        St = wave_sum64(St);
-        Stt = wave_sum64(Stt);
-        Std = wave_sum64(Std);
-        Sd = wave_sum64(Sd);
-        Sdd = wave_sum64(Sdd);
-        if (lane_id() == 0) {
-            acc.St[x] = St;
-            acc.Stt[x] = Stt;
-            acc.Std[x] = Std;
-            acc.Sd[x] = Sd;
-            acc.Sdd[x] = Sdd;
-            acc.Tp[2 * (i64)x] = St >> 1;
-            acc.Tp[2 * (i64)x + 1] = Sd - (e0 - b0);
-        }
+    const int waves = gridDim.x * (blockDim.x / WAVE);
+    const int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const i32 cut = first_above(g.ndeg, g.n, SG_MAXDEG);
+    constexpr int GPW = WAVE / SG;
+    for (i32 xb = wid * GPW; xb < cut; xb += waves * GPW) {
+        const i32 x = xb + lane_id() / SG;
+        sums_vertex<SG>(g, t, acc, x, x < cut, lane_id() % SG);
     }
+    for (i32 x = g.n - 1 - wid; x >= cut; x -= waves) sums_vertex<WAVE>(g, t, acc, x, true, lane_id());
 }
 
 // ---------------------------------------------------------------------------
@@ -785,41 +801,55 @@ __device__ __forceinline__ void solve_vertex(i64 d, i64 T, i64 psi1, i64 St, i64
     psi[14] = k4;
 }
 
+template <int W>
+__device__ __forceinline__ void solve_one(const DevGraph &g, const Accum &acc, i64 *__restrict__ out,
+                                          i64 *__restrict__ fvars, i32 x, bool active, int l, int *err) {
+    i32 b0 = 0, e0 = 0;
+    if (active) {
+        b0 = g.nrp[x];
+        e0 = g.nrp[x + 1];
+    }
+    i64 ST = 0, Sp = 0;
+    for (i32 s = b0 + l; s < e0; s += W) {
+        i32 a = g.ncol[s];
+        const longlong2 tp = *reinterpret_cast<const longlong2 *>(acc.Tp + 2 * (i64)a);
+        ST += tp.x;
+        Sp += tp.y;
+    }
+    ST = group_sum64<W>(ST);
+    Sp = group_sum64<W>(Sp);
+    if (!active) return;
+    // lanes 0..14 of the group each write one column; all compute the same row
+    i64 f[9], psi[15];
+    solve_vertex(e0 - b0, acc.Tp[2 * (i64)x], acc.Tp[2 * (i64)x + 1], acc.St[x], acc.Stt[x], acc.Std[x], acc.Sd[x],
+                 acc.Sdd[x], ST, Sp, acc.tau[x], acc.Q[x], acc.K4[x], f, psi, err);
+    const i64 xo = g.order[x];
+    if (out && l < 15) {
+        i64 v = 0;
+#pragma unroll
+        for (int k = 0; k < 15; k++) v = (l == k) ? psi[k] : v;
+        out[xo * 15 + l] = v;
+    }
+    if (fvars && l < 9) {
+        i64 v = 0;
+#pragma unroll
+        for (int k = 0; k < 9; k++) v = (l == k) ? f[k] : v;
+        fvars[xo * 9 + l] = v;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_solve(DevGraph g, Accum acc, i64 *__restrict__ out,
                                                i64 *__restrict__ fvars, GraphStats *__restrict__ st) {
-    int waves = gridDim.x * (blockDim.x / WAVE);
-    int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int waves = gridDim.x * (blockDim.x / WAVE);
+    const int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const i32 cut = first_above(g.ndeg, g.n, SG_MAXDEG);
+    constexpr int GPW = WAVE / SG;
     int err = 0;
-    for (i32 x = g.n - 1 - wid; x >= 0; x -= waves) {
-        i32 b0 = g.nrp[x], e0 = g.nrp[x + 1];
-        i64 ST = 0, Sp = 0;
-        for (i32 s = b0 + lane_id(); s < e0; s += WAVE) {
-            i32 a = g.ncol[s];
-            const longlong2 tp = *reinterpret_cast<const longlong2 *>(acc.Tp + 2 * (i64)a);
-            ST += tp.x;
-            Sp += tp.y;
-        }
-        ST = wave_sum64(ST);
-        Sp = wave_sum64(Sp);
-        // lanes 0..14 each write one column; all compute the same row
-        i64 f[9], psi[15];
-        solve_vertex(e0 - b0, acc.Tp[2 * (i64)x], acc.Tp[2 * (i64)x + 1], acc.St[x], acc.Stt[x], acc.Std[x], acc.Sd[x], acc.Sdd[x], ST,
-                     Sp, acc.tau[x], acc.Q[x], acc.K4[x], f, psi, &err);
-        i64 xo = g.order[x];
-        int l = lane_id();
-        if (out && l < 15) {
-            i64 v = 0;
-#pragma unroll
-            for (int k = 0; k < 15; k++) v = (l == k) ? psi[k] : v;
-            out[xo * 15 + l] = v;
-        }
-        if (fvars && l < 9) {
-            i64 v = 0;
-#pragma unroll
-            for (int k = 0; k < 9; k++) v = (l == k) ? f[k] : v;
-            fvars[xo * 9 + l] = v;
-        }
+    for (i32 xb = wid * GPW; xb < cut; xb += waves * GPW) {
+        const i32 x = xb + lane_id() / SG;
+        solve_one<SG>(g, acc, out, fvars, x, x < cut, lane_id() % SG, &err);
     }
+    for (i32 x = g.n - 1 - wid; x >= cut; x -= waves) solve_one<WAVE>(g, acc, out, fvars, x, true, lane_id(), &err);
     if (err) atomicOr(&st->err, 1);
 }
 

@@ -124,8 +124,8 @@ __global__ void k_sort_upper_small(i32 n, const i32 *nrp, const i32 *nsplit, i32
                                    i32 *longlist, i32 *longcount);
 __global__ void k_sort_upper_large(const i32 *nrp, const i32 *nsplit, i32 *ncol, i32 *hstart, i32 h0,
                                    const i32 *longlist, const i32 *longcount);
-__global__ void k_mirror(i32 n, const i32 *nrp, const i32 *nsplit, const i32 *ncol, const i32 *hstart, i32 h0,
-                         i32 *mirror, i64 *wlight, i64 *wheavy, i64 *probes, float *feat);
+__global__ void k_mirror(i32 n, const u32 *ndeg, const i32 *nrp, const i32 *nsplit, const i32 *ncol,
+                         const i32 *hstart, i32 h0, i32 *mirror, i64 *wlight, i64 *wheavy, i64 *probes, float *feat);
 #define LSORT_CAP 16384
 
 // count.hip

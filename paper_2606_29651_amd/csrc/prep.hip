@@ -399,53 +399,75 @@ __global__ void __launch_bounds__(LSORT_NT) k_sort_upper_large(const i32 *__rest
 // model: log2(1 + x) of degree, |N+|, |N-|, neighbour-degree sum, probes and the
 // largest |N+(b)| over b in N+(y).
 // ---------------------------------------------------------------------------
-__global__ void k_mirror(i32 n, const i32 *__restrict__ nrp, const i32 *__restrict__ nsplit,
-                         const i32 *__restrict__ ncol, const i32 *__restrict__ hstart, i32 h0,
-                         i32 *__restrict__ mirror, i64 *__restrict__ wlight, i64 *__restrict__ wheavy,
-                         i64 *__restrict__ probes, float *__restrict__ feat) {
-    int waves = gridDim.x * (blockDim.x / WAVE);
-    int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    for (i32 y = n - 1 - wid; y >= 0; y -= waves) {
-        i32 b0 = nrp[y], sp = nsplit[y], e0 = nrp[y + 1];
-        i64 wl = 0, wh = 0, pr = 0, nds = 0;
-        int mx = 0;
-        for (i32 s = b0 + lane_id(); s < e0; s += WAVE) {
-            i32 b = ncol[s];
-            i32 bb = nrp[b], bend = nrp[b + 1];
-            nds += bend - bb;
-            if (s < sp) {
-                i32 m = lower_bound_i32(ncol, nsplit[b], bend, y);
-                mirror[s] = m;
-                wl += m - bb;
-                i32 st = (y >= h0) ? m + 1 : hstart[b];
-                wh += bend - st;
-            } else {
-                wh += bend - hstart[b];
-                i32 dpb = bend - nsplit[b];
-                pr += dpb;
-                mx = max(mx, dpb);
-            }
-        }
-        wl = wave_sum64(wl);
-        wh = wave_sum64(wh);
-        pr = wave_sum64(pr);
-        if (lane_id() == 0) {
-            wlight[y] = (y < h0) ? wl : 0;
-            wheavy[y] = wh;
-            probes[y] = pr;
-        }
-        if (feat) {
-            nds = wave_sum64(nds);
-            mx = wave_max32(mx);
-            if (lane_id() == 0) {
-                float *f = feat + (i64)y * 6;
-                f[0] = log2f(1.0f + (float)(e0 - b0));
-                f[1] = log2f(1.0f + (float)(e0 - sp));
-                f[2] = log2f(1.0f + (float)(sp - b0));
-                f[3] = log2f(1.0f + (float)nds);
-                f[4] = log2f(1.0f + (float)pr);
-                f[5] = log2f(1.0f + (float)mx);
-            }
+template <int W>
+__device__ __forceinline__ void mirror_row(i32 y, bool active, int l, const i32 *__restrict__ nrp,
+                                           const i32 *__restrict__ nsplit, const i32 *__restrict__ ncol,
+                                           const i32 *__restrict__ hstart, i32 h0, i32 *__restrict__ mirror,
+                                           i64 *__restrict__ wlight, i64 *__restrict__ wheavy,
+                                           i64 *__restrict__ probes, float *__restrict__ feat) {
+    i32 b0 = 0, sp = 0, e0 = 0;
+    if (active) {
+        b0 = nrp[y];
+        sp = nsplit[y];
+        e0 = nrp[y + 1];
+    }
+    i64 wl = 0, wh = 0, pr = 0, nds = 0;
+    int mx = 0;
+    for (i32 s = b0 + l; s < e0; s += W) {
+        i32 b = ncol[s];
+        i32 bb = nrp[b], bend = nrp[b + 1];
+        nds += bend - bb;
+        if (s < sp) {
+            i32 m = lower_bound_i32(ncol, nsplit[b], bend, y);
+            mirror[s] = m;
+            wl += m - bb;
+            i32 st = (y >= h0) ? m + 1 : hstart[b];
+            wh += bend - st;
+        } else {
+            wh += bend - hstart[b];
+            i32 dpb = bend - nsplit[b];
+            pr += dpb;
+            mx = max(mx, dpb);
         }
     }
+    wl = group_sum64<W>(wl);
+    wh = group_sum64<W>(wh);
+    pr = group_sum64<W>(pr);
+    nds = group_sum64<W>(nds);
+    mx = group_max32<W>(mx);
+    if (active && l == 0) {
+        wlight[y] = (y < h0) ? wl : 0;
+        wheavy[y] = wh;
+        probes[y] = pr;
+        if (feat) {
+            float *f = feat + (i64)y * 6;
+            f[0] = log2f(1.0f + (float)(e0 - b0));
+            f[1] = log2f(1.0f + (float)(e0 - sp));
+            f[2] = log2f(1.0f + (float)(sp - b0));
+            f[3] = log2f(1.0f + (float)nds);
+            f[4] = log2f(1.0f + (float)pr);
+            f[5] = log2f(1.0f + (float)mx);
+        }
+    }
+}
+
+// Mirror slots (for each N- slot, the N+ slot of the reverse edge), the per-vertex
+// work of the later passes (4-cycle wedges light and heavy, Stage I probes) and the
+// work-model features.
+__global__ void k_mirror(i32 n, const u32 *__restrict__ ndeg, const i32 *__restrict__ nrp,
+                         const i32 *__restrict__ nsplit, const i32 *__restrict__ ncol,
+                         const i32 *__restrict__ hstart, i32 h0, i32 *__restrict__ mirror,
+                         i64 *__restrict__ wlight, i64 *__restrict__ wheavy, i64 *__restrict__ probes,
+                         float *__restrict__ feat) {
+    const int waves = gridDim.x * (blockDim.x / WAVE);
+    const int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const i32 cut = first_above(ndeg, n, SG_MAXDEG);
+    constexpr int GPW = WAVE / SG;
+    for (i32 yb = wid * GPW; yb < cut; yb += waves * GPW) {
+        const i32 y = yb + lane_id() / SG;
+        mirror_row<SG>(y, y < cut, lane_id() % SG, nrp, nsplit, ncol, hstart, h0, mirror, wlight, wheavy, probes,
+                       feat);
+    }
+    for (i32 y = n - 1 - wid; y >= cut; y -= waves)
+        mirror_row<WAVE>(y, true, lane_id(), nrp, nsplit, ncol, hstart, h0, mirror, wlight, wheavy, probes, feat);
 }
