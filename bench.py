@@ -45,14 +45,14 @@ def log(msg):
 KERNEL_CLASS = {"probe_thread": "tri_thread", "probe_wave": "tri_wave", "probe_block": "tri_block",
                 "probe_large": "tri_large", "ql_wave": "ql_wave", "ql_block": "ql_block",
                 "ql_global": "ql_global", "qh_wave": "qh_wave", "qh_block": "qh_block",
-                "qh_dense": "qh_dense", "qh_global": "qh_global"}
+                "qh_dense": "qh_dense", "qh_global": "qh_global", "probe_group": "tri_group"}
 
 
 # kernel names of the bench's per-kernel timings -> device symbol prefixes under rocprofv3
 PROF_NAME = {"probe_thread": "k_probe_thread<0>", "probe_wave": "k_probe_wave<0>", "probe_block": "k_probe_block<0>",
              "probe_large": "k_probe_large<0,", "ql_wave": "k_q_wave<0>", "ql_block": "k_q_block<0>",
              "ql_global": "k_q_global<0>", "qh_wave": "k_qh_wave", "qh_block": "k_qh_block",
-             "qh_dense": "k_q_dense", "qh_global": "k_q_global<1>"}
+             "qh_dense": "k_q_dense", "qh_global": "k_q_global<1>", "probe_group": "k_probe_group<0>"}
 CSRC = os.path.join(ROOT, "paper_2606_29651_amd", "csrc")
 
 
@@ -242,15 +242,17 @@ def forms(args, ni, ctx, g, rp, cl, out, base_ms):
     # thresholds of the learned binning: a small search on the training graph
     ref = out.clone()
     best = None
-    for thr_t in (8.0, 10.0, 12.0):
-        for thr_b in (15.0, 17.0, 99.0):
-            ni.set_cost_model(model, thr_t, thr_b, ctx=ctx)
-            ms, _, _ = time_count(ni, ctx, rp, cl, out, ni.BIN_MLP, 2, 1)
-            if best is None or ms < best[0]:
-                best = (ms, thr_t, thr_b)
-    ni.set_cost_model(model, best[1], best[2], ctx=ctx)
+    for thr_t in (-99.0, 8.0):
+        for thr_g in (-99.0, 10.0, 11.0, 12.0, 13.0):
+            for thr_b in (17.0, 99.0):
+                ni.set_cost_model(model, thr_t, thr_b, thr_g, ctx=ctx)
+                ms, _, _ = time_count(ni, ctx, rp, cl, out, ni.BIN_MLP, 2, 1)
+                if best is None or ms < best[0]:
+                    best = (ms, thr_t, thr_b, thr_g)
+    ni.set_cost_model(model, best[1], best[2], best[3], ctx=ctx)
     res["work_model"] = {"train_rows": fit["rows"], "mse": round(fit["mse"], 4),
-                         "target_var": round(fit["target_var"], 4), "thr_thread": best[1], "thr_block": best[2]}
+                         "target_var": round(fit["target_var"], 4), "thr_thread": best[1], "thr_group": best[3],
+                         "thr_block": best[2]}
     deg_ms, _, _ = time_count(ni, ctx, rp, cl, out, ni.BIN_DEGREE, 3, 1)
     same_deg = bool(torch.equal(out, ref))
     mlp_ms, _, _ = time_count(ni, ctx, rp, cl, out, ni.BIN_MLP, 3, 1)

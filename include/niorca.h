@@ -95,6 +95,8 @@ uint64_t niorca_workspace_bytes(const niorca_ctx *ctx);
  *                        mean degree, else 0; 4096 in niorca_count_batched
  *   "bin_deg_thread" (NIORCA_BIN_DEGREE) degree up to which a vertex with |N+| <= 8
  *               goes to the one-lane Stage I class (default 16)
+ *   "bin_deg_group"  (NIORCA_BIN_DEGREE) degree up to which a vertex with |N+| <= 16
+ *               (and not one-lane) goes to the sixteen-lane Stage I class (default 48)
  *   "bin_deg_block"  (NIORCA_BIN_DEGREE) degree from which a vertex goes to the
  *               workgroup Stage I class (default 4096)
  *   "tri_cache" 0..2^34  most triangles kept from Stage I for the tau pass (8 bytes
@@ -171,8 +173,9 @@ niorca_status niorca_stage_times(niorca_ctx *ctx, float *ms, int32_t count);
  *   4 4-cycles light, wave  5 light, workgroup   6 light, global counters
  *   7 4-cycles heavy, wave  8 heavy, workgroup   9 heavy, dense LDS counters
  *   10 heavy, global counters and the heavy-key reduction
+ *   11 Stage I/II sixteen-lane
  * Waits for the call to finish. */
-#define NIORCA_NUM_KERNEL_TIMES 11
+#define NIORCA_NUM_KERNEL_TIMES 12
 niorca_status niorca_kernel_times(niorca_ctx *ctx, float *ms, int32_t count);
 
 /* Work classes of the last count: out HOST int64[3*NIORCA_NUM_CLASSES]: vertices per
@@ -180,8 +183,9 @@ niorca_status niorca_kernel_times(niorca_ctx *ctx, float *ms, int32_t count);
  * wedges for the others), then their row slots (|N+| for the first four, |N-| for the
  * light 4-cycle classes, degree for the heavy ones).  Class order: Stage I/II wave,
  * one-lane, workgroup, large; 4-cycles light wave, light workgroup, light global;
- * heavy wave, heavy workgroup, heavy dense, heavy global.  Waits for the device. */
-#define NIORCA_NUM_CLASSES 11
+ * heavy wave, heavy workgroup, heavy dense, heavy global; Stage I/II sixteen-lane.
+ * Waits for the device. */
+#define NIORCA_NUM_CLASSES 12
 niorca_status niorca_class_stats(niorca_ctx *ctx, int64_t *out, int32_t count);
 
 /* Number of per-vertex work counters written by niorca_work_counters. */
@@ -210,12 +214,13 @@ niorca_status niorca_last_features(niorca_ctx *ctx, int32_t n, float *features, 
  * weights is a HOST float array: W1[32][6], b1[32], W2[32][32], b2[32], W3[32], b3,
  * then the feature normalisation mean[6] and inv_std[6] (1325 floats).  Items that
  * fit one wave go to the one-lane class when |N+| <= 8 and the prediction is at
- * most thr_thread, and to the workgroup class when the prediction is at least
- * thr_block; capacity limits always take precedence, so no count depends on the
- * model.  Copied into the context (and to the device); waits for the copy. */
+ * most thr_thread, else to the sixteen-lane class when |N+| <= 16 and the
+ * prediction is at most thr_group, and to the workgroup class when the prediction
+ * is at least thr_block; capacity limits always take precedence, so no count depends
+ * on the model.  Copied into the context (and to the device); waits for the copy. */
 #define NIORCA_MLP_PARAMS 1325
 niorca_status niorca_set_cost_model(niorca_ctx *ctx, const float *weights, int32_t count, float thr_thread,
-                                    float thr_block);
+                                    float thr_group, float thr_block);
 
 /* Train the work model with the library's FP32 kernels: Adam on the mean squared
  * error between the prediction and y, minibatches of `batch` rows drawn by a

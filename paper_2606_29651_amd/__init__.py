@@ -34,9 +34,9 @@ EXPORTS = ["niorca_create", "niorca_destroy", "niorca_last_error", "niorca_set_w
            "niorca_set_cost_model", "niorca_stage_times", "niorca_last_features", "niorca_mlp_train",
            "niorca_mlp_predict", "niorca_kernel_times", "niorca_class_stats"]
 KERNEL_NAMES = ["probe_thread", "probe_wave", "probe_block", "probe_large", "ql_wave", "ql_block", "ql_global",
-                "qh_wave", "qh_block", "qh_dense", "qh_global"]
+                "qh_wave", "qh_block", "qh_dense", "qh_global", "probe_group"]
 CLASS_NAMES = ["tri_wave", "tri_thread", "tri_block", "tri_large", "ql_wave", "ql_block", "ql_global",
-               "qh_wave", "qh_block", "qh_dense", "qh_global"]
+               "qh_wave", "qh_block", "qh_dense", "qh_global", "tri_group"]
 NUM_COUNTERS = 7
 MLP_PARAMS = 1325
 COUNTER_NAMES = ["probes", "triangles", "k4_words", "wedges_light", "wedges_heavy", "sum_slots", "stage1_cycles"]
@@ -78,7 +78,7 @@ def load_library():
         lib.niorca_k4.argtypes = [P, i32, i64, P, P, P, P]
         lib.niorca_fvars.argtypes = [P, i32, i64, P, P, P, P]
         lib.niorca_work_counters.argtypes = [P, i32, P, P]
-        lib.niorca_set_cost_model.argtypes = [P, P, i32, ctypes.c_float, ctypes.c_float]
+        lib.niorca_set_cost_model.argtypes = [P, P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float]
         lib.niorca_stage_times.argtypes = [P, P, i32]
         lib.niorca_kernel_times.argtypes = [P, P, i32]
         lib.niorca_class_stats.argtypes = [P, P, i32]
@@ -285,11 +285,16 @@ def mlp_predict(model, X: torch.Tensor, ctx: Context = None, stream=None) -> tor
     return out
 
 
-def set_cost_model(model, thr_thread: float, thr_block: float, ctx: Context = None, device=None):
+def set_cost_model(model, thr_thread: float, thr_block: float, thr_group: float = None, ctx: Context = None,
+                   device=None):
+    """Load the work model for BIN_MLP with its thresholds on predicted log2 work:
+    one lane up to thr_thread, sixteen lanes up to thr_group (None: no such class),
+    a workgroup from thr_block."""
     import numpy as np
     model = np.ascontiguousarray(model, dtype=np.float32)
     if model.shape != (MLP_PARAMS,):
         raise ValueError(f"model must hold {MLP_PARAMS} floats")
     ctx = ctx or context(device)
     ctx.check(ctx.lib.niorca_set_cost_model(ctx.h, model.ctypes.data_as(ctypes.c_void_p), MLP_PARAMS,
-                                            float(thr_thread), float(thr_block)), "niorca_set_cost_model")
+                                            float(thr_thread), float(-1e30 if thr_group is None else thr_group),
+                                            float(thr_block)), "niorca_set_cost_model")

@@ -21,7 +21,7 @@ struct niorca_ctx {
     // cost model for NIORCA_BIN_MLP (host copy and device copy)
     std::vector<float> mlp;
     float *mlp_dev = nullptr;
-    float thr_wave = 0.f, thr_block = 0.f;
+    float thr_thread = 0.f, thr_group = -1e30f, thr_block = 0.f;
     // where the last count left its counters and features (offsets in the workspace)
     int32_t last_n = -1;
     uint64_t last_counters = 0, last_feat = 0, last_order = 0, last_stats_dev = 0;
@@ -34,7 +34,7 @@ struct niorca_ctx {
     bool ev_valid = false;
     // tunable class thresholds and the size of the heavy 4-cycle key range
     Thresholds th{TRI_WAVE_CAP, TRI_BLOCK_CAP, 0, 16, 4096, 0.f, 0.f, nullptr,
-                  512, 8192, 1024, 2048, 2048};
+                  512, 8192, 1024, 2048, 2048, 48, -1e30f};
     // size of the heavy 4-cycle key range; -1 = chosen per call from the degrees
     int32_t heavy_k = -1;
     // the last captured batched sequence and the shape it was captured for
@@ -153,6 +153,9 @@ extern "C" niorca_status niorca_set_param(niorca_ctx *ctx, const char *name, int
     } else if (k == "bin_deg_thread") {
         if (value < 0 || value > ((int64_t)1 << 30)) return bad(0, (int64_t)1 << 30);
         ctx->th.deg_thread = (int)value;
+    } else if (k == "bin_deg_group") {
+        if (value < 0 || value > ((int64_t)1 << 30)) return bad(0, (int64_t)1 << 30);
+        ctx->th.deg_group = (int)value;
     } else if (k == "bin_deg_block") {
         if (value < 1 || value > ((int64_t)1 << 30)) return bad(1, (int64_t)1 << 30);
         ctx->th.deg_block = (int)value;
@@ -515,7 +518,8 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     if (th.bin_mode == 2) {
         HIP_TRY(mlp_predict(n, feat, ctx->mlp_dev, pred, s));
         th.pred = pred;
-        th.thr_thread = ctx->thr_wave;
+        th.thr_thread = ctx->thr_thread;
+        th.thr_group = ctx->thr_group;
         th.thr_block = ctx->thr_block;
     }
     DevGraph g{n, (i32)nnz, h0, nrp, nsplit, ncol, mirror, hstart, deg, val, wl, wh};
@@ -541,7 +545,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     };
     TriCacheArgs tca{L.tc_cap > 0 ? (u64 *)(W + L.tcrec) : nullptr, L.tc_cap, (u64 *)(W + L.tcbump),
                      (i64 *)(W + L.tcoff), (i32 *)(W + L.tccnt), chunk_for((i64)cu * 8 * 4, 2048, 1 << 14),
-                     chunk_for((i64)cu * 2, 1 << 17, 1 << 18)};
+                     chunk_for((i64)cu * 2, 1 << 17, 1 << 18), chunk_for((i64)cu * 8 * 16, 256, 1 << 12)};
     HIP_TRY(fill32(tca.bump, sizeof(u64), 0u, s));
     STAGE_MARK(4);
     HIP_TRY(launch_probe(0, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, L.large_slice, L.large_cap,
@@ -894,8 +898,9 @@ extern "C" niorca_status niorca_kernel_times(niorca_ctx *ctx, float *ms, int32_t
         return fail(ctx, NIORCA_EINVAL, "need %d floats", NIORCA_NUM_KERNEL_TIMES);
     if (!ctx->ev_valid) return fail(ctx, NIORCA_EINVAL, "the last call did not record kernel times");
     HIP_TRY(hipEventSynchronize(ctx->ev[NIORCA_NUM_STAGES]));
-    // events 0..4 bracket the Stage I/II launches, 5..12 the 4-cycle launches
-    static const int first[NIORCA_NUM_KERNEL_TIMES] = {0, 1, 2, 3, 5, 6, 7, 8, 9, 10, 11};
+    // events 0..4 bracket the Stage I/II launches, 5..12 the 4-cycle launches, 13..14
+    // the sixteen-lane Stage I launch
+    static const int first[NIORCA_NUM_KERNEL_TIMES] = {0, 1, 2, 3, 5, 6, 7, 8, 9, 10, 11, 13};
     for (int i = 0; i < NIORCA_NUM_KERNEL_TIMES; i++)
         HIP_TRY(hipEventElapsedTime(&ms[i], ctx->kev[first[i]], ctx->kev[first[i] + 1]));
     return NIORCA_OK;
@@ -915,11 +920,12 @@ extern "C" niorca_status niorca_class_stats(niorca_ctx *ctx, int64_t *out, int32
     return NIORCA_OK;
 }
 
-extern "C" niorca_status niorca_set_cost_model(niorca_ctx *ctx, const float *weights, int32_t count, float thr_wave,
-                                               float thr_block) {
+extern "C" niorca_status niorca_set_cost_model(niorca_ctx *ctx, const float *weights, int32_t count,
+                                               float thr_thread, float thr_group, float thr_block) {
     if (!ctx || !weights || count != NIORCA_MLP_PARAMS) return fail(ctx, NIORCA_EINVAL, "cost model needs %d floats", NIORCA_MLP_PARAMS);
     ctx->mlp.assign(weights, weights + count);
-    ctx->thr_wave = thr_wave;
+    ctx->thr_thread = thr_thread;
+    ctx->thr_group = thr_group;
     ctx->thr_block = thr_block;
     HIP_TRY(hipSetDevice(ctx->device));
     if (!ctx->mlp_dev && hipMalloc((void **)&ctx->mlp_dev, sizeof(float) * NIORCA_MLP_PARAMS) != hipSuccess) {

@@ -30,6 +30,15 @@ __device__ __forceinline__ int wave_incl_sum(int v) {
     return v;
 }
 
+// Inclusive sum within each 16-lane row of the wave (DPP row shifts only).
+__device__ __forceinline__ int row_incl_sum(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    return v;
+}
+
 // Adds, for every run of consecutive lanes holding the same index si, the run's
 // total of val to dst[si] with one atomic (issued by the run's last lane).  All 64
 // lanes active; lanes with nothing to add pass val = 0.  Values of 2^24 or more are

@@ -18,9 +18,11 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+// An item is worked on by NT threads: a 16-lane group of a wave (NT = 16), a wave
+// (NT = 64) or a workgroup (NT a multiple of 64).
 template <int NT>
 __device__ __forceinline__ void item_sync() {
-    if constexpr (NT == WAVE) {
+    if constexpr (NT <= WAVE) {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     } else {
@@ -31,6 +33,7 @@ __device__ __forceinline__ void item_sync() {
 // Sum over the NT threads of one item; red must hold NT/WAVE entries.
 template <int NT>
 __device__ __forceinline__ i64 item_sum(i64 v, i64 *red, int tid) {
+    if constexpr (NT < WAVE) return group_sum64<NT>(v);
     v = wave_sum64(v);
     if constexpr (NT == WAVE) {
         return v;
@@ -52,6 +55,13 @@ __device__ __forceinline__ void item_scan(i32 *a, int len, int tid, i32 *red32) 
     for (int c = 0; c < len; c += NT) {
         int i = c + tid;
         i32 v = i < len ? a[i + 1] : 0;
+        if constexpr (NT < WAVE) {
+            static_assert(NT == 16, "sub-wave items are 16-lane rows");
+            const i32 x = row_incl_sum(v);
+            if (i < len) a[i + 1] = carry + x;
+            carry += __shfl(x, (lane_id() & ~15) + 15, WAVE);
+            continue;
+        }
         i32 x = wave_incl_sum(v);
         if constexpr (NT == WAVE) {
             if (i < len) a[i + 1] = carry + x;
@@ -102,10 +112,12 @@ __device__ __forceinline__ VertexClasses classify_vertex(const DevGraph &g, cons
             tc = WC_TRI_WAVE;
             if (th.bin_mode == 1) {
                 if (du <= TRI_THREAD_CAP && d <= th.deg_thread) tc = WC_TRI_THREAD;
+                else if (du <= TRI_GROUP_CAP && d <= th.deg_group) tc = WC_TRI_GROUP;
                 else if (d >= th.deg_block) tc = WC_TRI_BLOCK;
             } else if (th.bin_mode == 2) {
                 float p = th.pred[y];
                 if (du <= TRI_THREAD_CAP && p <= th.thr_thread) tc = WC_TRI_THREAD;
+                else if (du <= TRI_GROUP_CAP && p <= th.thr_group) tc = WC_TRI_GROUP;
                 else if (p >= th.thr_block) tc = WC_TRI_BLOCK;
             }
         }
@@ -303,7 +315,8 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
                 const bool ok = rec[k] != ~0ull;
                 const int i = ok ? (int)(rec[k] & 0xffffu) : 0, p = ok ? (int)((rec[k] >> 16) & 0xffffu) : 0;
                 tau_local += tq[k];
-                wave_run_add(M.acc, i, ok ? M.tcnt[p] : 0);
+                if constexpr (NT >= WAVE) wave_run_add(M.acc, i, ok ? M.tcnt[p] : 0);
+                else if (ok) atomicAdd((unsigned long long *)&M.acc[i], (unsigned long long)M.tcnt[p]);
                 if (ok) atomicAdd((unsigned long long *)&M.acc[p], (unsigned long long)M.tcnt[i]);
             }
         }
@@ -516,6 +529,47 @@ __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__res
         un = it + 2 * waves < cnt ? list[it + 2 * waves] : -1;
         probe_item<WAVE, MODE, PW_QP>(g, cur, tid, M, HC, WORDS, t, K4, tau, nullptr, nullptr, tc, &s_st[w],
                                       counters);
+        cur = nxt;
+    }
+}
+
+// Sixteen lanes per vertex, |N+(u)| <= TRI_GROUP_CAP (16 items per 256-thread block):
+// for items with little work, which would leave most of a wave idle.
+#define PG_NT 16
+#ifndef PG_QP
+#define PG_QP 4
+#endif
+template <int MODE>
+__global__ void __launch_bounds__(256) k_probe_group(DevGraph g, const i32 *__restrict__ list,
+                                                     const GraphStats *__restrict__ st, i32 *t, i64 *K4,
+                                                     i64 *tau, TriCache tc, i64 *counters) {
+    constexpr int CAP = TRI_GROUP_CAP, HC = 2 * CAP, WORDS = 1, NG = 256 / PG_NT;
+    __shared__ i32 s_hkey[NG][HC];
+    __shared__ i32 s_hpos[NG][HC];
+    __shared__ i32 s_off[NG][CAP + 1];
+    __shared__ i32 s_nb[NG][CAP];
+    __shared__ i32 s_beg[NG][CAP];
+    __shared__ i32 s_tcnt[NG][CAP];
+    __shared__ u32 s_A[NG][CAP * WORDS];
+    __shared__ i64 s_acc[NG][CAP];
+    __shared__ ItemState s_st[NG];
+    const int gr = threadIdx.x / PG_NT, tid = threadIdx.x % PG_NT;
+    ProbeMem M{s_hkey[gr], s_hpos[gr], s_off[gr], s_nb[gr], s_beg[gr], s_tcnt[gr], s_A[gr], s_acc[gr], s_A[gr]};
+    if (tid == 0) {
+        s_st[gr].chunk_cur = s_st[gr].chunk_end = 0;
+        s_st[gr].full = 0;
+    }
+    item_sync<PG_NT>();
+    const i32 cnt = st->cnt[WC_TRI_GROUP];
+    const int groups = gridDim.x * NG;
+    i32 it = blockIdx.x * NG + gr;
+    PMeta cur = p_meta<MODE>(g, tc, it < cnt ? list[it] : -1);
+    i32 un = it + groups < cnt ? list[it + groups] : -1;
+    for (; it < cnt; it += groups) {
+        const PMeta nxt = p_meta<MODE>(g, tc, un);
+        un = it + 2 * groups < cnt ? list[it + 2 * groups] : -1;
+        probe_item<PG_NT, MODE, PG_QP>(g, cur, tid, M, HC, WORDS, t, K4, tau, nullptr, nullptr, tc, &s_st[gr],
+                                       counters);
         cur = nxt;
     }
 }
@@ -1550,6 +1604,7 @@ hipError_t launch_probe(int mode, const DevGraph &g, i32 *const *lists_host, con
     if (kev.ev) (void)hipEventRecord(kev.ev[i], s)
     TriCache tw{tca.rec, tca.cap, tca.bump, tca.off, tca.cnt, tca.chunk_wave};
     TriCache tb{tca.rec, tca.cap, tca.bump, tca.off, tca.cnt, tca.chunk_block};
+    TriCache tg{tca.rec, tca.cap, tca.bump, tca.off, tca.cnt, tca.chunk_group};
     if (mode == PROBE_TRI) {
         KMARK(0);
         hipLaunchKernelGGL(k_probe_thread<PROBE_TRI>, dim3(grid_wave), dim3(256), 0, s, g,
@@ -1565,7 +1620,13 @@ hipError_t launch_probe(int mode, const DevGraph &g, i32 *const *lists_host, con
             launch_large<PROBE_TRI>(g, lists_host[WC_TRI_LARGE], st, t, K4, tau, tb, large_scratch, large_slice,
                                  large_cap, large_hc, large_blocks, large_lds_max, counters, s);
         KMARK(4);
+        KMARK(13);
+        hipLaunchKernelGGL(k_probe_group<PROBE_TRI>, dim3(grid_wave), dim3(256), 0, s, g,
+                           lists_host[WC_TRI_GROUP], st, t, K4, tau, tg, counters);
+        KMARK(14);
     } else {
+        hipLaunchKernelGGL(k_probe_group<PROBE_TAU>, dim3(grid_wave), dim3(256), 0, s, g,
+                           lists_host[WC_TRI_GROUP], st, t, K4, tau, tg, (i64 *)nullptr);
         hipLaunchKernelGGL(k_probe_thread<PROBE_TAU>, dim3(grid_wave), dim3(256), 0, s, g,
                            lists_host[WC_TRI_THREAD], st, t, K4, tau, tw, (i64 *)nullptr);
         hipLaunchKernelGGL(k_probe_wave<PROBE_TAU>, dim3(grid_wave), dim3(256), 0, s, g, lists_host[WC_TRI_WAVE], st,

@@ -28,8 +28,9 @@ struct GraphStats {
 struct KernelEvents {
     hipEvent_t *ev;   // nullptr: no events
 };
-#define NUM_KERNEL_SLOTS 13  // probe: thread, wave, block, large; q: ql wave, ql block,
-                             // ql global, qh wave, qh block, qh dense, qh global, reduce
+#define NUM_KERNEL_SLOTS 15  // probe: thread, wave, block, large; q: ql wave, ql block,
+                             // ql global, qh wave, qh block, qh dense, qh global, reduce;
+                             // probe: group
 
 // Classes of work items (indices into GraphStats::cnt and the list table).
 enum WorkClass {
@@ -44,6 +45,7 @@ enum WorkClass {
     WC_QH_BLOCK,       // hash per workgroup
     WC_QH_DENSE,       // dense 16-bit LDS counters over the heavy range
     WC_QH_GLOBAL,      // heavy-range items of degree >= 2^16: int32 counters in global scratch
+    WC_TRI_GROUP,      // |N+(u)| <= 16 and little predicted work: sixteen lanes per vertex
     WC_COUNT
 };
 
@@ -67,12 +69,15 @@ struct Thresholds {
     i64 qh_wave;
     i64 qh_block;
     i64 ql_split;    // light workgroup items up to this many wedges use the small-table launch
+    int deg_group;   // mode 1: degree <= deg_group (and |N+| <= 16) -> sixteen lanes
+    float thr_group; // mode 2: predicted log2 work bound of the sixteen-lane class
 };
 
 #define NUM_COUNTERS 7   // per-vertex work counters (see include/niorca.h)
 
 // Class capacities (shared by classification and kernels).
 #define TRI_WAVE_CAP 64
+#define TRI_GROUP_CAP 16
 #define TRI_BLOCK_CAP 512
 #define QL_WAVE_HC 4096     // largest hash per wave, light 4-cycle items (sized per launch)
 #define QL_WAVE_DC 64       // segment (row slot) capacity per wave item
@@ -137,7 +142,7 @@ struct TriCacheArgs {
     u64 *bump;
     i64 *off;
     i32 *cnt;
-    i64 chunk_wave, chunk_block;
+    i64 chunk_wave, chunk_block, chunk_group;
 };
 hipError_t launch_probe(int mode, const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i32 *t,
                         i64 *K4, i64 *tau, const TriCacheArgs &tca, char *large_scratch, i64 large_slice,

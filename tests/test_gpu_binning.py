@@ -178,6 +178,9 @@ MODES = {
     "mlp_mid": ("mlp", (8.0, 14.0)),
     "mlp_all_thread": ("mlp", (1e9, 2e9)),
     "mlp_all_block": ("mlp", (-1e9, -1e9)),
+    "degree_all_group": ("deg", {"bin_deg_thread": 0, "bin_deg_group": 1 << 30, "bin_deg_block": 1 << 30}),
+    "mlp_group": ("mlp", (8.0, 15.0, 12.0)),
+    "mlp_all_group": ("mlp", (-1e9, 2e9, 1e9)),
 }
 
 
@@ -197,7 +200,7 @@ def test_binning_never_changes_counts(ni, mode, name):
         else:
             X, y = _trained_model(ni, ctx)
             model, _ = ni.mlp_train(X, y, epochs=1, batch=4096, lr=3e-3, seed=1, ctx=ctx)
-            ni.set_cost_model(model, arg[0], arg[1], ctx=ctx)
+            ni.set_cost_model(model, *arg, ctx=ctx)
             flags = ni.BIN_MLP
         rp, cl = _dev(g)
         got = ni.count(rp, cl, flags=flags, ctx=ctx).cpu().numpy()
