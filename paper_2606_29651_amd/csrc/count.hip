@@ -244,7 +244,8 @@ struct ProbeMem {
 // its lowest vertex u, (slot of v->w) << 32 | p << 16 | i, where i and p are the
 // positions of v and w in N+(u).  Vertex u owns records [off[u], off[u]+cnt[u]);
 // cnt[u] = -1 means its records were not kept and tau probes it again.  Space is
-// handed out in chunks per wave/workgroup, so there is one global atomic per chunk.
+// handed out in chunks per wave/workgroup, so there is one global atomic per chunk;
+// an item that may find more triangles than a chunk holds reserves its own space.
 struct TriCache {
     u64 *rec;
     i64 cap;        // records
@@ -257,6 +258,7 @@ struct TriCache {
 struct ItemState {  // per item group, in LDS
     i64 chunk_cur, chunk_end, item_base;
     i32 item_ok, item_cnt;
+    i32 item_own;   // the item reserved its records outside the chunk
     i32 full;       // the record space ran out: stop asking for chunks
 };
 
@@ -357,7 +359,18 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
         i64 ub = min((i64)total, (i64)du * (du - 1) / 2);
         S->item_ok = 0;
         S->item_cnt = 0;
-        if (tc.rec && ub <= tc.chunk && !S->full) {
+        S->item_own = 0;
+        if (tc.rec && ub > tc.chunk && !S->full) {
+            // more than a chunk: the item reserves its own space
+            u64 b = atomicAdd((unsigned long long *)tc.bump, (unsigned long long)ub);
+            if ((i64)b + ub <= tc.cap) {
+                S->item_ok = 1;
+                S->item_own = 1;
+                S->item_base = (i64)b;
+            } else {
+                S->full = 1;
+            }
+        } else if (tc.rec && !S->full) {
             if (S->chunk_end - S->chunk_cur < ub) {
                 u64 b = atomicAdd((unsigned long long *)tc.bump, (unsigned long long)tc.chunk);
                 if ((i64)b + tc.chunk <= tc.cap) {
@@ -431,7 +444,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
             if (keep) {
                 tc.off[u] = item_base;
                 tc.cnt[u] = S->item_cnt;
-                S->chunk_cur += S->item_cnt;
+                if (!S->item_own) S->chunk_cur += S->item_cnt;
             } else {
                 tc.cnt[u] = -1;
             }

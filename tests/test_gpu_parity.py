@@ -135,6 +135,7 @@ FORCED = {
     "all_large_global": dict(tri_wave=1, tri_block=1, large_lds=0),
     "tri_cache_none": dict(tri_cache=0),
     "tri_cache_small": dict(tri_cache=2000, tri_wave=8),
+    "tri_cache_partial": dict(tri_cache=300000, tri_wave=8, tri_block=32),
     "qh_wave_small": dict(qh_wave=64, heavy_k=32768),
     "qh_wave_max": dict(qh_wave=2048, heavy_k=32768),
     "q_global_light": dict(ql_wave=0, ql_block=0, heavy_k=0),
