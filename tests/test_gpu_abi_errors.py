@@ -38,6 +38,8 @@ def test_argument_errors(ni):
     assert _raw(ni, ctx, 5, 20, ok(rp), ok(cl), None) == ni.EINVAL             # NULL out
     assert _raw(ni, ctx, 5, 20, ok(rp), ok(cl), ok(out), 0x80) == ni.EINVAL    # unknown flag
     assert _raw(ni, ctx, 5, 22, ok(rp), ok(cl), ok(out)) == ni.EINVAL          # nnz > n(n-1)
+    # slot ids are int32: 2^31 slots are refused on the host, before any buffer is read
+    assert _raw(ni, ctx, 100000, 1 << 31, ok(rp), ok(cl), ok(out)) == ni.ENOTIMPL
     assert _raw(ni, ctx, 0, 0, None, None, None) == ni.OK                      # empty graph
     assert lib.niorca_set_param(ctx.h, b"no_such_knob", 1) == ni.EINVAL
     assert lib.niorca_set_param(ctx.h, b"tri_wave", 65) == ni.EINVAL
@@ -101,4 +103,18 @@ def test_workspace_limit_enomem(ni):
     got = ni.count(torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda(), ctx=ctx)
     torch.cuda.synchronize()
     assert got.shape == (g.n, 15)
+    ctx.close()
+
+
+def test_degree_overflow_guard(ni):
+    """A degree above 1.2 million could overflow the int64 counts (psi_7 = C(d, 3) and
+    the f-variable products): the call stops after the degree statistics with
+    EOVERFLOW instead of returning wrapped counts."""
+    import torch
+    g = gg.star(1_200_001)
+    ctx = ni.Context(0)
+    with pytest.raises(ni.NiorcaError) as e:
+        ni.count(torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda(), ctx=ctx)
+    assert e.value.status == ni.EOVERFLOW
+    torch.cuda.synchronize()
     ctx.close()
