@@ -88,8 +88,12 @@ __device__ __forceinline__ void atomic_add_i64(i64 *p, i64 v) {
     atomicAdd(reinterpret_cast<unsigned long long *>(p), static_cast<unsigned long long>(v));
 }
 
-// Multiplicative hash into a power-of-two table.
-__device__ __forceinline__ u32 hslot(u32 key, u32 mask) { return (key * 0x9E3779B1u >> 7) & mask; }
+// Multiplicative hash into a power-of-two table.  The 24-bit multiply is a
+// full-rate instruction (a 32-bit multiply is quarter rate); folding the high bits in
+// first keeps all 32 key bits in play.
+__device__ __forceinline__ u32 hslot(u32 key, u32 mask) {
+    return (__umul24(key ^ (key >> 15), 0x9E3779u) >> 7) & mask;
+}
 
 // Largest i in [lo, hi) with off[i] <= e, for a non-decreasing array off (lo valid).
 template <typename T>
