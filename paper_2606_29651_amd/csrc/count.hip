@@ -943,7 +943,66 @@ struct QChunk {
     i32 *vv;     // [dc]
     i32 *beg;    // [dc]
     i64 *mid;    // [dc]
+    u32 *seg;    // segment byte of each wedge of a step (NT * max(QK, QS) bytes), or null
 };
+
+// Which 4-cycle kernels locate wedges through a segment map (the map costs LDS, and
+// so occupancy, that the smaller kernels cannot spare).
+#ifndef QMAP_QLW
+#define QMAP_QLW 0
+#endif
+#ifndef QMAP_QLB
+#define QMAP_QLB 0
+#endif
+#ifndef QMAP_QHW
+#define QMAP_QHW 0
+#endif
+#ifndef QMAP_QHB
+#define QMAP_QHB 0
+#endif
+#ifndef QMAP_QD
+#define QMAP_QD 1
+#endif
+
+// Segment of every wedge e in [eb, total), eb + NT*PER at most, one byte each at
+// byte e - eb of map (chunks have at most 256 segments): thread t walks its run of
+// PER consecutive wedges from eb + t*PER on after one search, where a search per
+// wedge would cost a logarithmic number of LDS reads for each.
+template <int NT, int PER>
+__device__ __forceinline__ void q_segmap(const i32 *off, int len, i32 eb, i32 total, int tid, u32 *map) {
+    static_assert(PER % 4 == 0, "whole words per thread");
+    const i32 e0 = eb + tid * PER;
+    if (e0 >= total) return;
+    int s = 0;
+    int step = 1;
+    while (2 * step < len) step <<= 1;
+    for (; step > 0; step >>= 1) {
+        const int m = s + step;
+        if (m < len && off[m] <= e0) s = m;
+    }
+    // off[len] = total > e, so the walk stops inside the chunk
+    i32 nb = off[s + 1];
+#pragma unroll
+    for (int k4 = 0; k4 < PER / 4; k4++) {
+        u32 w = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const i32 e = e0 + 4 * k4 + b;
+            if (e < total) {
+                while (nb <= e) {
+                    s++;
+                    nb = off[s + 1];
+                }
+            }
+            w |= (u32)s << (8 * b);
+        }
+        map[tid * (PER / 4) + k4] = w;
+    }
+}
+
+__device__ __forceinline__ int seg_at(const u32 *map, i32 i) {
+    return ((const unsigned char *)map)[i];
+}
 
 // Loads chunk [c0, c0+len) of the item's slots; returns its wedge count.
 template <int NT, int MODE>
@@ -1040,7 +1099,7 @@ __device__ __forceinline__ QMeta q_meta(const DevGraph &g, i32 x) {
 // created a key's counter then credits C(c, 2) through cr, adds it to *local and
 // empties the counter, and the call returns true.  Otherwise (false) the counters
 // are left for the caller to harvest.
-template <int NT, int MODE, int QK = 0, typename Ctr, typename Credit>
+template <int NT, int MODE, int QK = 0, bool MAP = false, typename Ctr, typename Credit>
 __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, const Ctr &ctr, const QChunk &C, int dc,
                                          int tid, i32 *red32, i64 *__restrict__ Q, const Credit &cr, i64 *local) {
     const i32 x = mt.x, s0 = mt.s0, sp = mt.sp;
@@ -1053,7 +1112,17 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                 const int nj = (total + NT - 1) / NT;
                 int lo[QK];
                 i32 key[QK];
-                q_locate<NT, QK>(C.off, ns, tid, nj, lo);
+                if constexpr (MAP) {
+                    q_segmap<NT, QK>(C.off, ns, 0, total, tid, C.seg);
+                    item_sync<NT>();
+#pragma unroll
+                    for (int j = 0; j < QK; j++) {
+                        const i32 e = tid + j * NT;
+                        lo[j] = (j < nj && e < total) ? seg_at(C.seg, e) : 0;
+                    }
+                } else {
+                    q_locate<NT, QK>(C.off, ns, tid, nj, lo);
+                }
 #pragma unroll
                 for (int j = 0; j < QK; j++) {
                     const i32 e = tid + j * NT;
@@ -1111,7 +1180,18 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                 int si[QS];
                 i32 key[QS];
                 bool ok[QS];
-                q_locate<NT, QS>(C.off, len, eb + tid, nj, si);
+                if constexpr (MAP) {
+                    item_sync<NT>();  // the previous step's map has been read
+                    q_segmap<NT, QS>(C.off, len, eb, total, tid, C.seg);
+                    item_sync<NT>();
+#pragma unroll
+                    for (int u = 0; u < QS; u++) {
+                        const i32 e = eb + tid + u * NT;
+                        si[u] = (u < nj && e < total) ? seg_at(C.seg, e - eb) : 0;
+                    }
+                } else {
+                    q_locate<NT, QS>(C.off, len, eb + tid, nj, si);
+                }
 #pragma unroll
                 for (int u = 0; u < QS; u++) {
                     i32 e = eb + tid + u * NT;
@@ -1194,8 +1274,9 @@ struct LightHash {
 #ifndef QLW_QK
 #define QLW_QK 8
 #endif
+#define QLW_SEGB (QMAP_QLW ? WAVE * (QLW_QK > QS ? QLW_QK : QS) : 0)
 __host__ __device__ constexpr int qlw_wave_bytes(int hcw) {
-    return ((8 * QLW_DC + 8 * hcw + 4 * (3 * QLW_DC + 1)) + 15) / 16 * 16;
+    return ((8 * QLW_DC + QLW_SEGB + 8 * hcw + 4 * (3 * QLW_DC + 1)) + 15) / 16 * 16;
 }
 
 template <int MODE>
@@ -1205,7 +1286,8 @@ __global__ void __launch_bounds__(256) k_q_wave(DevGraph g, const i32 *__restric
     const int w = threadIdx.x / WAVE, tid = lane_id();
     char *base = s_dyn + (size_t)w * qlw_wave_bytes(hcw);
     i64 *s_mid = (i64 *)base;
-    i32 *s_key = (i32 *)(base + 8 * QLW_DC);
+    u32 *s_seg = (u32 *)(base + 8 * QLW_DC);
+    i32 *s_key = (i32 *)(base + 8 * QLW_DC + QLW_SEGB);
     i32 *s_cnt = s_key + hcw;
     i32 *s_off = s_cnt + hcw;
     i32 *s_vv = s_off + QLW_DC + 1;
@@ -1215,7 +1297,7 @@ __global__ void __launch_bounds__(256) k_q_wave(DevGraph g, const i32 *__restric
         s_cnt[i] = 0;
     }
     item_sync<WAVE>();
-    QChunk C{s_off, s_vv, s_beg, s_mid};
+    QChunk C{s_off, s_vv, s_beg, s_mid, s_seg};
     const i32 cnt = st->cnt[wc];
     const int waves = gridDim.x * 4;
     i32 it = blockIdx.x * 4 + w;
@@ -1229,7 +1311,7 @@ __global__ void __launch_bounds__(256) k_q_wave(DevGraph g, const i32 *__restric
         const int hc = need >= hcw ? hcw : (need <= 64 ? 64 : (int)(1u << (32 - __clz((u32)(need - 1)))));
         LightHash H{s_key, s_cnt, (u32)hc - 1};
         i64 local = 0;
-        const bool taken = q_sweeps<WAVE, MODE, QLW_QK>(g, cur, H, C, QLW_DC, tid, nullptr, Q, CreditLight{Q}, &local);
+        const bool taken = q_sweeps<WAVE, MODE, QLW_QK, QMAP_QLW>(g, cur, H, C, QLW_DC, tid, nullptr, Q, CreditLight{Q}, &local);
         for (int j = tid; !taken && j < hc; j += WAVE) {
             const i32 k = s_key[j];
             if (k >= 0) {
@@ -1254,8 +1336,10 @@ __global__ void __launch_bounds__(256) k_q_wave(DevGraph g, const i32 *__restric
 // per item, at most hcb entries (dynamic LDS given with the launch).
 #define QLB_DC 256
 #define QLB_NT 256
+#define QLB_QK 16
+#define QLB_SEGB (QMAP_QLB ? QLB_NT * (QLB_QK > QS ? QLB_QK : QS) : 0)
 __host__ __device__ constexpr int qlb_bytes(int hcb) {
-    return ((8 * QLB_DC + 8 * hcb + 4 * (3 * QLB_DC + 1)) + 15) / 16 * 16;
+    return ((8 * QLB_DC + QLB_SEGB + 8 * hcb + 4 * (3 * QLB_DC + 1)) + 15) / 16 * 16;
 }
 
 // Items of the list with wlo < wedges <= whi only (the class is split into two
@@ -1268,7 +1352,8 @@ __global__ void __launch_bounds__(QLB_NT) k_q_block(DevGraph g, const i32 *__res
     __shared__ i64 s_red[QLB_NT / WAVE];
     __shared__ i32 s_red32[QLB_NT / WAVE];
     i64 *s_mid = (i64 *)s_dyn;
-    i32 *s_key = (i32 *)(s_dyn + 8 * QLB_DC);
+    u32 *s_seg = (u32 *)(s_dyn + 8 * QLB_DC);
+    i32 *s_key = (i32 *)(s_dyn + 8 * QLB_DC + QLB_SEGB);
     i32 *s_cnt = s_key + hcb;
     i32 *s_off = s_cnt + hcb;
     i32 *s_vv = s_off + QLB_DC + 1;
@@ -1278,7 +1363,7 @@ __global__ void __launch_bounds__(QLB_NT) k_q_block(DevGraph g, const i32 *__res
         s_cnt[i] = 0;
     }
     __syncthreads();
-    QChunk C{s_off, s_vv, s_beg, s_mid};
+    QChunk C{s_off, s_vv, s_beg, s_mid, s_seg};
     const i32 cnt = st->cnt[wc];
     i32 it = blockIdx.x;
     QMeta cur = q_meta<MODE>(g, it < cnt ? list[it] : -1);
@@ -1295,7 +1380,8 @@ __global__ void __launch_bounds__(QLB_NT) k_q_block(DevGraph g, const i32 *__res
         LightHash H{s_key, s_cnt, (u32)hc - 1};
         i64 local = 0;
         const bool taken =
-            q_sweeps<QLB_NT, MODE, 16>(g, cur, H, C, QLB_DC, threadIdx.x, s_red32, Q, CreditLight{Q}, &local);
+            q_sweeps<QLB_NT, MODE, QLB_QK, QMAP_QLB>(g, cur, H, C, QLB_DC, threadIdx.x, s_red32, Q, CreditLight{Q},
+                                                     &local);
         for (int j = threadIdx.x; !taken && j < hc; j += QLB_NT) {
             const i32 k = s_key[j];
             if (k >= 0) {
@@ -1370,7 +1456,7 @@ struct PackedHash {
     }
 };
 
-template <int NT, int QK>
+template <int NT, int QK, bool MAP>
 __device__ __forceinline__ void qh_item_packed(const DevGraph &g, const QMeta &mt, const PackedHash &H0, int hc_max,
                                                const QChunk &C, int dc, int tid, i64 *red, i32 *red32,
                                                i64 *__restrict__ Q, i64 *__restrict__ prow) {
@@ -1381,7 +1467,8 @@ __device__ __forceinline__ void qh_item_packed(const DevGraph &g, const QMeta &m
     const int hc = need >= hc_max ? hc_max : (need <= 64 ? 64 : (int)(1u << (32 - __clz((u32)(need - 1)))));
     PackedHash H{H0.tab, (u32)hc - 1, H0.h0};
     i64 local = 0;
-    const bool taken = q_sweeps<NT, Q_HEAVY, QK>(g, mt, H, C, dc, tid, red32, Q, CreditHeavy{prow, H0.h0}, &local);
+    const bool taken =
+        q_sweeps<NT, Q_HEAVY, QK, MAP>(g, mt, H, C, dc, tid, red32, Q, CreditHeavy{prow, H0.h0}, &local);
     for (int j = tid; !taken && j < hc; j += NT) {
         u32 cur = H.tab[j];
         if (cur != PK_EMPTY) {
@@ -1405,24 +1492,26 @@ __device__ __forceinline__ void qh_item_packed(const DevGraph &g, const QMeta &m
 #ifndef QHW_QK
 #define QHW_QK 16
 #endif
+#define QHW_SEGB (QMAP_QHW ? WAVE * (QHW_QK > QS ? QHW_QK : QS) : 0)
 __host__ __device__ constexpr int qhw_wave_bytes(int hcw) {
-    return ((8 * QHW_DC + 4 * hcw + 4 * (3 * QHW_DC + 1)) + 15) / 16 * 16;
+    return ((8 * QHW_DC + QHW_SEGB + 4 * hcw + 4 * (3 * QHW_DC + 1)) + 15) / 16 * 16;
 }
-__global__ void __launch_bounds__(256) k_qh_wave(DevGraph g, const i32 *__restrict__ list,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QMAP_QHW ? 4 : 1))) k_qh_wave(DevGraph g, const i32 *__restrict__ list,
                                                  const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 K,
                                                  int hcw) {
     extern __shared__ __align__(16) char s_dyn[];
     const int w = threadIdx.x / WAVE, tid = lane_id();
     char *base = s_dyn + (size_t)w * qhw_wave_bytes(hcw);
     i64 *s_mid = (i64 *)base;
-    u32 *s_tab = (u32 *)(base + 8 * QHW_DC);
+    u32 *s_seg = (u32 *)(base + 8 * QHW_DC);
+    u32 *s_tab = (u32 *)(base + 8 * QHW_DC + QHW_SEGB);
     i32 *s_off = (i32 *)(s_tab + hcw);
     i32 *s_vv = s_off + QHW_DC + 1;
     i32 *s_beg = s_vv + QHW_DC;
     for (int i = tid; i < hcw; i += WAVE) s_tab[i] = PK_EMPTY;
     item_sync<WAVE>();
     PackedHash H{s_tab, (u32)hcw - 1, g.h0};
-    QChunk C{s_off, s_vv, s_beg, s_mid};
+    QChunk C{s_off, s_vv, s_beg, s_mid, s_seg};
     i64 *prow = part + (i64)(blockIdx.x % QH_PART_ROWS) * K;
     const i32 cnt = st->cnt[WC_QH_WAVE];
     const int waves = gridDim.x * 4;
@@ -1432,7 +1521,7 @@ __global__ void __launch_bounds__(256) k_qh_wave(DevGraph g, const i32 *__restri
     for (; it < cnt; it += waves) {
         const QMeta nxt = q_meta<Q_HEAVY>(g, xn);
         xn = it + 2 * waves < cnt ? list[it + 2 * waves] : -1;
-        qh_item_packed<WAVE, QHW_QK>(g, cur, H, hcw, C, QHW_DC, tid, nullptr, nullptr, Q, prow);
+        qh_item_packed<WAVE, QHW_QK, QMAP_QHW>(g, cur, H, hcw, C, QHW_DC, tid, nullptr, nullptr, Q, prow);
         cur = nxt;
     }
 }
@@ -1445,6 +1534,7 @@ __global__ void __launch_bounds__(256) k_qh_wave(DevGraph g, const i32 *__restri
 __global__ void __launch_bounds__(QHB_NT) k_qh_block(DevGraph g, const i32 *__restrict__ list,
                                                      const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 K) {
     __shared__ u32 s_tab[QHB_HC];
+    __shared__ u32 s_seg[QMAP_QHB ? QHB_NT * (QHB_HC / 2 / QHB_NT > QS ? QHB_HC / 2 / QHB_NT : QS) / 4 : 1];
     __shared__ i32 s_off[QHB_DC + 1];
     __shared__ i32 s_vv[QHB_DC];
     __shared__ i32 s_beg[QHB_DC];
@@ -1454,7 +1544,7 @@ __global__ void __launch_bounds__(QHB_NT) k_qh_block(DevGraph g, const i32 *__re
     for (int i = threadIdx.x; i < QHB_HC; i += QHB_NT) s_tab[i] = PK_EMPTY;
     __syncthreads();
     PackedHash H{s_tab, QHB_HC - 1, g.h0};
-    QChunk C{s_off, s_vv, s_beg, s_mid};
+    QChunk C{s_off, s_vv, s_beg, s_mid, s_seg};
     i64 *prow = part + (i64)(blockIdx.x % QH_PART_ROWS) * K;
     const i32 cnt = st->cnt[WC_QH_BLOCK];
     i32 it = blockIdx.x;
@@ -1463,8 +1553,8 @@ __global__ void __launch_bounds__(QHB_NT) k_qh_block(DevGraph g, const i32 *__re
     for (; it < cnt; it += gridDim.x) {
         const QMeta nxt = q_meta<Q_HEAVY>(g, xn);
         xn = it + 2 * (i32)gridDim.x < cnt ? list[it + 2 * gridDim.x] : -1;
-        qh_item_packed<QHB_NT, QHB_HC / 2 / QHB_NT>(g, cur, H, QHB_HC, C, QHB_DC, threadIdx.x, s_red, s_red32, Q,
-                                                    prow);
+        qh_item_packed<QHB_NT, QHB_HC / 2 / QHB_NT, QMAP_QHB>(g, cur, H, QHB_HC, C, QHB_DC, threadIdx.x, s_red,
+                                                              s_red32, Q, prow);
         cur = nxt;
     }
 }
@@ -1486,9 +1576,10 @@ __global__ void k_qh_reduce(const i64 *__restrict__ part, int rows, i32 K, i32 h
 #define QD_QK 16  // wedges per thread kept in registers by the dense kernel
 #endif
 #define QD_DC 256
-__global__ void __launch_bounds__(QD_NT) k_q_dense(DevGraph g, const i32 *__restrict__ list,
+__global__ void __launch_bounds__(QD_NT) __attribute__((amdgpu_waves_per_eu(4))) k_q_dense(DevGraph g, const i32 *__restrict__ list,
                                                    const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 Kp) {
     __shared__ u32 s_w[QH_DENSE_K / 2];
+    __shared__ u32 s_seg[QMAP_QD ? QD_NT * (QD_QK > QS ? QD_QK : QS) / 4 : 1];
     __shared__ i32 s_off[QD_DC + 1];
     __shared__ i32 s_vv[QD_DC];
     __shared__ i32 s_beg[QD_DC];
@@ -1500,14 +1591,15 @@ __global__ void __launch_bounds__(QD_NT) k_q_dense(DevGraph g, const i32 *__rest
     for (int i = threadIdx.x; i < KW; i += QD_NT) s_w[i] = 0u;
     __syncthreads();
     DenseCounter ctr{s_w, g.h0};
-    QChunk C{s_off, s_vv, s_beg, s_mid};
+    QChunk C{s_off, s_vv, s_beg, s_mid, s_seg};
     i64 *prow = part + (i64)(blockIdx.x % QH_PART_ROWS) * Kp;
     const i32 cnt = st->cnt[WC_QH_DENSE];
     for (i32 it = blockIdx.x; it < cnt; it += gridDim.x) {
         i32 x = list[it];
         i64 local = 0;
-        const bool taken = q_sweeps<QD_NT, Q_HEAVY, QD_QK>(g, q_meta<Q_HEAVY>(g, x), ctr, C, QD_DC, threadIdx.x,
-                                                           s_red32, Q, CreditHeavy{prow, g.h0}, &local);
+        const bool taken = q_sweeps<QD_NT, Q_HEAVY, QD_QK, QMAP_QD>(g, q_meta<Q_HEAVY>(g, x), ctr, C, QD_DC,
+                                                                     threadIdx.x, s_red32, Q,
+                                                                     CreditHeavy{prow, g.h0}, &local);
         for (i32 i = threadIdx.x; !taken && i < KW; i += QD_NT) {
             u32 word = s_w[i];
             if (word) {
