@@ -227,6 +227,10 @@ enum { PROBE_TRI = 0, PROBE_TAU = 1 };
 #define QS 8  // wedges per thread per step in the 4-cycle sweeps
 #endif
 
+// Row pitch (in words) of the bitset of H_u: odd, so that lanes reading word k of
+// consecutive rows hit distinct LDS banks.
+__host__ __device__ constexpr int bit_pitch(int cap) { return ((cap + 31) / 32) | 1; }
+
 struct ProbeMem {
     i32 *hkey;   // [hc]
     i32 *hpos;   // [hc]
@@ -234,7 +238,7 @@ struct ProbeMem {
     i32 *nb;     // [cap]
     i32 *beg;    // [cap]: first slot of N+(nb[i])
     i32 *tcnt;   // [cap]
-    u32 *A;      // [cap*words]
+    u32 *A;      // [cap*pitch]: row i is the bitset of i's neighbours in H_u
     i64 *acc;    // [cap]
     u32 *A_k4;   // where the 4-clique pass reads the bitset: A itself, or an LDS copy
                  // taken after the probes (over the then unused hash and slot arrays)
@@ -285,7 +289,7 @@ __device__ __forceinline__ PMeta p_meta(const DevGraph &g, const TriCache &tc, i
 
 template <int NT, int MODE, int QP>
 __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, int tid, const ProbeMem &M, int hc,
-                                           int words, i32 *__restrict__ t, i64 *__restrict__ K4,
+                                           int pitch, i32 *__restrict__ t, i64 *__restrict__ K4,
                                            i64 *__restrict__ tau, i64 *red, i32 *red32, const TriCache &tc,
                                            ItemState *S, i64 *__restrict__ counters) {
     const i64 t_start = (counters && MODE == PROBE_TRI) ? (i64)clock64() : 0;
@@ -345,10 +349,12 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
         u32 sl = hslot((u32)v, hmask);
         while (atomicCAS(&M.hkey[sl], -1, v) != -1) sl = (sl + 1) & hmask;
         M.hpos[sl] = i;
-        M.acc[i] = 0;
+        // acc serves the tau pass only; the triangle pass leaves it alone, so that
+        // its kernels need no LDS for it
+        if (MODE == PROBE_TAU) M.acc[i] = 0;
         if (MODE == PROBE_TRI) {
             M.tcnt[i] = 0;
-            for (int k = 0; k < nw; k++) M.A[i * words + k] = 0u;
+            for (int k = 0; k < nw; k++) M.A[i * pitch + k] = 0u;
         }
     }
     item_sync<NT>();
@@ -425,8 +431,8 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
                 atomicAdd(&M.tcnt[i], 1);
                 atomicAdd(&M.tcnt[p], 1);
                 atomicAdd(&t[q], 1);
-                atomicOr(&M.A[i * words + (p >> 5)], 1u << (p & 31));
-                atomicOr(&M.A[p * words + (i >> 5)], 1u << (i & 31));
+                atomicOr(&M.A[i * pitch + (p >> 5)], 1u << (p & 31));
+                atomicOr(&M.A[p * pitch + (i >> 5)], 1u << (i & 31));
                 if (keep) {
                     i32 r = atomicAdd(&S->item_cnt, 1);
                     tc.rec[item_base + r] = ((u64)(u32)q << 32) | ((u64)p << 16) | (u64)i;
@@ -458,19 +464,19 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
         const u32 *A = M.A_k4;
         if (A != M.A) {
             item_sync<NT>();
-            for (int i = tid; i < du * words; i += NT) M.A_k4[i] = M.A[i];
+            for (int i = tid; i < du * pitch; i += NT) M.A_k4[i] = M.A[i];
             item_sync<NT>();
         }
         for (int j = tid; j < du; j += NT) {
             i64 sj = 0;
             for (int wd = 0; wd < nw; wd++) {
-                u32 bits = A[j * words + wd];
+                u32 bits = A[j * pitch + wd];
                 while (bits) {
                     int b = __ffs(bits) - 1;
                     bits &= bits - 1;
                     int i = wd * 32 + b;
                     words_scanned += nw;
-                    for (int k = 0; k < nw; k++) sj += __popc(A[i * words + k] & A[j * words + k]);
+                    for (int k = 0; k < nw; k++) sj += __popc(A[i * pitch + k] & A[j * pitch + k]);
                 }
             }
             // sj = 2 x (triangles of H_u through j) = 2 x (4-cliques containing u and nb[j])
@@ -514,14 +520,14 @@ template <int MODE>
 __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__restrict__ list,
                                                     const GraphStats *__restrict__ st, i32 *t, i64 *K4,
                                                     i64 *tau, TriCache tc, i64 *counters) {
-    constexpr int CAP = TRI_WAVE_CAP, HC = 2 * CAP, WORDS = CAP / 32;
+    constexpr int CAP = TRI_WAVE_CAP, HC = 2 * CAP, PITCH = bit_pitch(CAP);
     __shared__ i32 s_hkey[4][HC];
     __shared__ i32 s_hpos[4][HC];
     __shared__ i32 s_off[4][CAP + 1];
     __shared__ i32 s_nb[4][CAP];
     __shared__ i32 s_beg[4][CAP];
     __shared__ i32 s_tcnt[4][CAP];
-    __shared__ u32 s_A[4][CAP * WORDS];
+    __shared__ u32 s_A[4][CAP * PITCH];
     __shared__ i64 s_acc[4][CAP];
     __shared__ ItemState s_st[4];
     const int w = threadIdx.x / WAVE, tid = lane_id();
@@ -540,7 +546,7 @@ __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__res
         // the next item's row bounds and the one after's id load while this one runs
         const PMeta nxt = p_meta<MODE>(g, tc, un);
         un = it + 2 * waves < cnt ? list[it + 2 * waves] : -1;
-        probe_item<WAVE, MODE, PW_QP>(g, cur, tid, M, HC, WORDS, t, K4, tau, nullptr, nullptr, tc, &s_st[w],
+        probe_item<WAVE, MODE, PW_QP>(g, cur, tid, M, HC, PITCH, t, K4, tau, nullptr, nullptr, tc, &s_st[w],
                                       counters);
         cur = nxt;
     }
@@ -556,14 +562,14 @@ template <int MODE>
 __global__ void __launch_bounds__(256) k_probe_group(DevGraph g, const i32 *__restrict__ list,
                                                      const GraphStats *__restrict__ st, i32 *t, i64 *K4,
                                                      i64 *tau, TriCache tc, i64 *counters) {
-    constexpr int CAP = TRI_GROUP_CAP, HC = 2 * CAP, WORDS = 1, NG = 256 / PG_NT;
+    constexpr int CAP = TRI_GROUP_CAP, HC = 2 * CAP, PITCH = bit_pitch(CAP), NG = 256 / PG_NT;
     __shared__ i32 s_hkey[NG][HC];
     __shared__ i32 s_hpos[NG][HC];
     __shared__ i32 s_off[NG][CAP + 1];
     __shared__ i32 s_nb[NG][CAP];
     __shared__ i32 s_beg[NG][CAP];
     __shared__ i32 s_tcnt[NG][CAP];
-    __shared__ u32 s_A[NG][CAP * WORDS];
+    __shared__ u32 s_A[NG][CAP * PITCH];
     __shared__ i64 s_acc[NG][CAP];
     __shared__ ItemState s_st[NG];
     const int gr = threadIdx.x / PG_NT, tid = threadIdx.x % PG_NT;
@@ -581,7 +587,7 @@ __global__ void __launch_bounds__(256) k_probe_group(DevGraph g, const i32 *__re
     for (; it < cnt; it += groups) {
         const PMeta nxt = p_meta<MODE>(g, tc, un);
         un = it + 2 * groups < cnt ? list[it + 2 * groups] : -1;
-        probe_item<PG_NT, MODE, PG_QP>(g, cur, tid, M, HC, WORDS, t, K4, tau, nullptr, nullptr, tc, &s_st[gr],
+        probe_item<PG_NT, MODE, PG_QP>(g, cur, tid, M, HC, PITCH, t, K4, tau, nullptr, nullptr, tc, &s_st[gr],
                                        counters);
         cur = nxt;
     }
@@ -595,14 +601,14 @@ template <int MODE>
 __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__restrict__ list,
                                                      const GraphStats *__restrict__ st, i32 *t, i64 *K4,
                                                      i64 *tau, TriCache tc, i64 *counters) {
-    constexpr int CAP = TRI_BLOCK_CAP, HC = 2 * CAP, WORDS = CAP / 32;
+    constexpr int CAP = TRI_BLOCK_CAP, HC = 2 * CAP, PITCH = bit_pitch(CAP);
     __shared__ i32 s_hkey[HC];
     __shared__ i32 s_hpos[HC];
     __shared__ i32 s_off[CAP + 1];
     __shared__ i32 s_nb[CAP];
     __shared__ i32 s_beg[CAP];
     __shared__ i32 s_tcnt[CAP];
-    __shared__ u32 s_A[CAP * WORDS];
+    __shared__ u32 s_A[CAP * PITCH];
     __shared__ i64 s_acc[CAP];
     __shared__ i64 s_red[PB_NT / WAVE];
     __shared__ i32 s_red32[PB_NT / WAVE];
@@ -620,7 +626,7 @@ __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__
     for (; it < cnt; it += gridDim.x) {
         const PMeta nxt = p_meta<MODE>(g, tc, un);
         un = it + 2 * (i32)gridDim.x < cnt ? list[it + 2 * gridDim.x] : -1;
-        probe_item<PB_NT, MODE, PB_QP>(g, cur, threadIdx.x, M, HC, WORDS, t, K4, tau, s_red, s_red32, tc, &s_st,
+        probe_item<PB_NT, MODE, PB_QP>(g, cur, threadIdx.x, M, HC, PITCH, t, K4, tau, s_red, s_red32, tc, &s_st,
                                    counters);
         cur = nxt;
     }
@@ -723,7 +729,7 @@ __host__ __device__ inline i64 probe_large_lds_bytes(int cap, int hc) {
     return (i64)sizeof(i32) * (2 * (i64)hc + 4 * (i64)cap + 1);
 }
 __host__ __device__ inline i64 probe_large_k4_bytes(int cap, int hc) {
-    const i64 words = (cap + 31) / 32;
+    const i64 words = bit_pitch(cap);
     const i64 probe = (i64)sizeof(i32) * (2 * (i64)hc + 3 * (i64)cap + 1);
     const i64 k4 = (i64)sizeof(u32) * cap * words;
     return (i64)sizeof(i32) * cap + (probe > k4 ? probe : k4);
@@ -737,7 +743,7 @@ __global__ void __launch_bounds__(PL_NT) k_probe_large(DevGraph g, const i32 *__
     extern __shared__ __align__(16) char s_dyn[];
     __shared__ i64 s_red[PL_NT / WAVE];
     __shared__ i32 s_red32[PL_NT / WAVE];
-    const int words = (cap + 31) / 32;
+    const int words = bit_pitch(cap);
     char *p = scratch + (i64)blockIdx.x * slice_bytes;
     ProbeMem M;
     M.acc = (i64 *)p; p += sizeof(i64) * cap;
@@ -774,7 +780,7 @@ __global__ void __launch_bounds__(PL_NT) k_probe_large(DevGraph g, const i32 *__
 }
 
 i64 probe_large_slice_bytes(int cap, int hc, i64 lds_max) {
-    int words = (cap + 31) / 32;
+    int words = bit_pitch(cap);
     i64 b = sizeof(i64) * cap + sizeof(u32) * (i64)cap * words;
     if (probe_large_lds_bytes(cap, hc) > lds_max) b += probe_large_lds_bytes(cap, hc);
     return (b + 255) & ~255ll;
