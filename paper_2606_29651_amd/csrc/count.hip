@@ -221,6 +221,47 @@ __device__ __forceinline__ void q_locate(const i32 *off, int len, i32 e0, int nj
     }
 }
 
+// Segment of every element e in [eb, total), eb + NT*PER at most, of a run of
+// segments with prefix offsets off[0..len] (at most 256 segments), one byte each at
+// byte e - eb of map: thread t walks its run of PER consecutive elements from
+// eb + t*PER on after one search, where a search per element would cost a
+// logarithmic number of LDS reads for each.
+template <int NT, int PER>
+__device__ __forceinline__ void q_segmap(const i32 *off, int len, i32 eb, i32 total, int tid, u32 *map) {
+    static_assert(PER % 4 == 0, "whole words per thread");
+    const i32 e0 = eb + tid * PER;
+    if (e0 >= total) return;
+    int s = 0;
+    int step = 1;
+    while (2 * step < len) step <<= 1;
+    for (; step > 0; step >>= 1) {
+        const int m = s + step;
+        if (m < len && off[m] <= e0) s = m;
+    }
+    // off[len] = total > e, so the walk stops inside the chunk
+    i32 nb = off[s + 1];
+#pragma unroll
+    for (int k4 = 0; k4 < PER / 4; k4++) {
+        u32 w = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const i32 e = e0 + 4 * k4 + b;
+            if (e < total) {
+                while (nb <= e) {
+                    s++;
+                    nb = off[s + 1];
+                }
+            }
+            w |= (u32)s << (8 * b);
+        }
+        map[tid * (PER / 4) + k4] = w;
+    }
+}
+
+__device__ __forceinline__ int seg_at(const u32 *map, i32 i) {
+    return ((const unsigned char *)map)[i];
+}
+
 enum { PROBE_TRI = 0, PROBE_TAU = 1 };
 
 #ifndef QS
@@ -242,6 +283,7 @@ struct ProbeMem {
     i64 *acc;    // [cap]
     u32 *A_k4;   // where the 4-clique pass reads the bitset: A itself, or an LDS copy
                  // taken after the probes (over the then unused hash and slot arrays)
+    u32 *seg;    // segment byte of each probe of a map block (NT*MP bytes), or null
 };
 
 // Triangle records kept by Stage I for the tau pass: one u64 per triangle found at
@@ -287,7 +329,7 @@ __device__ __forceinline__ PMeta p_meta(const DevGraph &g, const TriCache &tc, i
     return m;
 }
 
-template <int NT, int MODE, int QP>
+template <int NT, int MODE, int QP, int MP = 0>
 __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, int tid, const ProbeMem &M, int hc,
                                            int pitch, i32 *__restrict__ t, i64 *__restrict__ K4,
                                            i64 *__restrict__ tau, i64 *red, i32 *red32, const TriCache &tc,
@@ -398,12 +440,29 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
     const i64 item_base = keep ? S->item_base : 0;
     i64 tau_local = 0;
     // rounds of NT*QP probes: each thread locates its QP probes together, then
-    // issues all their loads before the first hash lookup
+    // issues all their loads before the first hash lookup.  With MP > 0 the
+    // probes are located through a segment map built every MP/QP rounds.
+    static_assert(MP % QP == 0, "map blocks hold whole rounds");
+    i32 mbase = 0;
     for (i32 eb = 0; eb < total; eb += NT * QP) {
         const int nj = min(QP, (total - eb + NT - 1) / NT);
         int lo[QP];
         i32 qq[QP], ww[QP];
-        q_locate<NT, QP>(M.off, du, eb + tid, nj, lo);
+        if constexpr (MP > 0) {
+            if (eb % (NT * MP) == 0) {
+                mbase = eb;
+                item_sync<NT>();  // the previous block's map has been read
+                q_segmap<NT, MP>(M.off, du, eb, total, tid, M.seg);
+                item_sync<NT>();
+            }
+#pragma unroll
+            for (int j = 0; j < QP; j++) {
+                const i32 e = eb + tid + j * NT;
+                lo[j] = (j < nj && e < total) ? seg_at(M.seg, e - mbase) : 0;
+            }
+        } else {
+            q_locate<NT, QP>(M.off, du, eb + tid, nj, lo);
+        }
 #pragma unroll
         for (int j = 0; j < QP; j++) {
             const i32 e = eb + tid + j * NT;
@@ -516,6 +575,9 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
 #ifndef PL_QP
 #define PL_QP 4   // probes per thread and round, large items
 #endif
+#ifndef PW_MP
+#define PW_MP 16  // probes per thread of a segment-map block, wave items (0: search)
+#endif
 template <int MODE>
 __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__restrict__ list,
                                                     const GraphStats *__restrict__ st, i32 *t, i64 *K4,
@@ -529,9 +591,10 @@ __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__res
     __shared__ i32 s_tcnt[4][CAP];
     __shared__ u32 s_A[4][CAP * PITCH];
     __shared__ i64 s_acc[4][CAP];
+    __shared__ u32 s_seg[4][PW_MP > 0 ? WAVE * PW_MP / 4 : 1];
     __shared__ ItemState s_st[4];
     const int w = threadIdx.x / WAVE, tid = lane_id();
-    ProbeMem M{s_hkey[w], s_hpos[w], s_off[w], s_nb[w], s_beg[w], s_tcnt[w], s_A[w], s_acc[w], s_A[w]};
+    ProbeMem M{s_hkey[w], s_hpos[w], s_off[w], s_nb[w], s_beg[w], s_tcnt[w], s_A[w], s_acc[w], s_A[w], s_seg[w]};
     if (tid == 0) {
         s_st[w].chunk_cur = s_st[w].chunk_end = 0;
         s_st[w].full = 0;
@@ -546,8 +609,8 @@ __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__res
         // the next item's row bounds and the one after's id load while this one runs
         const PMeta nxt = p_meta<MODE>(g, tc, un);
         un = it + 2 * waves < cnt ? list[it + 2 * waves] : -1;
-        probe_item<WAVE, MODE, PW_QP>(g, cur, tid, M, HC, PITCH, t, K4, tau, nullptr, nullptr, tc, &s_st[w],
-                                      counters);
+        probe_item<WAVE, MODE, PW_QP, PW_MP>(g, cur, tid, M, HC, PITCH, t, K4, tau, nullptr, nullptr, tc,
+                                             &s_st[w], counters);
         cur = nxt;
     }
 }
@@ -970,45 +1033,6 @@ struct QChunk {
 #define QMAP_QD 1
 #endif
 
-// Segment of every wedge e in [eb, total), eb + NT*PER at most, one byte each at
-// byte e - eb of map (chunks have at most 256 segments): thread t walks its run of
-// PER consecutive wedges from eb + t*PER on after one search, where a search per
-// wedge would cost a logarithmic number of LDS reads for each.
-template <int NT, int PER>
-__device__ __forceinline__ void q_segmap(const i32 *off, int len, i32 eb, i32 total, int tid, u32 *map) {
-    static_assert(PER % 4 == 0, "whole words per thread");
-    const i32 e0 = eb + tid * PER;
-    if (e0 >= total) return;
-    int s = 0;
-    int step = 1;
-    while (2 * step < len) step <<= 1;
-    for (; step > 0; step >>= 1) {
-        const int m = s + step;
-        if (m < len && off[m] <= e0) s = m;
-    }
-    // off[len] = total > e, so the walk stops inside the chunk
-    i32 nb = off[s + 1];
-#pragma unroll
-    for (int k4 = 0; k4 < PER / 4; k4++) {
-        u32 w = 0;
-#pragma unroll
-        for (int b = 0; b < 4; b++) {
-            const i32 e = e0 + 4 * k4 + b;
-            if (e < total) {
-                while (nb <= e) {
-                    s++;
-                    nb = off[s + 1];
-                }
-            }
-            w |= (u32)s << (8 * b);
-        }
-        map[tid * (PER / 4) + k4] = w;
-    }
-}
-
-__device__ __forceinline__ int seg_at(const u32 *map, i32 i) {
-    return ((const unsigned char *)map)[i];
-}
 
 // Loads chunk [c0, c0+len) of the item's slots; returns its wedge count.
 template <int NT, int MODE>
