@@ -221,23 +221,30 @@ __device__ __forceinline__ void q_locate(const i32 *off, int len, i32 e0, int nj
     }
 }
 
-// Segment of every element e in [eb, total), eb + NT*PER at most, of a run of
-// segments with prefix offsets off[0..len] (at most 256 segments), one byte each at
-// byte e - eb of map: thread t walks its run of PER consecutive elements from
-// eb + t*PER on after one search, where a search per element would cost a
-// logarithmic number of LDS reads for each.
-template <int NT, int PER>
-__device__ __forceinline__ void q_segmap(const i32 *off, int len, i32 eb, i32 total, int tid, u32 *map) {
-    static_assert(PER % 4 == 0, "whole words per thread");
-    const i32 e0 = eb + tid * PER;
-    if (e0 >= total) return;
+// Largest i in [0, len) with off[i] <= e (off non-decreasing, off[0] = 0 <= e).
+__device__ __forceinline__ int seg_search(const i32 *off, int len, i32 e) {
     int s = 0;
     int step = 1;
     while (2 * step < len) step <<= 1;
     for (; step > 0; step >>= 1) {
         const int m = s + step;
-        if (m < len && off[m] <= e0) s = m;
+        if (m < len && off[m] <= e) s = m;
     }
+    return s;
+}
+
+// Segment of every element e in [eb, total), eb + NT*PER at most, of a run of
+// segments with prefix offsets off[0..len], less sbase, one byte each at byte e - eb
+// of map (the segments of the block lie in [sbase, sbase + 256)): thread t walks its
+// run of PER consecutive elements from eb + t*PER on after one search, where a
+// search per element would cost a logarithmic number of LDS reads for each.
+template <int NT, int PER>
+__device__ __forceinline__ void q_segmap(const i32 *off, int len, i32 eb, i32 total, int tid, u32 *map,
+                                         int sbase = 0) {
+    static_assert(PER % 4 == 0, "whole words per thread");
+    const i32 e0 = eb + tid * PER;
+    if (e0 >= total) return;
+    int s = seg_search(off, len, e0);
     // off[len] = total > e, so the walk stops inside the chunk
     i32 nb = off[s + 1];
 #pragma unroll
@@ -252,7 +259,7 @@ __device__ __forceinline__ void q_segmap(const i32 *off, int len, i32 eb, i32 to
                     nb = off[s + 1];
                 }
             }
-            w |= (u32)s << (8 * b);
+            w |= (u32)(s - sbase) << (8 * b);
         }
         map[tid * (PER / 4) + k4] = w;
     }
@@ -284,6 +291,7 @@ struct ProbeMem {
     u32 *A_k4;   // where the 4-clique pass reads the bitset: A itself, or an LDS copy
                  // taken after the probes (over the then unused hash and slot arrays)
     u32 *seg;    // segment byte of each probe of a map block (NT*MP bytes), or null
+                 // (nb may be null too: then neighbours are read from the row again)
 };
 
 // Triangle records kept by Stage I for the tau pass: one u64 per triangle found at
@@ -329,7 +337,7 @@ __device__ __forceinline__ PMeta p_meta(const DevGraph &g, const TriCache &tc, i
     return m;
 }
 
-template <int NT, int MODE, int QP, int MP = 0>
+template <int NT, int MODE, int QP, int MP = 0, int MAXDU = (1 << 30)>
 __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, int tid, const ProbeMem &M, int hc,
                                            int pitch, i32 *__restrict__ t, i64 *__restrict__ K4,
                                            i64 *__restrict__ tau, i64 *red, i32 *red32, const TriCache &tc,
@@ -385,7 +393,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
     for (int i = tid; i < du; i += NT) {
         i32 v = g.ncol[base + i];
         const i32 b = g.nsplit[v];
-        M.nb[i] = v;
+        if (M.nb) M.nb[i] = v;
         M.beg[i] = b;
         M.off[i + 1] = g.nrp[v + 1] - b;
         u32 sl = hslot((u32)v, hmask);
@@ -444,6 +452,9 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
     // probes are located through a segment map built every MP/QP rounds.
     static_assert(MP % QP == 0, "map blocks hold whole rounds");
     i32 mbase = 0;
+    int sfirst = 0;
+    bool mapped = true;
+    constexpr bool FEW = MAXDU <= 256;  // every item's segments fit a byte
     for (i32 eb = 0; eb < total; eb += NT * QP) {
         const int nj = min(QP, (total - eb + NT - 1) / NT);
         int lo[QP];
@@ -451,14 +462,26 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
         if constexpr (MP > 0) {
             if (eb % (NT * MP) == 0) {
                 mbase = eb;
-                item_sync<NT>();  // the previous block's map has been read
-                q_segmap<NT, MP>(M.off, du, eb, total, tid, M.seg);
-                item_sync<NT>();
+                // a byte holds the segment relative to the block's first one; a
+                // block spanning 256 segments or more is searched instead
+                if (!FEW && du > 256) {
+                    sfirst = seg_search(M.off, du, eb);
+                    mapped = seg_search(M.off, du, min(eb + NT * MP, total) - 1) - sfirst < 256;
+                }
+                if (FEW || mapped) {
+                    item_sync<NT>();  // the previous block's map has been read
+                    q_segmap<NT, MP>(M.off, du, eb, total, tid, M.seg, FEW ? 0 : sfirst);
+                    item_sync<NT>();
+                }
             }
+            if (FEW || mapped) {
 #pragma unroll
-            for (int j = 0; j < QP; j++) {
-                const i32 e = eb + tid + j * NT;
-                lo[j] = (j < nj && e < total) ? seg_at(M.seg, e - mbase) : 0;
+                for (int j = 0; j < QP; j++) {
+                    const i32 e = eb + tid + j * NT;
+                    lo[j] = (j < nj && e < total) ? (FEW ? 0 : sfirst) + seg_at(M.seg, e - mbase) : 0;
+                }
+            } else {
+                q_locate<NT, QP>(M.off, du, eb + tid, nj, lo);
             }
         } else {
             q_locate<NT, QP>(M.off, du, eb + tid, nj, lo);
@@ -539,7 +562,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
                 }
             }
             // sj = 2 x (triangles of H_u through j) = 2 x (4-cliques containing u and nb[j])
-            if (sj) atomic_add_i64(&K4[M.nb[j]], sj >> 1);
+            if (sj) atomic_add_i64(&K4[M.nb ? M.nb[j] : g.ncol[base + j]], sj >> 1);
             s_local += sj;
         }
         i64 s = item_sum<NT>(s_local, red, tid);
@@ -557,7 +580,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
     } else {
         for (int j = tid; j < du; j += NT) {
             i64 a = M.acc[j];
-            if (a) atomic_add_i64(&tau[M.nb[j]], a);
+            if (a) atomic_add_i64(&tau[M.nb ? M.nb[j] : g.ncol[base + j]], a);
         }
         i64 s = item_sum<NT>(tau_local, red, tid);
         if (tid == 0 && s) atomic_add_i64(&tau[u], s);
@@ -577,6 +600,9 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
 #endif
 #ifndef PW_MP
 #define PW_MP 16  // probes per thread of a segment-map block, wave items (0: search)
+#endif
+#ifndef PB_MP
+#define PB_MP 4   // the same, workgroup items
 #endif
 template <int MODE>
 __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__restrict__ list,
@@ -609,7 +635,7 @@ __global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__res
         // the next item's row bounds and the one after's id load while this one runs
         const PMeta nxt = p_meta<MODE>(g, tc, un);
         un = it + 2 * waves < cnt ? list[it + 2 * waves] : -1;
-        probe_item<WAVE, MODE, PW_QP, PW_MP>(g, cur, tid, M, HC, PITCH, t, K4, tau, nullptr, nullptr, tc,
+        probe_item<WAVE, MODE, PW_QP, PW_MP, CAP>(g, cur, tid, M, HC, PITCH, t, K4, tau, nullptr, nullptr, tc,
                                              &s_st[w], counters);
         cur = nxt;
     }
@@ -673,10 +699,12 @@ __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__
     __shared__ i32 s_tcnt[CAP];
     __shared__ u32 s_A[CAP * PITCH];
     __shared__ i64 s_acc[CAP];
+    __shared__ u32 s_seg[PB_MP > 0 ? PB_NT * PB_MP / 4 : 1];
     __shared__ i64 s_red[PB_NT / WAVE];
     __shared__ i32 s_red32[PB_NT / WAVE];
     __shared__ ItemState s_st;
-    ProbeMem M{s_hkey, s_hpos, s_off, s_nb, s_beg, s_tcnt, s_A, s_acc, s_A};
+    // the triangle pass reads neighbours from the row again (its LDS is full)
+    ProbeMem M{s_hkey, s_hpos, s_off, MODE == PROBE_TRI ? nullptr : s_nb, s_beg, s_tcnt, s_A, s_acc, s_A, s_seg};
     if (threadIdx.x == 0) {
         s_st.chunk_cur = s_st.chunk_end = 0;
         s_st.full = 0;
@@ -689,8 +717,8 @@ __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__
     for (; it < cnt; it += gridDim.x) {
         const PMeta nxt = p_meta<MODE>(g, tc, un);
         un = it + 2 * (i32)gridDim.x < cnt ? list[it + 2 * gridDim.x] : -1;
-        probe_item<PB_NT, MODE, PB_QP>(g, cur, threadIdx.x, M, HC, PITCH, t, K4, tau, s_red, s_red32, tc, &s_st,
-                                   counters);
+        probe_item<PB_NT, MODE, PB_QP, PB_MP, CAP>(g, cur, threadIdx.x, M, HC, PITCH, t, K4, tau, s_red, s_red32,
+                                                   tc, &s_st, counters);
         cur = nxt;
     }
 }

@@ -82,6 +82,20 @@ def bipartite_matched(a):
                          f"bip_matched({a})")
 
 
+def hub_band(k, width, leaves):
+    """Vertex 0 joined to v_1..v_k; v_i joined to v_{i+1..i+width} and to `leaves`
+    leaves of its own.  Every v_i outranks vertex 0, so vertex 0's Stage I item has k
+    segments of about `width` probes each (short segments: with width 1 a block of
+    2048 probes covers more than 256 segments)."""
+    v = 1 + np.arange(k)
+    us, ws = [np.zeros(k, np.int64)], [v]
+    for d in range(1, width + 1):
+        us.append(v[:-d]); ws.append(v[d:])
+    lv = 1 + k + np.arange(k * leaves)
+    us.append(np.repeat(v, leaves)); ws.append(lv)
+    return gg.from_edges(1 + k + k * leaves, np.concatenate(us), np.concatenate(ws), f"hub_band({k},{width})")
+
+
 GRAPHS = {
     "K1": lambda: gg.complete(1),
     "K2": lambda: gg.complete(2),
@@ -89,6 +103,8 @@ GRAPHS = {
     "K30": lambda: gg.complete(30),
     "K90": lambda: gg.complete(90),
     "bip_hub": lambda: bipartite_matched(520),
+    "hub_band1": lambda: hub_band(300, 1, 301),
+    "hub_band20": lambda: hub_band(300, 20, 301),
     "star300": lambda: gg.star(300),
     "path50": lambda: gg.path(50),
     "cycle4": lambda: gg.cycle(4),
