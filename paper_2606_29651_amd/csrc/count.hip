@@ -269,6 +269,72 @@ __device__ __forceinline__ int seg_at(const u32 *map, i32 i) {
     return ((const unsigned char *)map)[i];
 }
 
+// Wave-wide inclusive maximum of non-negative values, all 64 lanes active.
+__device__ __forceinline__ int wave_incl_max(int v) {
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return v;
+}
+
+// The same byte map as q_segmap (sbase 0), built without a search per thread: every
+// nonempty segment starting in the block writes its index at its first element, and
+// a running maximum over the elements (within each thread's PER bytes, then across
+// the item's threads, from the segment of element eb on) fills in the rest.  The
+// indices of nonempty segments grow with their starts, so the maximum at e is the
+// segment holding e.  NT is a multiple of the wave; red32 holds NT/WAVE entries.
+template <int NT, int PER>
+__device__ __forceinline__ void seg_map_scan(const i32 *off, int len, i32 eb, i32 total, int tid, u32 *map,
+                                             i32 *red32) {
+    static_assert(PER % 4 == 0 && NT % WAVE == 0, "whole words per thread, whole waves");
+    constexpr int PW = PER / 4;
+    u32 *mine = map + tid * PW;
+#pragma unroll
+    for (int k = 0; k < PW; k++) mine[k] = 0u;
+    item_sync<NT>();
+    const i32 eend = min(eb + NT * PER, total);
+    for (int i = tid; i < len; i += NT) {
+        const i32 o = off[i];
+        if (o >= eb && o < eend && o < off[i + 1]) ((unsigned char *)map)[o - eb] = (unsigned char)i;
+    }
+    item_sync<NT>();
+    u32 w[PW];
+    int r = 0;
+#pragma unroll
+    for (int k = 0; k < PW; k++) {
+        const u32 v = mine[k];
+        u32 o = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            r = max(r, (int)((v >> (8 * b)) & 0xffu));
+            o |= (u32)r << (8 * b);
+        }
+        w[k] = o;
+    }
+    const int incl = wave_incl_max(r);
+    int c = __shfl_up(incl, 1, WAVE);
+    if (lane_id() == 0) c = 0;
+    if constexpr (NT > WAVE) {
+        const int wv = tid / WAVE;
+        if (lane_id() == WAVE - 1) red32[wv] = incl;
+        item_sync<NT>();
+        for (int k = 0; k < NT / WAVE; k++)
+            if (k < wv) c = max(c, red32[k]);
+    }
+    if (eb > 0) c = max(c, seg_search(off, len, eb));
+#pragma unroll
+    for (int k = 0; k < PW; k++) {
+        u32 o = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++) o |= (u32)max(c, (int)((w[k] >> (8 * b)) & 0xffu)) << (8 * b);
+        mine[k] = o;
+    }
+    item_sync<NT>();
+}
+
 enum { PROBE_TRI = 0, PROBE_TAU = 1 };
 
 #ifndef QS
@@ -1043,8 +1109,9 @@ struct QChunk {
     u32 *seg;    // segment byte of each wedge of a step (NT * max(QK, QS) bytes), or null
 };
 
-// Which 4-cycle kernels locate wedges through a segment map (the map costs LDS, and
-// so occupancy, that the smaller kernels cannot spare).
+// How each 4-cycle kernel locates wedges (0 search, 1 q_segmap, 2 seg_map_scan): a
+// map costs LDS, and so occupancy, that some kernels cannot spare; the wave kernel
+// makes room for its map by crediting middles straight to Q.
 #ifndef QMAP_QLW
 #define QMAP_QLW 0
 #endif
@@ -1052,13 +1119,20 @@ struct QChunk {
 #define QMAP_QLB 0
 #endif
 #ifndef QMAP_QHW
-#define QMAP_QHW 0
+#define QMAP_QHW 2
 #endif
 #ifndef QMAP_QHB
 #define QMAP_QHB 0
 #endif
 #ifndef QMAP_QD
-#define QMAP_QD 1
+#define QMAP_QD 2
+#endif
+// Which ones credit middles straight to Q (and so keep no per-segment sums in LDS).
+#ifndef QGMID_QHW
+#define QGMID_QHW 1
+#endif
+#ifndef QGMID_QHB
+#define QGMID_QHB 0
 #endif
 
 
@@ -1072,7 +1146,7 @@ __device__ __forceinline__ i32 q_load_chunk(const DevGraph &g, i32 x, i32 s0, i3
         C.vv[i] = v;
         C.beg[i] = b;
         C.off[i + 1] = e - b;
-        C.mid[i] = 0;
+        if (C.mid) C.mid[i] = 0;
     }
     item_sync<NT>();
     item_scan<NT>(C.off, len, tid, red32);
@@ -1157,7 +1231,10 @@ __device__ __forceinline__ QMeta q_meta(const DevGraph &g, i32 x) {
 // created a key's counter then credits C(c, 2) through cr, adds it to *local and
 // empties the counter, and the call returns true.  Otherwise (false) the counters
 // are left for the caller to harvest.
-template <int NT, int MODE, int QK = 0, bool MAP = false, typename Ctr, typename Credit>
+// MAP: how wedges find their segments -- 0 a search each, 1 q_segmap, 2 seg_map_scan.
+// GMID: middles' credits go straight to Q (runs of lanes in one segment add once)
+// rather than through C.mid.
+template <int NT, int MODE, int QK = 0, int MAP = 0, bool GMID = false, typename Ctr, typename Credit>
 __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, const Ctr &ctr, const QChunk &C, int dc,
                                          int tid, i32 *red32, i64 *__restrict__ Q, const Credit &cr, i64 *local) {
     const i32 x = mt.x, s0 = mt.s0, sp = mt.sp;
@@ -1170,9 +1247,13 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                 const int nj = (total + NT - 1) / NT;
                 int lo[QK];
                 i32 key[QK];
-                if constexpr (MAP) {
-                    q_segmap<NT, QK>(C.off, ns, 0, total, tid, C.seg);
-                    item_sync<NT>();
+                if constexpr (MAP > 0) {
+                    if constexpr (MAP == 1) {
+                        q_segmap<NT, QK>(C.off, ns, 0, total, tid, C.seg);
+                        item_sync<NT>();
+                    } else {
+                        seg_map_scan<NT, QK>(C.off, ns, 0, total, tid, C.seg, red32);
+                    }
 #pragma unroll
                     for (int j = 0; j < QK; j++) {
                         const i32 e = tid + j * NT;
@@ -1198,7 +1279,8 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                 for (int j = 0; j < QK; j++) {
                     if (j < nj) {
                         const i32 c = key[j] >= 0 ? ctr.get(key[j]) : 0;
-                        wave_run_add(C.mid, lo[j], c > 1 ? c - 1 : 0);
+                        if constexpr (GMID) wave_run_add(Q, C.vv[lo[j]], c > 1 ? c - 1 : 0);
+                        else wave_run_add(C.mid, lo[j], c > 1 ? c - 1 : 0);
                     }
                 }
                 item_sync<NT>();
@@ -1215,9 +1297,11 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                     }
                 }
                 *local += acc;
-                for (int i = tid; i < ns; i += NT) {
-                    i64 m = C.mid[i];
-                    if (m) atomic_add_i64(&Q[C.vv[i]], m);
+                if constexpr (!GMID) {
+                    for (int i = tid; i < ns; i += NT) {
+                        i64 m = C.mid[i];
+                        if (m) atomic_add_i64(&Q[C.vv[i]], m);
+                    }
                 }
                 item_sync<NT>();
                 return true;
@@ -1238,10 +1322,14 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                 int si[QS];
                 i32 key[QS];
                 bool ok[QS];
-                if constexpr (MAP) {
+                if constexpr (MAP > 0) {
                     item_sync<NT>();  // the previous step's map has been read
-                    q_segmap<NT, QS>(C.off, len, eb, total, tid, C.seg);
-                    item_sync<NT>();
+                    if constexpr (MAP == 1) {
+                        q_segmap<NT, QS>(C.off, len, eb, total, tid, C.seg);
+                        item_sync<NT>();
+                    } else {
+                        seg_map_scan<NT, QS>(C.off, len, eb, total, tid, C.seg, red32);
+                    }
 #pragma unroll
                     for (int u = 0; u < QS; u++) {
                         const i32 e = eb + tid + u * NT;
@@ -1265,12 +1353,13 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                         if (ok[u]) ctr.inc(key[u]);
                     } else {
                         const i32 c = ok[u] ? ctr.get(key[u]) : 0;
-                        wave_run_add(C.mid, si[u], c > 1 ? c - 1 : 0);
+                        if constexpr (GMID) wave_run_add(Q, C.vv[si[u]], c > 1 ? c - 1 : 0);
+                        else wave_run_add(C.mid, si[u], c > 1 ? c - 1 : 0);
                     }
                 }
             }
             item_sync<NT>();
-            if (pass == 1) {
+            if (pass == 1 && !GMID) {
                 for (int i = tid; i < len; i += NT) {
                     i64 m = C.mid[i];
                     if (m) atomic_add_i64(&Q[C.vv[i]], m);
@@ -1369,7 +1458,8 @@ __global__ void __launch_bounds__(256) k_q_wave(DevGraph g, const i32 *__restric
         const int hc = need >= hcw ? hcw : (need <= 64 ? 64 : (int)(1u << (32 - __clz((u32)(need - 1)))));
         LightHash H{s_key, s_cnt, (u32)hc - 1};
         i64 local = 0;
-        const bool taken = q_sweeps<WAVE, MODE, QLW_QK, QMAP_QLW>(g, cur, H, C, QLW_DC, tid, nullptr, Q, CreditLight{Q}, &local);
+        const bool taken =
+            q_sweeps<WAVE, MODE, QLW_QK, QMAP_QLW>(g, cur, H, C, QLW_DC, tid, nullptr, Q, CreditLight{Q}, &local);
         for (int j = tid; !taken && j < hc; j += WAVE) {
             const i32 k = s_key[j];
             if (k >= 0) {
@@ -1514,7 +1604,7 @@ struct PackedHash {
     }
 };
 
-template <int NT, int QK, bool MAP>
+template <int NT, int QK, int MAP, bool GMID>
 __device__ __forceinline__ void qh_item_packed(const DevGraph &g, const QMeta &mt, const PackedHash &H0, int hc_max,
                                                const QChunk &C, int dc, int tid, i64 *red, i32 *red32,
                                                i64 *__restrict__ Q, i64 *__restrict__ prow) {
@@ -1526,7 +1616,7 @@ __device__ __forceinline__ void qh_item_packed(const DevGraph &g, const QMeta &m
     PackedHash H{H0.tab, (u32)hc - 1, H0.h0};
     i64 local = 0;
     const bool taken =
-        q_sweeps<NT, Q_HEAVY, QK, MAP>(g, mt, H, C, dc, tid, red32, Q, CreditHeavy{prow, H0.h0}, &local);
+        q_sweeps<NT, Q_HEAVY, QK, MAP, GMID>(g, mt, H, C, dc, tid, red32, Q, CreditHeavy{prow, H0.h0}, &local);
     for (int j = tid; !taken && j < hc; j += NT) {
         u32 cur = H.tab[j];
         if (cur != PK_EMPTY) {
@@ -1551,8 +1641,9 @@ __device__ __forceinline__ void qh_item_packed(const DevGraph &g, const QMeta &m
 #define QHW_QK 16
 #endif
 #define QHW_SEGB (QMAP_QHW ? WAVE * (QHW_QK > QS ? QHW_QK : QS) : 0)
+#define QHW_MIDB (QGMID_QHW ? 0 : 8 * QHW_DC)
 __host__ __device__ constexpr int qhw_wave_bytes(int hcw) {
-    return ((8 * QHW_DC + QHW_SEGB + 4 * hcw + 4 * (3 * QHW_DC + 1)) + 15) / 16 * 16;
+    return ((QHW_MIDB + QHW_SEGB + 4 * hcw + 4 * (3 * QHW_DC + 1)) + 15) / 16 * 16;
 }
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QMAP_QHW ? 4 : 1))) k_qh_wave(DevGraph g, const i32 *__restrict__ list,
                                                  const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 K,
@@ -1560,9 +1651,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QMAP_Q
     extern __shared__ __align__(16) char s_dyn[];
     const int w = threadIdx.x / WAVE, tid = lane_id();
     char *base = s_dyn + (size_t)w * qhw_wave_bytes(hcw);
-    i64 *s_mid = (i64 *)base;
-    u32 *s_seg = (u32 *)(base + 8 * QHW_DC);
-    u32 *s_tab = (u32 *)(base + 8 * QHW_DC + QHW_SEGB);
+    i64 *s_mid = QGMID_QHW ? nullptr : (i64 *)base;
+    u32 *s_seg = (u32 *)(base + QHW_MIDB);
+    u32 *s_tab = (u32 *)(base + QHW_MIDB + QHW_SEGB);
     i32 *s_off = (i32 *)(s_tab + hcw);
     i32 *s_vv = s_off + QHW_DC + 1;
     i32 *s_beg = s_vv + QHW_DC;
@@ -1579,7 +1670,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QMAP_Q
     for (; it < cnt; it += waves) {
         const QMeta nxt = q_meta<Q_HEAVY>(g, xn);
         xn = it + 2 * waves < cnt ? list[it + 2 * waves] : -1;
-        qh_item_packed<WAVE, QHW_QK, QMAP_QHW>(g, cur, H, hcw, C, QHW_DC, tid, nullptr, nullptr, Q, prow);
+        qh_item_packed<WAVE, QHW_QK, QMAP_QHW, QGMID_QHW>(g, cur, H, hcw, C, QHW_DC, tid, nullptr, nullptr, Q, prow);
         cur = nxt;
     }
 }
@@ -1596,13 +1687,13 @@ __global__ void __launch_bounds__(QHB_NT) k_qh_block(DevGraph g, const i32 *__re
     __shared__ i32 s_off[QHB_DC + 1];
     __shared__ i32 s_vv[QHB_DC];
     __shared__ i32 s_beg[QHB_DC];
-    __shared__ i64 s_mid[QHB_DC];
+    __shared__ i64 s_mid[QGMID_QHB ? 1 : QHB_DC];
     __shared__ i64 s_red[QHB_NT / WAVE];
     __shared__ i32 s_red32[QHB_NT / WAVE];
     for (int i = threadIdx.x; i < QHB_HC; i += QHB_NT) s_tab[i] = PK_EMPTY;
     __syncthreads();
     PackedHash H{s_tab, QHB_HC - 1, g.h0};
-    QChunk C{s_off, s_vv, s_beg, s_mid, s_seg};
+    QChunk C{s_off, s_vv, s_beg, QGMID_QHB ? nullptr : s_mid, s_seg};
     i64 *prow = part + (i64)(blockIdx.x % QH_PART_ROWS) * K;
     const i32 cnt = st->cnt[WC_QH_BLOCK];
     i32 it = blockIdx.x;
@@ -1611,7 +1702,7 @@ __global__ void __launch_bounds__(QHB_NT) k_qh_block(DevGraph g, const i32 *__re
     for (; it < cnt; it += gridDim.x) {
         const QMeta nxt = q_meta<Q_HEAVY>(g, xn);
         xn = it + 2 * (i32)gridDim.x < cnt ? list[it + 2 * gridDim.x] : -1;
-        qh_item_packed<QHB_NT, QHB_HC / 2 / QHB_NT, QMAP_QHB>(g, cur, H, QHB_HC, C, QHB_DC, threadIdx.x, s_red,
+        qh_item_packed<QHB_NT, QHB_HC / 2 / QHB_NT, QMAP_QHB, QGMID_QHB>(g, cur, H, QHB_HC, C, QHB_DC, threadIdx.x, s_red,
                                                               s_red32, Q, prow);
         cur = nxt;
     }
