@@ -1161,16 +1161,19 @@ __device__ __forceinline__ i32 q_load_chunk(const DevGraph &g, i32 x, i32 s0, i3
 struct DenseCounter {
     u32 *w;   // K/2 words
     i32 h0;
-    // returns the counter index when this call took it from 0 (its owner), else -1
-    __device__ int inc(i32 k) const {
-        i32 i = k - h0;
+    // counts k; returns its counter's index, own set when this call took it from 0
+    __device__ int inc_at(i32 k, bool &own) const {
+        const i32 i = k - h0;
         const u32 old = atomicAdd(&w[i >> 1], 1u << ((i & 1) << 4));
-        return ((old >> ((i & 1) << 4)) & 0xffffu) == 0 ? i : -1;
+        own = ((old >> ((i & 1) << 4)) & 0xffffu) == 0;
+        return i;
     }
-    __device__ i32 get(i32 k) const {
-        i32 i = k - h0;
-        return (i32)((w[i >> 1] >> ((i & 1) << 4)) & 0xffffu);
+    __device__ void inc(i32 k) const {
+        bool own;
+        inc_at(k, own);
     }
+    __device__ i32 at(int i) const { return (i32)((w[i >> 1] >> ((i & 1) << 4)) & 0xffffu); }
+    __device__ i32 get(i32 k) const { return at(k - h0); }
     // count of an owned counter, which is returned to zero (the word's other half may
     // be taken at the same time)
     __device__ i32 take(int i) const {
@@ -1184,9 +1187,8 @@ struct GlobalCounter {
     i32 *c;       // [n] zero between items
     i32 *used;    // list of touched keys
     i32 *nused;   // LDS counter
-    __device__ int inc(i32 k) const {
+    __device__ void inc(i32 k) const {
         if (atomicAdd(&c[k], 1) == 0) used[atomicAdd(nused, 1)] = k;
-        return -1;
     }
     __device__ i32 get(i32 k) const { return c[k]; }
 };
@@ -1269,16 +1271,23 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                 }
 #pragma unroll
                 for (int j = 0; j < QK; j++) key[j] = key[j] >= 0 ? g.ncol[key[j]] : -1;
-                int own[QK];
+                // where each key's count lives, so that the second sweep reads it
+                // without a lookup; bit j of ownm: this thread created key j's count
+                int loc[QK];
+                u32 ownm = 0;
 #pragma unroll
-                for (int j = 0; j < QK; j++) own[j] = key[j] >= 0 ? ctr.inc(key[j]) : -1;
+                for (int j = 0; j < QK; j++) {
+                    bool o = false;
+                    loc[j] = key[j] >= 0 ? ctr.inc_at(key[j], o) : -1;
+                    ownm |= (u32)o << j;
+                }
                 item_sync<NT>();
                 // second sweep: each wedge's middle gains c - 1, summed over runs of
                 // lanes in the same segment before the LDS atomic
 #pragma unroll
                 for (int j = 0; j < QK; j++) {
                     if (j < nj) {
-                        const i32 c = key[j] >= 0 ? ctr.get(key[j]) : 0;
+                        const i32 c = loc[j] >= 0 ? ctr.at(loc[j]) : 0;
                         if constexpr (GMID) wave_run_add(Q, C.vv[lo[j]], c > 1 ? c - 1 : 0);
                         else wave_run_add(C.mid, lo[j], c > 1 ? c - 1 : 0);
                     }
@@ -1287,8 +1296,8 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                 i64 acc = 0;
 #pragma unroll
                 for (int j = 0; j < QK; j++) {
-                    if (own[j] >= 0) {
-                        const i64 c = ctr.take(own[j]);
+                    if ((ownm >> j) & 1u) {
+                        const i64 c = ctr.take(loc[j]);
                         if (c >= 2) {
                             const i64 cc = c * (c - 1) / 2;
                             cr(key[j], cc);
@@ -1379,17 +1388,17 @@ struct LightHash {
     i32 *key;
     i32 *cnt;
     u32 mask;
-    // returns the slot when this call inserted the key (its owner), else -1
-    __device__ int inc(i32 k) const {
+    // counts k; returns its slot, own set when this call inserted the key
+    __device__ int inc_at(i32 k, bool &own) const {
         u32 sl = hslot((u32)k, mask);
-        int own = -1;
+        own = false;
         while (true) {
             i32 cur = key[sl];
             if (cur == k) break;
             if (cur == -1) {
                 i32 prev = atomicCAS(&key[sl], -1, k);
                 if (prev == -1) {
-                    own = (int)sl;
+                    own = true;
                     break;
                 }
                 if (prev == k) break;
@@ -1397,8 +1406,13 @@ struct LightHash {
             sl = (sl + 1) & mask;
         }
         atomicAdd(&cnt[sl], 1);
-        return own;
+        return (int)sl;
     }
+    __device__ void inc(i32 k) const {
+        bool own;
+        inc_at(k, own);
+    }
+    __device__ i32 at(int sl) const { return cnt[sl]; }
     // count of an owned slot, which is emptied
     __device__ i32 take(int sl) const {
         const i32 c = cnt[sl];
@@ -1568,24 +1582,33 @@ struct PackedHash {
     u32 *tab;
     u32 mask;
     i32 h0;
-    // returns the slot when this call inserted the key (its owner), else -1
-    __device__ int inc(i32 k) const {
+    // counts k; returns its slot, own set when this call inserted the key
+    __device__ int inc_at(i32 k, bool &own) const {
         const u32 idx = (u32)(k - h0);
         u32 sl = hslot(idx, mask);
+        own = false;
         while (true) {
             u32 cur = tab[sl];
             if (cur == PK_EMPTY) {
                 u32 prev = atomicCAS(&tab[sl], PK_EMPTY, (idx << PK_SHIFT) | 1u);
-                if (prev == PK_EMPTY) return (int)sl;
+                if (prev == PK_EMPTY) {
+                    own = true;
+                    return (int)sl;
+                }
                 cur = prev;
             }
             if ((cur >> PK_SHIFT) == idx) {
                 atomicAdd(&tab[sl], 1u);
-                return -1;
+                return (int)sl;
             }
             sl = (sl + 1) & mask;
         }
     }
+    __device__ void inc(i32 k) const {
+        bool own;
+        inc_at(k, own);
+    }
+    __device__ i32 at(int sl) const { return (i32)(tab[sl] & PK_CMASK); }
     // count of an owned slot, which is emptied
     __device__ i32 take(int sl) const {
         const u32 cur = tab[sl];
