@@ -358,6 +358,8 @@ struct ProbeMem {
                  // taken after the probes (over the then unused hash and slot arrays)
     u32 *seg;    // segment byte of each probe of a map block (NT*MP bytes), or null
                  // (nb may be null too: then neighbours are read from the row again)
+    i32 *k4s;    // [cap] per-slot sums of the 4-clique pass over triangle records, or
+                 // null for the scan over bitset rows
 };
 
 // Triangle records kept by Stage I for the tau pass: one u64 per triangle found at
@@ -615,21 +617,49 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
             for (int i = tid; i < du * pitch; i += NT) M.A_k4[i] = M.A[i];
             item_sync<NT>();
         }
-        for (int j = tid; j < du; j += NT) {
-            i64 sj = 0;
-            for (int wd = 0; wd < nw; wd++) {
-                u32 bits = A[j * pitch + wd];
-                while (bits) {
-                    int b = __ffs(bits) - 1;
-                    bits &= bits - 1;
-                    int i = wd * 32 + b;
-                    words_scanned += nw;
-                    for (int k = 0; k < nw; k++) sj += __popc(A[i * pitch + k] & A[j * pitch + k]);
+        if (M.k4s && keep) {
+            // every edge (i, p) of H_u once, from this item's triangle records: the
+            // common neighbours of i and p in H_u close triangles of H_u through both,
+            // summed per slot in k4s (which may share the spent tcnt)
+            i32 *sk = M.k4s;
+            item_sync<NT>();
+            for (int j = tid; j < du; j += NT) sk[j] = 0;
+            item_sync<NT>();
+            const i64 r1 = item_base + S->item_cnt;
+            for (i64 r = item_base + tid; r < r1; r += NT) {
+                const u64 rec = tc.rec[r];
+                const int i = (int)(rec & 0xffffu), p = (int)((rec >> 16) & 0xffffu);
+                i32 c = 0;
+                for (int k = 0; k < nw; k++) c += __popc(A[i * pitch + k] & A[p * pitch + k]);
+                words_scanned += nw;
+                if (c) {
+                    atomicAdd(&sk[i], c);
+                    atomicAdd(&sk[p], c);
                 }
             }
-            // sj = 2 x (triangles of H_u through j) = 2 x (4-cliques containing u and nb[j])
-            if (sj) atomic_add_i64(&K4[M.nb ? M.nb[j] : g.ncol[base + j]], sj >> 1);
-            s_local += sj;
+            item_sync<NT>();
+            for (int j = tid; j < du; j += NT) {
+                const i64 sj = sk[j];
+                if (sj) atomic_add_i64(&K4[M.nb ? M.nb[j] : g.ncol[base + j]], sj >> 1);
+                s_local += sj;
+            }
+        } else {
+            for (int j = tid; j < du; j += NT) {
+                i64 sj = 0;
+                for (int wd = 0; wd < nw; wd++) {
+                    u32 bits = A[j * pitch + wd];
+                    while (bits) {
+                        int b = __ffs(bits) - 1;
+                        bits &= bits - 1;
+                        int i = wd * 32 + b;
+                        words_scanned += nw;
+                        for (int k = 0; k < nw; k++) sj += __popc(A[i * pitch + k] & A[j * pitch + k]);
+                    }
+                }
+                // sj = 2 x (triangles of H_u through j) = 2 x (4-cliques containing u and nb[j])
+                if (sj) atomic_add_i64(&K4[M.nb ? M.nb[j] : g.ncol[base + j]], sj >> 1);
+                s_local += sj;
+            }
         }
         i64 s = item_sum<NT>(s_local, red, tid);
         if (tid == 0 && s) atomic_add_i64(&K4[u], s / 6);
@@ -770,7 +800,8 @@ __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__
     __shared__ i32 s_red32[PB_NT / WAVE];
     __shared__ ItemState s_st;
     // the triangle pass reads neighbours from the row again (its LDS is full)
-    ProbeMem M{s_hkey, s_hpos, s_off, MODE == PROBE_TRI ? nullptr : s_nb, s_beg, s_tcnt, s_A, s_acc, s_A, s_seg};
+    ProbeMem M{s_hkey, s_hpos, s_off, MODE == PROBE_TRI ? nullptr : s_nb, s_beg, s_tcnt, s_A, s_acc, s_A, s_seg,
+               s_tcnt};
     if (threadIdx.x == 0) {
         s_st.chunk_cur = s_st.chunk_end = 0;
         s_st.full = 0;
@@ -888,7 +919,7 @@ __host__ __device__ inline i64 probe_large_lds_bytes(int cap, int hc) {
 __host__ __device__ inline i64 probe_large_k4_bytes(int cap, int hc) {
     const i64 words = bit_pitch(cap);
     const i64 probe = (i64)sizeof(i32) * (2 * (i64)hc + 3 * (i64)cap + 1);
-    const i64 k4 = (i64)sizeof(u32) * cap * words;
+    const i64 k4 = (i64)sizeof(u32) * cap * words + (i64)sizeof(i32) * cap;  // bitset copy, per-slot sums
     return (i64)sizeof(i32) * cap + (probe > k4 ? probe : k4);
 }
 
@@ -903,6 +934,7 @@ __global__ void __launch_bounds__(PL_NT) k_probe_large(DevGraph g, const i32 *__
     const int words = bit_pitch(cap);
     char *p = scratch + (i64)blockIdx.x * slice_bytes;
     ProbeMem M;
+    M.seg = nullptr;
     M.acc = (i64 *)p; p += sizeof(i64) * cap;
     M.A = (u32 *)p; p += sizeof(u32) * (i64)cap * words;
     M.A_k4 = M.A;
@@ -910,6 +942,8 @@ __global__ void __launch_bounds__(PL_NT) k_probe_large(DevGraph g, const i32 *__
         M.nb = (i32 *)s_dyn;
         char *q = s_dyn + sizeof(i32) * cap;
         M.A_k4 = (u32 *)q;
+        // the 4-clique sums follow the bitset copy
+        M.k4s = (i32 *)(q + sizeof(u32) * (i64)cap * words);
         M.hkey = (i32 *)q; q += sizeof(i32) * hc;
         M.hpos = (i32 *)q; q += sizeof(i32) * hc;
         M.off = (i32 *)q; q += sizeof(i32) * (cap + 1);
@@ -923,6 +957,7 @@ __global__ void __launch_bounds__(PL_NT) k_probe_large(DevGraph g, const i32 *__
         M.nb = (i32 *)q; q += sizeof(i32) * cap;
         M.beg = (i32 *)q; q += sizeof(i32) * cap;
         M.tcnt = (i32 *)q;
+        M.k4s = M.tcnt;
     }
     __shared__ ItemState s_st;
     if (threadIdx.x == 0) {
