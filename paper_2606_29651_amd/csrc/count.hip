@@ -103,8 +103,10 @@ __device__ __forceinline__ VertexClasses classify_vertex(const DevGraph &g, cons
     const i32 du = e - sp, d = e - b, dm = sp - b;
     const i64 wl = wlight[y], wh = wheavy[y];
     // Stage I/II items: capacity decides first (|N+| sizes the LDS structures); items
-    // that fit a wave may move to one lane or to a whole workgroup by predicted work
-    if (du >= 2) {
+    // that fit a wave may move to one lane or to a whole workgroup by predicted work.
+    // An item whose neighbours above it have no neighbours above them closes no
+    // triangle and is left out.
+    if (du >= 2 && probes[y] > 0) {
         int tc;
         if (du > th.tri_block) tc = WC_TRI_LARGE;
         else if (du > th.tri_wave) tc = WC_TRI_BLOCK;
@@ -412,6 +414,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
                                            ItemState *S, i64 *__restrict__ counters) {
     const i64 t_start = (counters && MODE == PROBE_TRI) ? (i64)clock64() : 0;
     const i32 u = pm.u, base = pm.base, du = pm.du;
+    if (MODE == PROBE_TAU && pm.tcnt == 0) return;  // no triangle at u: nothing to add
     if (MODE == PROBE_TAU && pm.tcnt >= 0) {
         // cached triangles: tau from the records and the final t values
         for (int i = tid; i < du; i += NT) {
