@@ -569,7 +569,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     STAGE_MARK(7);
     if (n - h0 > 0) HIP_TRY(fill32(qpart, (i64)sizeof(i64) * L.part_rows * (n - h0), 0u, s));
     HIP_TRY(launch_q(g, lh, dst, acc.Q, gscratch, L.gslice, L.gblocks, cu * 4, cu * 4, cu * 2, qpart, L.part_rows,
-                     th.ql_wave, th.ql_block, th.ql_split, th.qh_wave, kev, s));
+                     th.ql_wave, th.ql_block, th.ql_split, th.qh_wave, th.qh_block, kev, s));
     STAGE_MARK(8);
     // ---- Stage III-b: equations ----
     HIP_TRY(launch_solve(g, acc, o.psi, o.fvars, dst, cu * 8, s));

@@ -88,12 +88,18 @@ __device__ __forceinline__ void atomic_add_i64(i64 *p, i64 v) {
     atomicAdd(reinterpret_cast<unsigned long long *>(p), static_cast<unsigned long long>(v));
 }
 
-// Multiplicative hash into a power-of-two table.  The 24-bit multiply is a
-// full-rate instruction (a 32-bit multiply is quarter rate); folding the high bits in
-// first keeps all 32 key bits in play.
+// Multiplicative hash into a power-of-two table (at most 2^15 entries), which
+// scatters runs of consecutive keys (linear probing would turn them into long
+// occupied runs).  The slot comes from bits 16..30 of a 24-bit product: the
+// compiler then keeps the full-rate 24-bit multiply (it narrows a product whose low
+// bits alone are used to a quarter-rate 32-bit one).
 __device__ __forceinline__ u32 hslot(u32 key, u32 mask) {
-    return (__umul24(key ^ (key >> 15), 0x9E3779u) >> 7) & mask;
+    return (__umul24(key ^ (key >> 15), 0x9E3779u) >> 16) & mask;
 }
+
+// A value every lane of the wave holds alike, moved to a scalar register so that
+// branches on it are scalar.
+__device__ __forceinline__ i32 wave_uniform(i32 v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Largest i in [lo, hi) with off[i] <= e, for a non-decreasing array off (lo valid).
 template <typename T>

@@ -202,11 +202,12 @@ __global__ void __launch_bounds__(CL_NT) k_classify(DevGraph g, const i64 *__res
 // ---------------------------------------------------------------------------
 // Stage I / Stage II / tau probe kernels.
 // ---------------------------------------------------------------------------
-// Largest i in [0, len) with off[i] <= e, for the QK elements e = e0 + j*NT (j < nj)
-// of one thread, searched together (power-of-two steps, independent LDS reads in
-// flight).  off is non-decreasing with off[0] = 0 <= e.
+// Largest i in [0, len) with off[i] <= e, for the QK elements e = min(e0 + j*NT, emax)
+// (j < nj) of one thread, searched together (power-of-two steps, independent LDS
+// reads in flight).  off is non-decreasing with off[0] = 0 <= e; with emax below
+// off[len], segment lo[j] holds e.
 template <int NT, int QK>
-__device__ __forceinline__ void q_locate(const i32 *off, int len, i32 e0, int nj, int *lo) {
+__device__ __forceinline__ void q_locate(const i32 *off, int len, i32 e0, int nj, int *lo, i32 emax) {
 #pragma unroll
     for (int j = 0; j < QK; j++) lo[j] = 0;
     int step = 1;
@@ -215,7 +216,7 @@ __device__ __forceinline__ void q_locate(const i32 *off, int len, i32 e0, int nj
 #pragma unroll
         for (int j = 0; j < QK; j++) {
             if (j < nj) {
-                const i32 e = e0 + j * NT;
+                const i32 e = min(e0 + j * NT, emax);
                 const int m = lo[j] + step;
                 if (m < len && off[m] <= e) lo[j] = m;
             }
@@ -552,10 +553,10 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
                     lo[j] = (j < nj && e < total) ? (FEW ? 0 : sfirst) + seg_at(M.seg, e - mbase) : 0;
                 }
             } else {
-                q_locate<NT, QP>(M.off, du, eb + tid, nj, lo);
+                q_locate<NT, QP>(M.off, du, eb + tid, nj, lo, total - 1);
             }
         } else {
-            q_locate<NT, QP>(M.off, du, eb + tid, nj, lo);
+            q_locate<NT, QP>(M.off, du, eb + tid, nj, lo, total - 1);
         }
 #pragma unroll
         for (int j = 0; j < QP; j++) {
@@ -1282,7 +1283,7 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
     const bool single = ns <= dc;
     if constexpr (QK > 0) {
         if (single) {
-            const i32 total = q_load_chunk<NT, MODE>(g, x, s0, sp, 0, ns, C, tid, red32);
+            const i32 total = wave_uniform(q_load_chunk<NT, MODE>(g, x, s0, sp, 0, ns, C, tid, red32));
             if (total <= NT * QK) {
                 const int nj = (total + NT - 1) / NT;
                 int lo[QK];
@@ -1295,20 +1296,22 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                         seg_map_scan<NT, QK>(C.off, ns, 0, total, tid, C.seg, red32);
                     }
 #pragma unroll
-                    for (int j = 0; j < QK; j++) {
-                        const i32 e = tid + j * NT;
-                        lo[j] = (j < nj && e < total) ? seg_at(C.seg, e) : 0;
-                    }
+                    for (int j = 0; j < QK; j++) lo[j] = j < nj ? seg_at(C.seg, min(tid + j * NT, total - 1)) : 0;
                 } else {
-                    q_locate<NT, QK>(C.off, ns, tid, nj, lo);
+                    q_locate<NT, QK>(C.off, ns, tid, nj, lo, total - 1);
                 }
+                // lanes past the end repeat the last wedge's reads (in bounds, results
+                // unused), so that the loads need no per-lane branch
 #pragma unroll
                 for (int j = 0; j < QK; j++) {
-                    const i32 e = tid + j * NT;
-                    key[j] = (j < nj && e < total) ? C.beg[lo[j]] + (e - C.off[lo[j]]) : -1;
+                    const i32 e = min(tid + j * NT, total - 1);
+                    key[j] = j < nj ? C.beg[lo[j]] + (e - C.off[lo[j]]) : 0;
                 }
 #pragma unroll
-                for (int j = 0; j < QK; j++) key[j] = key[j] >= 0 ? g.ncol[key[j]] : -1;
+                for (int j = 0; j < QK; j++) key[j] = j < nj ? g.ncol[key[j]] : -1;
+#pragma unroll
+                for (int j = 0; j < QK; j++)
+                    if (tid + j * NT >= total) key[j] = -1;
                 // where each key's count lives, so that the second sweep reads it
                 // without a lookup; bit j of ownm: this thread created key j's count
                 int loc[QK];
@@ -1364,6 +1367,7 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
             } else {
                 total = C.off[len];
             }
+            total = wave_uniform(total);
             for (i32 eb = 0; eb < total; eb += NT * QS) {
                 const int nj = min(QS, (total - eb + NT - 1) / NT);
                 int si[QS];
@@ -1378,21 +1382,19 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                         seg_map_scan<NT, QS>(C.off, len, eb, total, tid, C.seg, red32);
                     }
 #pragma unroll
-                    for (int u = 0; u < QS; u++) {
-                        const i32 e = eb + tid + u * NT;
-                        si[u] = (u < nj && e < total) ? seg_at(C.seg, e - eb) : 0;
-                    }
+                    for (int u = 0; u < QS; u++)
+                        si[u] = u < nj ? seg_at(C.seg, min(eb + tid + u * NT, total - 1) - eb) : 0;
                 } else {
-                    q_locate<NT, QS>(C.off, len, eb + tid, nj, si);
+                    q_locate<NT, QS>(C.off, len, eb + tid, nj, si, total - 1);
                 }
 #pragma unroll
                 for (int u = 0; u < QS; u++) {
-                    i32 e = eb + tid + u * NT;
-                    ok[u] = u < nj && e < total;
-                    key[u] = ok[u] ? C.beg[si[u]] + (e - C.off[si[u]]) : 0;
+                    const i32 e = min(eb + tid + u * NT, total - 1);
+                    ok[u] = u < nj && eb + tid + u * NT < total;
+                    key[u] = u < nj ? C.beg[si[u]] + (e - C.off[si[u]]) : 0;
                 }
 #pragma unroll
-                for (int u = 0; u < QS; u++) key[u] = ok[u] ? g.ncol[key[u]] : 0;
+                for (int u = 0; u < QS; u++) key[u] = u < nj ? g.ncol[key[u]] : 0;
 #pragma unroll
                 for (int u = 0; u < QS; u++) {
                     if (u >= nj) continue;
@@ -1736,14 +1738,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QMAP_Q
     }
 }
 
-#define QHB_HC 8192
+#define QHB_HC QH_BLOCK_HC
 #define QHB_DC 256
 #ifndef QHB_NT
 #define QHB_NT 256
 #endif
-__global__ void __launch_bounds__(QHB_NT) k_qh_block(DevGraph g, const i32 *__restrict__ list,
-                                                     const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 K) {
-    __shared__ u32 s_tab[QHB_HC];
+#ifndef QHB_WPE
+#define QHB_WPE 1
+#endif
+#ifndef QHB_GRID
+#define QHB_GRID 4  // workgroups per CU (the class's grid is given per 4)
+#endif
+// The table (hcb entries, a power of two at least twice the class's wedge bound)
+// comes with the launch in dynamic LDS.
+__global__ void __launch_bounds__(QHB_NT) __attribute__((amdgpu_waves_per_eu(QHB_WPE)))
+k_qh_block(DevGraph g, const i32 *__restrict__ list, const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 K,
+           int hcb) {
+    extern __shared__ __align__(16) char s_dyn[];
+    u32 *s_tab = (u32 *)s_dyn;
     __shared__ u32 s_seg[QMAP_QHB ? QHB_NT * (QHB_HC / 2 / QHB_NT > QS ? QHB_HC / 2 / QHB_NT : QS) / 4 : 1];
     __shared__ i32 s_off[QHB_DC + 1];
     __shared__ i32 s_vv[QHB_DC];
@@ -1751,9 +1763,9 @@ __global__ void __launch_bounds__(QHB_NT) k_qh_block(DevGraph g, const i32 *__re
     __shared__ i64 s_mid[QGMID_QHB ? 1 : QHB_DC];
     __shared__ i64 s_red[QHB_NT / WAVE];
     __shared__ i32 s_red32[QHB_NT / WAVE];
-    for (int i = threadIdx.x; i < QHB_HC; i += QHB_NT) s_tab[i] = PK_EMPTY;
+    for (int i = threadIdx.x; i < hcb; i += QHB_NT) s_tab[i] = PK_EMPTY;
     __syncthreads();
-    PackedHash H{s_tab, QHB_HC - 1, g.h0};
+    PackedHash H{s_tab, (u32)hcb - 1, g.h0};
     QChunk C{s_off, s_vv, s_beg, QGMID_QHB ? nullptr : s_mid, s_seg};
     i64 *prow = part + (i64)(blockIdx.x % QH_PART_ROWS) * K;
     const i32 cnt = st->cnt[WC_QH_BLOCK];
@@ -1763,8 +1775,8 @@ __global__ void __launch_bounds__(QHB_NT) k_qh_block(DevGraph g, const i32 *__re
     for (; it < cnt; it += gridDim.x) {
         const QMeta nxt = q_meta<Q_HEAVY>(g, xn);
         xn = it + 2 * (i32)gridDim.x < cnt ? list[it + 2 * gridDim.x] : -1;
-        qh_item_packed<QHB_NT, QHB_HC / 2 / QHB_NT, QMAP_QHB, QGMID_QHB>(g, cur, H, QHB_HC, C, QHB_DC, threadIdx.x, s_red,
-                                                              s_red32, Q, prow);
+        qh_item_packed<QHB_NT, QHB_HC / 2 / QHB_NT, QMAP_QHB, QGMID_QHB>(g, cur, H, hcb, C, QHB_DC, threadIdx.x,
+                                                                         s_red, s_red32, Q, prow);
         cur = nxt;
     }
 }
@@ -1970,7 +1982,7 @@ hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvar
 
 hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i64 *Q, i32 *gscratch,
                     i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, i64 *part, int part_rows,
-                    i64 ql_wave_bound, i64 ql_block_bound, i64 ql_split, i64 qh_wave_bound,
+                    i64 ql_wave_bound, i64 ql_block_bound, i64 ql_split, i64 qh_wave_bound, i64 qh_block_bound,
                     const KernelEvents &kev, hipStream_t s) {
     KMARK(5);
     {
@@ -2012,8 +2024,10 @@ hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats 
         hipLaunchKernelGGL(k_qh_wave, dim3(grid_wave), dim3(256), 4 * qhw_wave_bytes(hcw), s, g,
                            lists_host[WC_QH_WAVE], st, Q, part, K, hcw);
         KMARK(9);
-        hipLaunchKernelGGL(k_qh_block, dim3(grid_block), dim3(QHB_NT), 0, s, g, lists_host[WC_QH_BLOCK], st, Q, part,
-                           K);
+        int hcb = 64;
+        while ((i64)hcb < 2 * qh_block_bound && hcb < QHB_HC) hcb <<= 1;
+        hipLaunchKernelGGL(k_qh_block, dim3(grid_block / 4 * QHB_GRID), dim3(QHB_NT), (size_t)hcb * sizeof(u32), s, g,
+                           lists_host[WC_QH_BLOCK], st, Q, part, K, hcb);
         KMARK(10);
         hipLaunchKernelGGL(k_q_dense, dim3(grid_dense), dim3(QD_NT), 0, s, g, lists_host[WC_QH_DENSE], st, Q, part,
                            K);

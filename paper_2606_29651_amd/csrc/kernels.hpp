@@ -166,7 +166,7 @@ hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvar
                         hipStream_t s);
 hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i64 *Q, i32 *gscratch,
                     i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, i64 *part, int part_rows,
-                    i64 ql_wave_bound, i64 ql_block_bound, i64 ql_split, i64 qh_wave_bound,
+                    i64 ql_wave_bound, i64 ql_block_bound, i64 ql_split, i64 qh_wave_bound, i64 qh_block_bound,
                     const KernelEvents &kev, hipStream_t s);
 i64 probe_large_slice_bytes(int cap, int hc, i64 lds_max);
 #define PL_LDS_MAX (150 * 1024)  // largest dynamic LDS of the large probe kernel
