@@ -308,7 +308,7 @@ static niorca_status check_graph_args(niorca_ctx *ctx, int32_t n, int64_t nnz, c
 
 // Workspace layout of one count.
 struct Layout {
-    uint64_t st, deg, val, k2, v2, hist, scan, perm, nrp, nsplit, hstart, lng, ncol, mirror, t, wl, wh;
+    uint64_t st, deg, val, k2, v2, hist, scan, perm, nrp, nsplit, hstart, lng, ncol, mirror, t, wl, wh, vmeta;
     uint64_t lists[WC_COUNT];
     uint64_t acc, tcoff, tccnt, tcbump, tcrec, probes, feat, pred, counters;
     uint64_t base_end;  // everything above needs no graph statistics
@@ -331,6 +331,7 @@ static void layout_base(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz
     // slot arrays carry a pad so that a one-past-the-row read never leaves the buffer
     L.ncol = A.take<i32>(nnz + 64); L.mirror = A.take<i32>(nnz + 64); L.t = A.take<i32>(nnz + 64);
     L.wl = A.take<i64>(n); L.wh = A.take<i64>(n);
+    L.vmeta = A.take<int4>(n);
     for (int c = 0; c < WC_COUNT; c++) L.lists[c] = A.take<i32>(n);
     L.acc = A.take<i64>((uint64_t)n * 10);
     L.tcoff = A.take<i64>(n); L.tccnt = A.take<i32>(n); L.tcbump = A.take<u64>(1);
@@ -443,6 +444,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     i32 *hstart = (i32 *)(W + L.hstart), *longlist = (i32 *)(W + L.lng);
     i32 *ncol = (i32 *)(W + L.ncol), *mirror = (i32 *)(W + L.mirror), *t = (i32 *)(W + L.t);
     i64 *wl = (i64 *)(W + L.wl), *wh = (i64 *)(W + L.wh);
+    int4 *vmeta = (int4 *)(W + L.vmeta);
     ListPtrs lists;
     for (int c = 0; c < WC_COUNT; c++) lists.l[c] = (i32 *)(W + L.lists[c]);
     i64 *accb = (i64 *)(W + L.acc);
@@ -502,15 +504,15 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     // ---- oriented layout: sorted N+, mirror slots, per-vertex 4-cycle work ----
     HIP_TRY(fill32(longcount, sizeof(i32), 0u, s));
     STAGE_MARK(2);
-    hipLaunchKernelGGL(k_sort_upper_small, dim3(cu * 8), dim3(nthr), 0, s, n, nrp, nsplit, ncol, hstart, h0,
+    hipLaunchKernelGGL(k_sort_upper_small, dim3(cu * 8), dim3(nthr), 0, s, n, nrp, nsplit, ncol, hstart, vmeta, h0,
                        longlist, longcount);
-    hipLaunchKernelGGL(k_sort_upper_large, dim3(cu), dim3(256), 0, s, nrp, nsplit, ncol, hstart, h0, longlist,
-                       longcount);
+    hipLaunchKernelGGL(k_sort_upper_large, dim3(cu), dim3(256), 0, s, nrp, nsplit, ncol, hstart, vmeta, h0,
+                       longlist, longcount);
     i64 *probes = (i64 *)(W + L.probes);
     float *feat = L.feat ? (float *)(W + L.feat) : nullptr;
     float *pred = L.pred ? (float *)(W + L.pred) : nullptr;
     i64 *counters = L.counters ? (i64 *)(W + L.counters) : nullptr;
-    hipLaunchKernelGGL(k_mirror, dim3(cu * 8), dim3(nthr), 0, s, n, deg, nrp, nsplit, ncol, hstart, h0, mirror, wl,
+    hipLaunchKernelGGL(k_mirror, dim3(cu * 8), dim3(nthr), 0, s, n, deg, nrp, nsplit, ncol, vmeta, h0, mirror, wl,
                        wh, probes, feat);
     HIP_TRY(hipGetLastError());
     Thresholds th = ctx->th;
@@ -522,7 +524,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
         th.thr_group = ctx->thr_group;
         th.thr_block = ctx->thr_block;
     }
-    DevGraph g{n, (i32)nnz, h0, nrp, nsplit, ncol, mirror, hstart, deg, val, wl, wh};
+    DevGraph g{n, (i32)nnz, h0, nrp, nsplit, ncol, mirror, hstart, deg, val, wl, wh, vmeta};
     HIP_TRY(launch_classify(g, wl, wh, probes, lists, dst, th, s));
     if (counters) {
         HIP_TRY(fill32(counters, (i64)sizeof(i64) * NUM_COUNTERS * n, 0u, s));

@@ -398,8 +398,8 @@ template <int MODE>
 __device__ __forceinline__ PMeta p_meta(const DevGraph &g, const TriCache &tc, i32 u) {
     PMeta m{u, 0, 0, -1, 0};
     if (u >= 0) {
-        m.base = g.nsplit[u];
-        m.du = g.nrp[u + 1] - m.base;
+        m.base = vmeta_at(g, u, VM_NSPLIT);
+        m.du = vmeta_at(g, u, VM_END) - m.base;
         if (MODE == PROBE_TAU) {
             m.tcnt = tc.cnt[u];
             m.toff = tc.off[u];
@@ -464,10 +464,10 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
     item_sync<NT>();
     for (int i = tid; i < du; i += NT) {
         i32 v = g.ncol[base + i];
-        const i32 b = g.nsplit[v];
+        const i32 b = vmeta_at(g, v, VM_NSPLIT);
         if (M.nb) M.nb[i] = v;
         M.beg[i] = b;
-        M.off[i + 1] = g.nrp[v + 1] - b;
+        M.off[i + 1] = vmeta_at(g, v, VM_END) - b;
         u32 sl = hslot((u32)v, hmask);
         while (atomicCAS(&M.hkey[sl], -1, v) != -1) sl = (sl + 1) & hmask;
         M.hpos[sl] = i;
@@ -704,8 +704,12 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
 #ifndef PB_MP
 #define PB_MP 4   // the same, workgroup items
 #endif
+#ifndef PW_WPE
+#define PW_WPE 8  // waves per SIMD the wave kernel is compiled for: 64 registers (with
+                  // one register more a SIMD holds a wave less, measured 30 % slower)
+#endif
 template <int MODE>
-__global__ void __launch_bounds__(256) k_probe_wave(DevGraph g, const i32 *__restrict__ list,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PW_WPE))) k_probe_wave(DevGraph g, const i32 *__restrict__ list,
                                                     const GraphStats *__restrict__ st, i32 *t, i64 *K4,
                                                     i64 *tau, TriCache tc, i64 *counters) {
     constexpr int CAP = TRI_WAVE_CAP, HC = 2 * CAP, PITCH = bit_pitch(CAP);
@@ -853,7 +857,7 @@ __global__ void __launch_bounds__(256) k_probe_thread(DevGraph g, const i32 *__r
         for (int i = 0; i < C; i++) {
             if (i >= du) break;
             const i32 v = nu[i];
-            const i32 q0 = g.nsplit[v], q1 = g.nrp[v + 1];
+            const i32 q0 = vmeta_at(g, v, VM_NSPLIT), q1 = vmeta_at(g, v, VM_END);
             probes += q1 - q0;
             for (i32 q = q0; q < q1; q++) {
                 const i32 w = g.ncol[q];
@@ -1132,11 +1136,11 @@ template <int MODE>
 __device__ __forceinline__ void q_segment(const DevGraph &g, i32 x, i32 s, i32 sp, i32 &v, i32 &beg, i32 &end) {
     v = g.ncol[s];
     if (MODE == Q_LIGHT) {
-        beg = g.nrp[v];
+        beg = vmeta_at(g, v, VM_BEGIN);
         end = g.mirror[s];
     } else {
-        beg = (x >= g.h0 && s < sp) ? g.mirror[s] + 1 : g.hstart[v];
-        end = g.nrp[v + 1];
+        beg = (x >= g.h0 && s < sp) ? g.mirror[s] + 1 : vmeta_at(g, v, VM_HSTART);
+        end = vmeta_at(g, v, VM_END);
     }
 }
 
@@ -1255,9 +1259,9 @@ template <int MODE>
 __device__ __forceinline__ QMeta q_meta(const DevGraph &g, i32 x) {
     QMeta m{x, 0, 0, 0, 0};
     if (x >= 0) {
-        m.s0 = g.nrp[x];
-        m.sp = g.nsplit[x];
-        m.s1 = g.nrp[x + 1];
+        m.s0 = vmeta_at(g, x, VM_BEGIN);
+        m.sp = vmeta_at(g, x, VM_NSPLIT);
+        m.s1 = vmeta_at(g, x, VM_END);
         m.w = (MODE == Q_LIGHT) ? g.wlight[x] : g.wheavy[x];
     }
     return m;

@@ -84,7 +84,9 @@ struct Thresholds {
 #define QL_BLOCK_HC 16384    // largest hash per workgroup, light 4-cycle items (sized per launch)
 #define QH_WAVE_HC 4096     // largest packed (key, count) table per wave (sized per launch)
 #define QH_BLOCK_HC 8192    // packed entries per workgroup
+#ifndef QH_PART_ROWS
 #define QH_PART_ROWS 64     // rows of heavy-key credits (8 per XCD)
+#endif
 #define QH_DENSE_K 32768    // size of the heavy key range (top-ranked vertices)
 #define QH_DENSE_DC 4096    // middles accumulated in LDS by the dense kernel (else global)
 
@@ -112,7 +114,16 @@ struct DevGraph {
     const u32 *order;       // uint32[n]: new id -> input id
     const i64 *wlight;      // int64[n]: 4-cycle wedges with y as largest (light) vertex
     const i64 *wheavy;      // int64[n]: 4-cycle wedges with y opposite a heavy largest vertex
+    const int4 *vmeta;      // int4[n]: {nrp[y], nsplit[y], nrp[y+1], hstart[y]}, one line
+                            // for kernels that visit y as some other vertex's neighbour
 };
+
+enum { VM_BEGIN = 0, VM_NSPLIT = 1, VM_END = 2, VM_HSTART = 3 };
+// One field of vmeta[v] (fields of one vertex share a cache line; loading only the
+// fields used keeps registers free).
+__device__ __forceinline__ i32 vmeta_at(const DevGraph &g, i32 v, int f) {
+    return reinterpret_cast<const i32 *>(g.vmeta)[4 * (i64)v + f];
+}
 
 // prep.hip
 i64 scan_ws_elems(i64 len);
@@ -125,12 +136,12 @@ __global__ void k_degree(i32 n, i64 nnz, const i64 *rp, u32 *deg, u32 *vals, Gra
 __global__ void k_invert(i32 n, const u32 *order, i32 *perm);
 __global__ void k_relabel(i32 n, const i64 *rp, const i32 *col, const u32 *order, const i32 *perm,
                           const u32 *ndeg, const i32 *nrp, i32 *nsplit, i32 *ncol, GraphStats *st);
-__global__ void k_sort_upper_small(i32 n, const i32 *nrp, const i32 *nsplit, i32 *ncol, i32 *hstart, i32 h0,
-                                   i32 *longlist, i32 *longcount);
-__global__ void k_sort_upper_large(const i32 *nrp, const i32 *nsplit, i32 *ncol, i32 *hstart, i32 h0,
+__global__ void k_sort_upper_small(i32 n, const i32 *nrp, const i32 *nsplit, i32 *ncol, i32 *hstart, int4 *vmeta,
+                                   i32 h0, i32 *longlist, i32 *longcount);
+__global__ void k_sort_upper_large(const i32 *nrp, const i32 *nsplit, i32 *ncol, i32 *hstart, int4 *vmeta, i32 h0,
                                    const i32 *longlist, const i32 *longcount);
 __global__ void k_mirror(i32 n, const u32 *ndeg, const i32 *nrp, const i32 *nsplit, const i32 *ncol,
-                         const i32 *hstart, i32 h0, i32 *mirror, i64 *wlight, i64 *wheavy, i64 *probes, float *feat);
+                         const int4 *vmeta, i32 h0, i32 *mirror, i64 *wlight, i64 *wheavy, i64 *probes, float *feat);
 #define LSORT_CAP 16384
 
 // count.hip

@@ -327,8 +327,8 @@ __device__ __forceinline__ i32 bitonic64(i32 v) {
 }
 
 __global__ void k_sort_upper_small(i32 n, const i32 *__restrict__ nrp, const i32 *__restrict__ nsplit,
-                                   i32 *__restrict__ ncol, i32 *__restrict__ hstart, i32 h0,
-                                   i32 *__restrict__ longlist, i32 *__restrict__ longcount) {
+                                   i32 *__restrict__ ncol, i32 *__restrict__ hstart, int4 *__restrict__ vmeta,
+                                   i32 h0, i32 *__restrict__ longlist, i32 *__restrict__ longcount) {
     int waves = gridDim.x * (blockDim.x / WAVE);
     int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     for (i32 y = wid; y < n; y += waves) {
@@ -342,7 +342,11 @@ __global__ void k_sort_upper_small(i32 n, const i32 *__restrict__ nrp, const i32
         if (len > 1) v = bitonic64(v);
         if (l < len) ncol[b + l] = v;
         u64 ge = __ballot(l < len && v >= h0);
-        if (l == 0) hstart[y] = ge ? b + (__ffsll((long long)ge) - 1) : e;
+        if (l == 0) {
+            const i32 hs = ge ? b + (__ffsll((long long)ge) - 1) : e;
+            hstart[y] = hs;
+            vmeta[y] = make_int4(nrp[y], b, e, hs);
+        }
     }
 }
 
@@ -350,7 +354,8 @@ __global__ void k_sort_upper_small(i32 n, const i32 *__restrict__ nrp, const i32
 __global__ void __launch_bounds__(LSORT_NT) k_sort_upper_large(const i32 *__restrict__ nrp,
                                                                const i32 *__restrict__ nsplit,
                                                                i32 *__restrict__ ncol, i32 *__restrict__ hstart,
-                                                               i32 h0, const i32 *__restrict__ longlist,
+                                                               int4 *__restrict__ vmeta, i32 h0,
+                                                               const i32 *__restrict__ longlist,
                                                                const i32 *__restrict__ longcount) {
     __shared__ i32 a[LSORT_CAP];
     __shared__ i32 first;
@@ -382,7 +387,10 @@ __global__ void __launch_bounds__(LSORT_NT) k_sort_upper_large(const i32 *__rest
             if (v >= h0 && (i == 0 || a[i - 1] < h0)) first = b + i;
         }
         __syncthreads();
-        if (threadIdx.x == 0) hstart[y] = first;
+        if (threadIdx.x == 0) {
+            hstart[y] = first;
+            vmeta[y] = make_int4(nrp[y], b, e, first);
+        }
         __syncthreads();
     }
 }
@@ -402,7 +410,7 @@ __global__ void __launch_bounds__(LSORT_NT) k_sort_upper_large(const i32 *__rest
 template <int W>
 __device__ __forceinline__ void mirror_row(i32 y, bool active, int l, const i32 *__restrict__ nrp,
                                            const i32 *__restrict__ nsplit, const i32 *__restrict__ ncol,
-                                           const i32 *__restrict__ hstart, i32 h0, i32 *__restrict__ mirror,
+                                           const int4 *__restrict__ vmeta, i32 h0, i32 *__restrict__ mirror,
                                            i64 *__restrict__ wlight, i64 *__restrict__ wheavy,
                                            i64 *__restrict__ probes, float *__restrict__ feat) {
     i32 b0 = 0, sp = 0, e0 = 0;
@@ -415,17 +423,18 @@ __device__ __forceinline__ void mirror_row(i32 y, bool active, int l, const i32 
     int mx = 0;
     for (i32 s = b0 + l; s < e0; s += W) {
         i32 b = ncol[s];
-        i32 bb = nrp[b], bend = nrp[b + 1];
+        const int4 vb = vmeta[b];  // row start, N+ start, row end, heavy start of b
+        i32 bb = vb.x, bend = vb.z;
         nds += bend - bb;
         if (s < sp) {
-            i32 m = lower_bound_i32(ncol, nsplit[b], bend, y);
+            i32 m = lower_bound_i32(ncol, vb.y, bend, y);
             mirror[s] = m;
             wl += m - bb;
-            i32 st = (y >= h0) ? m + 1 : hstart[b];
+            i32 st = (y >= h0) ? m + 1 : vb.w;
             wh += bend - st;
         } else {
-            wh += bend - hstart[b];
-            i32 dpb = bend - nsplit[b];
+            wh += bend - vb.w;
+            i32 dpb = bend - vb.y;
             pr += dpb;
             mx = max(mx, dpb);
         }
@@ -456,7 +465,7 @@ __device__ __forceinline__ void mirror_row(i32 y, bool active, int l, const i32 
 // work-model features.
 __global__ void k_mirror(i32 n, const u32 *__restrict__ ndeg, const i32 *__restrict__ nrp,
                          const i32 *__restrict__ nsplit, const i32 *__restrict__ ncol,
-                         const i32 *__restrict__ hstart, i32 h0, i32 *__restrict__ mirror,
+                         const int4 *__restrict__ vmeta, i32 h0, i32 *__restrict__ mirror,
                          i64 *__restrict__ wlight, i64 *__restrict__ wheavy, i64 *__restrict__ probes,
                          float *__restrict__ feat) {
     const int waves = gridDim.x * (blockDim.x / WAVE);
@@ -465,9 +474,9 @@ __global__ void k_mirror(i32 n, const u32 *__restrict__ ndeg, const i32 *__restr
     constexpr int GPW = WAVE / SG;
     for (i32 yb = wid * GPW; yb < cut; yb += waves * GPW) {
         const i32 y = yb + lane_id() / SG;
-        mirror_row<SG>(y, y < cut, lane_id() % SG, nrp, nsplit, ncol, hstart, h0, mirror, wlight, wheavy, probes,
+        mirror_row<SG>(y, y < cut, lane_id() % SG, nrp, nsplit, ncol, vmeta, h0, mirror, wlight, wheavy, probes,
                        feat);
     }
     for (i32 y = n - 1 - wid; y >= cut; y -= waves)
-        mirror_row<WAVE>(y, true, lane_id(), nrp, nsplit, ncol, hstart, h0, mirror, wlight, wheavy, probes, feat);
+        mirror_row<WAVE>(y, true, lane_id(), nrp, nsplit, ncol, vmeta, h0, mirror, wlight, wheavy, probes, feat);
 }
