@@ -1378,16 +1378,23 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                 i32 key[QS];
                 bool ok[QS];
                 if constexpr (MAP > 0) {
-                    item_sync<NT>();  // the previous step's map has been read
-                    if constexpr (MAP == 1) {
-                        q_segmap<NT, QS>(C.off, len, eb, total, tid, C.seg);
-                        item_sync<NT>();
-                    } else {
-                        seg_map_scan<NT, QS>(C.off, len, eb, total, tid, C.seg, red32);
+                    // one map per block of NT*MQ wedges (the map's capacity), read by
+                    // MQ/QS steps
+                    constexpr int MQ = QK > QS ? QK : QS;
+                    static_assert(MQ % QS == 0, "map blocks hold whole steps");
+                    const i32 mb = eb - eb % (NT * MQ);
+                    if (mb == eb) {
+                        item_sync<NT>();  // the previous block's map has been read
+                        if constexpr (MAP == 1) {
+                            q_segmap<NT, MQ>(C.off, len, eb, total, tid, C.seg);
+                            item_sync<NT>();
+                        } else {
+                            seg_map_scan<NT, MQ>(C.off, len, eb, total, tid, C.seg, red32);
+                        }
                     }
 #pragma unroll
                     for (int u = 0; u < QS; u++)
-                        si[u] = u < nj ? seg_at(C.seg, min(eb + tid + u * NT, total - 1) - eb) : 0;
+                        si[u] = u < nj ? seg_at(C.seg, min(eb + tid + u * NT, total - 1) - mb) : 0;
                 } else {
                     q_locate<NT, QS>(C.off, len, eb + tid, nj, si, total - 1);
                 }
