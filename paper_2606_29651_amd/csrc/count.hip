@@ -702,7 +702,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
 #define PW_MP 16  // probes per thread of a segment-map block, wave items (0: search)
 #endif
 #ifndef PB_MP
-#define PB_MP 4   // the same, workgroup items
+#define PB_MP 8   // the same, workgroup items
 #endif
 #ifndef PW_WPE
 #define PW_WPE 8  // waves per SIMD the wave kernel is compiled for: 64 registers (with
@@ -1153,13 +1153,13 @@ struct QChunk {
 };
 
 // How each 4-cycle kernel locates wedges (0 search, 1 q_segmap, 2 seg_map_scan): a
-// map costs LDS, and so occupancy, that some kernels cannot spare; the wave kernel
-// makes room for its map by crediting middles straight to Q.
+// map costs LDS, and so occupancy, which the kernels win back by crediting middles
+// straight to Q instead of through per-segment sums in LDS.
 #ifndef QMAP_QLW
-#define QMAP_QLW 0
+#define QMAP_QLW 2
 #endif
 #ifndef QMAP_QLB
-#define QMAP_QLB 0
+#define QMAP_QLB 2
 #endif
 #ifndef QMAP_QHW
 #define QMAP_QHW 2
@@ -1176,6 +1176,12 @@ struct QChunk {
 #endif
 #ifndef QGMID_QHB
 #define QGMID_QHB 0
+#endif
+#ifndef QGMID_QLW
+#define QGMID_QLW 1
+#endif
+#ifndef QGMID_QLB
+#define QGMID_QLB 1
 #endif
 
 
@@ -1487,8 +1493,9 @@ struct LightHash {
 #define QLW_QK 8
 #endif
 #define QLW_SEGB (QMAP_QLW ? WAVE * (QLW_QK > QS ? QLW_QK : QS) : 0)
+#define QLW_MIDB (QGMID_QLW ? 0 : 8 * QLW_DC)
 __host__ __device__ constexpr int qlw_wave_bytes(int hcw) {
-    return ((8 * QLW_DC + QLW_SEGB + 8 * hcw + 4 * (3 * QLW_DC + 1)) + 15) / 16 * 16;
+    return ((QLW_MIDB + QLW_SEGB + 8 * hcw + 4 * (3 * QLW_DC + 1)) + 15) / 16 * 16;
 }
 
 template <int MODE>
@@ -1497,9 +1504,9 @@ __global__ void __launch_bounds__(256) k_q_wave(DevGraph g, const i32 *__restric
     extern __shared__ __align__(16) char s_dyn[];
     const int w = threadIdx.x / WAVE, tid = lane_id();
     char *base = s_dyn + (size_t)w * qlw_wave_bytes(hcw);
-    i64 *s_mid = (i64 *)base;
-    u32 *s_seg = (u32 *)(base + 8 * QLW_DC);
-    i32 *s_key = (i32 *)(base + 8 * QLW_DC + QLW_SEGB);
+    i64 *s_mid = QGMID_QLW ? nullptr : (i64 *)base;
+    u32 *s_seg = (u32 *)(base + QLW_MIDB);
+    i32 *s_key = (i32 *)(base + QLW_MIDB + QLW_SEGB);
     i32 *s_cnt = s_key + hcw;
     i32 *s_off = s_cnt + hcw;
     i32 *s_vv = s_off + QLW_DC + 1;
@@ -1524,7 +1531,8 @@ __global__ void __launch_bounds__(256) k_q_wave(DevGraph g, const i32 *__restric
         LightHash H{s_key, s_cnt, (u32)hc - 1};
         i64 local = 0;
         const bool taken =
-            q_sweeps<WAVE, MODE, QLW_QK, QMAP_QLW>(g, cur, H, C, QLW_DC, tid, nullptr, Q, CreditLight{Q}, &local);
+            q_sweeps<WAVE, MODE, QLW_QK, QMAP_QLW, QGMID_QLW>(g, cur, H, C, QLW_DC, tid, nullptr, Q, CreditLight{Q},
+                                                              &local);
         for (int j = tid; !taken && j < hc; j += WAVE) {
             const i32 k = s_key[j];
             if (k >= 0) {
@@ -1551,8 +1559,9 @@ __global__ void __launch_bounds__(256) k_q_wave(DevGraph g, const i32 *__restric
 #define QLB_NT 256
 #define QLB_QK 16
 #define QLB_SEGB (QMAP_QLB ? QLB_NT * (QLB_QK > QS ? QLB_QK : QS) : 0)
+#define QLB_MIDB (QGMID_QLB ? 0 : 8 * QLB_DC)
 __host__ __device__ constexpr int qlb_bytes(int hcb) {
-    return ((8 * QLB_DC + QLB_SEGB + 8 * hcb + 4 * (3 * QLB_DC + 1)) + 15) / 16 * 16;
+    return ((QLB_MIDB + QLB_SEGB + 8 * hcb + 4 * (3 * QLB_DC + 1)) + 15) / 16 * 16;
 }
 
 // Items of the list with wlo < wedges <= whi only (the class is split into two
@@ -1564,9 +1573,9 @@ __global__ void __launch_bounds__(QLB_NT) k_q_block(DevGraph g, const i32 *__res
     extern __shared__ __align__(16) char s_dyn[];
     __shared__ i64 s_red[QLB_NT / WAVE];
     __shared__ i32 s_red32[QLB_NT / WAVE];
-    i64 *s_mid = (i64 *)s_dyn;
-    u32 *s_seg = (u32 *)(s_dyn + 8 * QLB_DC);
-    i32 *s_key = (i32 *)(s_dyn + 8 * QLB_DC + QLB_SEGB);
+    i64 *s_mid = QGMID_QLB ? nullptr : (i64 *)s_dyn;
+    u32 *s_seg = (u32 *)(s_dyn + QLB_MIDB);
+    i32 *s_key = (i32 *)(s_dyn + QLB_MIDB + QLB_SEGB);
     i32 *s_cnt = s_key + hcb;
     i32 *s_off = s_cnt + hcb;
     i32 *s_vv = s_off + QLB_DC + 1;
@@ -1593,8 +1602,8 @@ __global__ void __launch_bounds__(QLB_NT) k_q_block(DevGraph g, const i32 *__res
         LightHash H{s_key, s_cnt, (u32)hc - 1};
         i64 local = 0;
         const bool taken =
-            q_sweeps<QLB_NT, MODE, QLB_QK, QMAP_QLB>(g, cur, H, C, QLB_DC, threadIdx.x, s_red32, Q, CreditLight{Q},
-                                                     &local);
+            q_sweeps<QLB_NT, MODE, QLB_QK, QMAP_QLB, QGMID_QLB>(g, cur, H, C, QLB_DC, threadIdx.x, s_red32, Q,
+                                                                CreditLight{Q}, &local);
         for (int j = threadIdx.x; !taken && j < hc; j += QLB_NT) {
             const i32 k = s_key[j];
             if (k >= 0) {
