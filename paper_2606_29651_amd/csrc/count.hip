@@ -291,7 +291,7 @@ __device__ __forceinline__ int wave_incl_max(int v) {
 // segment holding e.  NT is a multiple of the wave; red32 holds NT/WAVE entries.
 template <int NT, int PER>
 __device__ __forceinline__ void seg_map_scan(const i32 *off, int len, i32 eb, i32 total, int tid, u32 *map,
-                                             i32 *red32) {
+                                             i32 *red32, int sbase = 0) {
     static_assert(PER % 4 == 0 && NT % WAVE == 0, "whole words per thread, whole waves");
     constexpr int PW = PER / 4;
     u32 *mine = map + tid * PW;
@@ -301,7 +301,7 @@ __device__ __forceinline__ void seg_map_scan(const i32 *off, int len, i32 eb, i3
     const i32 eend = min(eb + NT * PER, total);
     for (int i = tid; i < len; i += NT) {
         const i32 o = off[i];
-        if (o >= eb && o < eend && o < off[i + 1]) ((unsigned char *)map)[o - eb] = (unsigned char)i;
+        if (o >= eb && o < eend && o < off[i + 1]) ((unsigned char *)map)[o - eb] = (unsigned char)(i - sbase);
     }
     item_sync<NT>();
     u32 w[PW];
@@ -327,7 +327,7 @@ __device__ __forceinline__ void seg_map_scan(const i32 *off, int len, i32 eb, i3
         for (int k = 0; k < NT / WAVE; k++)
             if (k < wv) c = max(c, red32[k]);
     }
-    if (eb > 0) c = max(c, seg_search(off, len, eb));
+    if (eb > 0) c = max(c, seg_search(off, len, eb) - sbase);
 #pragma unroll
     for (int k = 0; k < PW; k++) {
         u32 o = 0;
@@ -408,7 +408,7 @@ __device__ __forceinline__ PMeta p_meta(const DevGraph &g, const TriCache &tc, i
     return m;
 }
 
-template <int NT, int MODE, int QP, int MP = 0, int MAXDU = (1 << 30)>
+template <int NT, int MODE, int QP, int MP = 0, int MAXDU = (1 << 30), bool PMAP_SCAN = false>
 __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, int tid, const ProbeMem &M, int hc,
                                            int pitch, i32 *__restrict__ t, i64 *__restrict__ K4,
                                            i64 *__restrict__ tau, i64 *red, i32 *red32, const TriCache &tc,
@@ -542,8 +542,12 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
                 }
                 if (FEW || mapped) {
                     item_sync<NT>();  // the previous block's map has been read
-                    q_segmap<NT, MP>(M.off, du, eb, total, tid, M.seg, FEW ? 0 : sfirst);
-                    item_sync<NT>();
+                    if constexpr (PMAP_SCAN && NT >= WAVE) {
+                        seg_map_scan<NT, MP>(M.off, du, eb, total, tid, M.seg, red32, FEW ? 0 : sfirst);
+                    } else {
+                        q_segmap<NT, MP>(M.off, du, eb, total, tid, M.seg, FEW ? 0 : sfirst);
+                        item_sync<NT>();
+                    }
                 }
             }
             if (FEW || mapped) {
@@ -704,6 +708,12 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
 #ifndef PB_MP
 #define PB_MP 8   // the same, workgroup items
 #endif
+#ifndef PW_MAPSCAN
+#define PW_MAPSCAN 0  // Stage I maps built by seg_map_scan (1) or q_segmap (0)
+#endif
+#ifndef PB_MAPSCAN
+#define PB_MAPSCAN 0
+#endif
 #ifndef PW_WPE
 #define PW_WPE 8  // waves per SIMD the wave kernel is compiled for: 64 registers (with
                   // one register more a SIMD holds a wave less, measured 30 % slower)
@@ -739,7 +749,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PW_WPE
         // the next item's row bounds and the one after's id load while this one runs
         const PMeta nxt = p_meta<MODE>(g, tc, un);
         un = it + 2 * waves < cnt ? list[it + 2 * waves] : -1;
-        probe_item<WAVE, MODE, PW_QP, PW_MP, CAP>(g, cur, tid, M, HC, PITCH, t, K4, tau, nullptr, nullptr, tc,
+        probe_item<WAVE, MODE, PW_QP, PW_MP, CAP, PW_MAPSCAN>(g, cur, tid, M, HC, PITCH, t, K4, tau, nullptr, nullptr, tc,
                                              &s_st[w], counters);
         cur = nxt;
     }
@@ -822,7 +832,7 @@ __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__
     for (; it < cnt; it += gridDim.x) {
         const PMeta nxt = p_meta<MODE>(g, tc, un);
         un = it + 2 * (i32)gridDim.x < cnt ? list[it + 2 * gridDim.x] : -1;
-        probe_item<PB_NT, MODE, PB_QP, PB_MP, CAP>(g, cur, threadIdx.x, M, HC, PITCH, t, K4, tau, s_red, s_red32,
+        probe_item<PB_NT, MODE, PB_QP, PB_MP, CAP, PB_MAPSCAN>(g, cur, threadIdx.x, M, HC, PITCH, t, K4, tau, s_red, s_red32,
                                                    tc, &s_st, counters);
         cur = nxt;
     }
