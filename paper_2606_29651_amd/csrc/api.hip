@@ -465,7 +465,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     hipLaunchKernelGGL(k_invert, dim3((n + nthr - 1) / nthr), dim3(nthr), 0, s, n, val, perm);
     HIP_TRY(scan_u32_to_i32(deg, n, nrp, scanw, 1, s));
     hipLaunchKernelGGL(k_relabel, dim3(cu * 8), dim3(nthr), 0, s, n, rp, col, val, perm, deg, nrp, nsplit, ncol,
-                       dst);
+                       vmeta, dst);
     HIP_TRY(hipGetLastError());
     STAGE_MARK(1);
     GraphStats hs{};
@@ -504,8 +504,8 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     // ---- oriented layout: sorted N+, mirror slots, per-vertex 4-cycle work ----
     HIP_TRY(fill32(longcount, sizeof(i32), 0u, s));
     STAGE_MARK(2);
-    hipLaunchKernelGGL(k_sort_upper_small, dim3(cu * 8), dim3(nthr), 0, s, n, nrp, nsplit, ncol, hstart, vmeta, h0,
-                       longlist, longcount);
+    hipLaunchKernelGGL(k_sort_upper_small, dim3(cu * 8), dim3(nthr), 0, s, n, deg, nrp, nsplit, ncol, hstart, vmeta,
+                       h0, longlist, longcount);
     hipLaunchKernelGGL(k_sort_upper_large, dim3(cu), dim3(256), 0, s, nrp, nsplit, ncol, hstart, vmeta, h0,
                        longlist, longcount);
     i64 *probes = (i64 *)(W + L.probes);

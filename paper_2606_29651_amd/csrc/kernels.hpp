@@ -135,9 +135,9 @@ hipError_t radix_sort_pairs(u32 *k, u32 *v, u32 *k2, u32 *v2, i64 n, int bits, i
 __global__ void k_degree(i32 n, i64 nnz, const i64 *rp, u32 *deg, u32 *vals, GraphStats *st);
 __global__ void k_invert(i32 n, const u32 *order, i32 *perm);
 __global__ void k_relabel(i32 n, const i64 *rp, const i32 *col, const u32 *order, const i32 *perm,
-                          const u32 *ndeg, const i32 *nrp, i32 *nsplit, i32 *ncol, GraphStats *st);
-__global__ void k_sort_upper_small(i32 n, const i32 *nrp, const i32 *nsplit, i32 *ncol, i32 *hstart, int4 *vmeta,
-                                   i32 h0, i32 *longlist, i32 *longcount);
+                          const u32 *ndeg, const i32 *nrp, i32 *nsplit, i32 *ncol, int4 *vmeta, GraphStats *st);
+__global__ void k_sort_upper_small(i32 n, const u32 *ndeg, const i32 *nrp, const i32 *nsplit, i32 *ncol,
+                                   i32 *hstart, int4 *vmeta, i32 h0, i32 *longlist, i32 *longcount);
 __global__ void k_sort_upper_large(const i32 *nrp, const i32 *nsplit, i32 *ncol, i32 *hstart, int4 *vmeta, i32 h0,
                                    const i32 *longlist, const i32 *longcount);
 __global__ void k_mirror(i32 n, const u32 *ndeg, const i32 *nrp, const i32 *nsplit, const i32 *ncol,

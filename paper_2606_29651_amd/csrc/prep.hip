@@ -268,7 +268,7 @@ __device__ __forceinline__ i32 relabel_id(const i32 *__restrict__ col, const i32
 __global__ void k_relabel(i32 n, const i64 *__restrict__ rp, const i32 *__restrict__ col,
                           const u32 *__restrict__ order, const i32 *__restrict__ perm, const u32 *__restrict__ ndeg,
                           const i32 *__restrict__ nrp, i32 *__restrict__ nsplit, i32 *__restrict__ ncol,
-                          GraphStats *__restrict__ st) {
+                          int4 *__restrict__ vmeta, GraphStats *__restrict__ st) {
     int waves = gridDim.x * (blockDim.x / WAVE);
     int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     int dplus_max = 0, bad = 0;
@@ -277,22 +277,26 @@ __global__ void k_relabel(i32 n, const i64 *__restrict__ rp, const i32 *__restri
         i32 x = (i32)order[y];
         i64 beg = rp[x];
         i32 len = (i32)ndeg[y];  // 0 for rows that failed the bounds check
-        i32 nlow = 0;
+        i32 nlow = 0, b_first = 0;  // the first 64 new ids stay in a register for the writes
         for (i32 c = 0; c < len; c += WAVE) {
             i32 j = c + lane_id();
             bool valid = j < len;
             i32 b = valid ? relabel_id(col, perm, beg + j, n, y, bad) : 0;
+            if (c == 0) b_first = b;
             nlow += __popcll(__ballot(valid && b < y));
         }
         i32 ybase = nrp[y];
         i32 lowpos = ybase, uppos = ybase + nlow;
-        if (lane_id() == 0) nsplit[y] = uppos;
+        if (lane_id() == 0) {
+            nsplit[y] = uppos;
+            vmeta[y] = make_int4(ybase, uppos, ybase + len, 0);  // heavy start: once sorted
+        }
         dplus_max = max(dplus_max, len - nlow);
         pairs += (long long)(len - nlow) * (len - nlow - 1) / 2;
         for (i32 c = 0; c < len; c += WAVE) {
             i32 j = c + lane_id();
             bool valid = j < len;
-            i32 b = valid ? relabel_id(col, perm, beg + j, n, y, bad) : 0;
+            i32 b = c == 0 ? b_first : (valid ? relabel_id(col, perm, beg + j, n, y, bad) : 0);
             bool low = valid && b < y;
             u64 ml = __ballot(low), mu = __ballot(valid && !low);
             if (low) ncol[lowpos + __popcll(ml & lanemask_lt())] = b;
@@ -326,12 +330,52 @@ __device__ __forceinline__ i32 bitonic64(i32 v) {
     return v;
 }
 
-__global__ void k_sort_upper_small(i32 n, const i32 *__restrict__ nrp, const i32 *__restrict__ nsplit,
-                                   i32 *__restrict__ ncol, i32 *__restrict__ hstart, int4 *__restrict__ vmeta,
-                                   i32 h0, i32 *__restrict__ longlist, i32 *__restrict__ longcount) {
+// The same network within each aligned 16-lane group (xor distances below 16 stay
+// inside the group).
+__device__ __forceinline__ i32 bitonic16(i32 v) {
+    int l = lane_id() & 15;
+#pragma unroll
+    for (int k = 2; k <= 16; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            i32 o = __shfl_xor(v, j, WAVE);
+            bool up = (l & k) == 0;
+            bool low = (l & j) == 0;
+            v = (low == up) ? min(v, o) : max(v, o);
+        }
+    }
+    return v;
+}
+
+__global__ void k_sort_upper_small(i32 n, const u32 *__restrict__ ndeg, const i32 *__restrict__ nrp,
+                                   const i32 *__restrict__ nsplit, i32 *__restrict__ ncol,
+                                   i32 *__restrict__ hstart, int4 *__restrict__ vmeta, i32 h0,
+                                   i32 *__restrict__ longlist, i32 *__restrict__ longcount) {
     int waves = gridDim.x * (blockDim.x / WAVE);
     int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    for (i32 y = wid; y < n; y += waves) {
+    // rows of degree <= 16 (so |N+| <= 16): four per wave, one per 16-lane group
+    const i32 cut = first_above(ndeg, n, 16);
+    for (i32 yb = wid * 4; yb < cut; yb += waves * 4) {
+        const i32 y = yb + lane_id() / 16, l = lane_id() & 15;
+        const bool act = y < cut;
+        i32 b = 0, e = 0;
+        if (act) {
+            b = nsplit[y];
+            e = nrp[y + 1];
+        }
+        const i32 len = e - b;
+        const bool in = act && l < len;
+        i32 v = in ? ncol[b + l] : 0x7fffffff;
+        if (__ballot(act && len > 1)) v = bitonic16(v);
+        if (in) ncol[b + l] = v;
+        const u32 ge = (u32)(__ballot(in && v >= h0) >> (lane_id() & 48)) & 0xffffu;
+        if (act && l == 0) {
+            const i32 hs = ge ? b + (__ffs((int)ge) - 1) : e;
+            hstart[y] = hs;
+            reinterpret_cast<i32 *>(vmeta)[4 * (i64)y + 3] = hs;
+        }
+    }
+    for (i32 y = cut + wid; y < n; y += waves) {
         i32 b = nsplit[y], e = nrp[y + 1], len = e - b;
         if (len > WAVE) {
             if (lane_id() == 0) longlist[atomicAdd(longcount, 1)] = y;
@@ -345,7 +389,7 @@ __global__ void k_sort_upper_small(i32 n, const i32 *__restrict__ nrp, const i32
         if (l == 0) {
             const i32 hs = ge ? b + (__ffsll((long long)ge) - 1) : e;
             hstart[y] = hs;
-            vmeta[y] = make_int4(nrp[y], b, e, hs);
+            reinterpret_cast<i32 *>(vmeta)[4 * (i64)y + 3] = hs;
         }
     }
 }
@@ -389,7 +433,7 @@ __global__ void __launch_bounds__(LSORT_NT) k_sort_upper_large(const i32 *__rest
         __syncthreads();
         if (threadIdx.x == 0) {
             hstart[y] = first;
-            vmeta[y] = make_int4(nrp[y], b, e, first);
+            reinterpret_cast<i32 *>(vmeta)[4 * (i64)y + 3] = first;
         }
         __syncthreads();
     }
