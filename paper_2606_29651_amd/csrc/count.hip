@@ -340,6 +340,10 @@ __device__ __forceinline__ void seg_map_scan(const i32 *off, int len, i32 eb, i3
 
 enum { PROBE_TRI = 0, PROBE_TAU = 1 };
 
+#ifndef TAU_RK
+#define TAU_RK 4  // triangle records per thread in flight in the tau pass
+#endif
+
 #ifndef QS
 #define QS 8  // wedges per thread per step in the 4-cycle sweeps
 #endif
@@ -426,20 +430,20 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
         item_sync<NT>();
         const i64 r0 = pm.toff, r1 = r0 + pm.tcnt;
         i64 tau_local = 0;
-        // four records per thread in flight; records of one probe batch are stored
+        // TAU_RK records per thread in flight; records of one probe batch are stored
         // in lane order, so runs of lanes share i and add to acc[i] once per run
-        for (i64 rb = r0; rb < r1; rb += (i64)NT * 4) {
-            u64 rec[4];
-            i32 tq[4];
+        for (i64 rb = r0; rb < r1; rb += (i64)NT * TAU_RK) {
+            u64 rec[TAU_RK];
+            i32 tq[TAU_RK];
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
+            for (int k = 0; k < TAU_RK; k++) {
                 const i64 r = rb + tid + (i64)k * NT;
                 rec[k] = r < r1 ? tc.rec[r] : ~0ull;
             }
 #pragma unroll
-            for (int k = 0; k < 4; k++) tq[k] = rec[k] != ~0ull ? t[(i32)(rec[k] >> 32)] : 0;
+            for (int k = 0; k < TAU_RK; k++) tq[k] = rec[k] != ~0ull ? t[(i32)(rec[k] >> 32)] : 0;
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
+            for (int k = 0; k < TAU_RK; k++) {
                 const bool ok = rec[k] != ~0ull;
                 const int i = ok ? (int)(rec[k] & 0xffffu) : 0, p = ok ? (int)((rec[k] >> 16) & 0xffffu) : 0;
                 tau_local += tq[k];
@@ -1770,6 +1774,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QMAP_Q
 
 #define QHB_HC QH_BLOCK_HC
 #define QHB_DC 256
+#ifndef QHB_QK
+#define QHB_QK 16  // wedges per thread kept in registers by the heavy workgroup kernel
+#endif
 #ifndef QHB_NT
 #define QHB_NT 256
 #endif
@@ -1786,7 +1793,7 @@ k_qh_block(DevGraph g, const i32 *__restrict__ list, const GraphStats *__restric
            int hcb) {
     extern __shared__ __align__(16) char s_dyn[];
     u32 *s_tab = (u32 *)s_dyn;
-    __shared__ u32 s_seg[QMAP_QHB ? QHB_NT * (QHB_HC / 2 / QHB_NT > QS ? QHB_HC / 2 / QHB_NT : QS) / 4 : 1];
+    __shared__ u32 s_seg[QMAP_QHB ? QHB_NT * (QHB_QK > QS ? QHB_QK : QS) / 4 : 1];
     __shared__ i32 s_off[QHB_DC + 1];
     __shared__ i32 s_vv[QHB_DC];
     __shared__ i32 s_beg[QHB_DC];
@@ -1805,7 +1812,7 @@ k_qh_block(DevGraph g, const i32 *__restrict__ list, const GraphStats *__restric
     for (; it < cnt; it += gridDim.x) {
         const QMeta nxt = q_meta<Q_HEAVY>(g, xn);
         xn = it + 2 * (i32)gridDim.x < cnt ? list[it + 2 * gridDim.x] : -1;
-        qh_item_packed<QHB_NT, QHB_HC / 2 / QHB_NT, QMAP_QHB, QGMID_QHB>(g, cur, H, hcb, C, QHB_DC, threadIdx.x,
+        qh_item_packed<QHB_NT, QHB_QK, QMAP_QHB, QGMID_QHB>(g, cur, H, hcb, C, QHB_DC, threadIdx.x,
                                                                          s_red, s_red32, Q, prow);
         cur = nxt;
     }
