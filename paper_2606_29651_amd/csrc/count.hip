@@ -1222,8 +1222,10 @@ __device__ __forceinline__ i32 q_load_chunk(const DevGraph &g, i32 x, i32 s0, i3
 // over [0, n) in global scratch).
 
 struct DenseCounter {
+    static constexpr bool LOC_IS_KEY = true;  // a key's counter index is k - h0
     u32 *w;   // K/2 words
     i32 h0;
+    __device__ int loc_of(i32 k) const { return k - h0; }
     // counts k; returns its counter's index, own set when this call took it from 0
     __device__ int inc_at(i32 k, bool &own) const {
         const i32 i = k - h0;
@@ -1247,6 +1249,7 @@ struct DenseCounter {
 };
 
 struct GlobalCounter {
+    static constexpr bool LOC_IS_KEY = false;
     i32 *c;       // [n] zero between items
     i32 *used;    // list of touched keys
     i32 *nused;   // LDS counter
@@ -1338,12 +1341,15 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                     if (tid + j * NT >= total) key[j] = -1;
                 // where each key's count lives, so that the second sweep reads it
                 // without a lookup; bit j of ownm: this thread created key j's count
+                // (a dense counter's location is its key's offset, so it is not kept;
+                // with a map the segments are read from it again rather than kept)
                 int loc[QK];
                 u32 ownm = 0;
 #pragma unroll
                 for (int j = 0; j < QK; j++) {
                     bool o = false;
-                    loc[j] = key[j] >= 0 ? ctr.inc_at(key[j], o) : -1;
+                    const int l = key[j] >= 0 ? ctr.inc_at(key[j], o) : -1;
+                    if constexpr (!Ctr::LOC_IS_KEY) loc[j] = l;
                     ownm |= (u32)o << j;
                 }
                 item_sync<NT>();
@@ -1352,9 +1358,13 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
 #pragma unroll
                 for (int j = 0; j < QK; j++) {
                     if (j < nj) {
-                        const i32 c = loc[j] >= 0 ? ctr.at(loc[j]) : 0;
-                        if constexpr (GMID) wave_run_add(Q, C.vv[lo[j]], c > 1 ? c - 1 : 0);
-                        else wave_run_add(C.mid, lo[j], c > 1 ? c - 1 : 0);
+                        int l;
+                        if constexpr (Ctr::LOC_IS_KEY) l = key[j] >= 0 ? ctr.loc_of(key[j]) : -1;
+                        else l = loc[j];
+                        const int sj = MAP > 0 ? seg_at(C.seg, min(tid + j * NT, total - 1)) : lo[j];
+                        const i32 c = l >= 0 ? ctr.at(l) : 0;
+                        if constexpr (GMID) wave_run_add(Q, C.vv[sj], c > 1 ? c - 1 : 0);
+                        else wave_run_add(C.mid, sj, c > 1 ? c - 1 : 0);
                     }
                 }
                 item_sync<NT>();
@@ -1362,7 +1372,10 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
 #pragma unroll
                 for (int j = 0; j < QK; j++) {
                     if ((ownm >> j) & 1u) {
-                        const i64 c = ctr.take(loc[j]);
+                        int l;
+                        if constexpr (Ctr::LOC_IS_KEY) l = ctr.loc_of(key[j]);
+                        else l = loc[j];
+                        const i64 c = ctr.take(l);
                         if (c >= 2) {
                             const i64 cc = c * (c - 1) / 2;
                             cr(key[j], cc);
@@ -1400,8 +1413,7 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                 if constexpr (MAP > 0) {
                     // one map per block of NT*MQ wedges (the map's capacity), read by
                     // MQ/QS steps
-                    constexpr int MQ = QK > QS ? QK : QS;
-                    static_assert(MQ % QS == 0, "map blocks hold whole steps");
+                    constexpr int MQ = ((QK > QS ? QK : QS) / QS) * QS;  // whole steps
                     const i32 mb = eb - eb % (NT * MQ);
                     if (mb == eb) {
                         item_sync<NT>();  // the previous block's map has been read
@@ -1456,6 +1468,7 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
 // wedge count (at most hcw entries, given with the launch in dynamic LDS), harvested
 // by scanning the item's part of the table.
 struct LightHash {
+    static constexpr bool LOC_IS_KEY = false;
     i32 *key;
     i32 *cnt;
     u32 mask;
@@ -1653,6 +1666,7 @@ __global__ void __launch_bounds__(QLB_NT) k_q_block(DevGraph g, const i32 *__res
 
 // Hash of (key index, count) packed in one 32-bit word: idx << 17 | count.
 struct PackedHash {
+    static constexpr bool LOC_IS_KEY = false;
     u32 *tab;
     u32 mask;
     i32 h0;
@@ -1829,13 +1843,16 @@ __global__ void k_qh_reduce(const i64 *__restrict__ part, int rows, i32 K, i32 h
 
 // Heavy largest vertices: dense 16-bit counters over [h0, n).
 #ifndef QD_NT
-#define QD_NT 512
+#define QD_NT 1024  // 16 waves per workgroup, two workgroups per CU (LDS)
 #endif
 #ifndef QD_QK
-#define QD_QK 16  // wedges per thread kept in registers by the dense kernel
+#define QD_QK 8  // wedges per thread kept in registers by the dense kernel
 #endif
 #define QD_DC 256
-__global__ void __launch_bounds__(QD_NT) __attribute__((amdgpu_waves_per_eu(4))) k_q_dense(DevGraph g, const i32 *__restrict__ list,
+#ifndef QD_WPE
+#define QD_WPE 8  // 64 registers: eight waves per SIMD
+#endif
+__global__ void __launch_bounds__(QD_NT) __attribute__((amdgpu_waves_per_eu(QD_WPE))) k_q_dense(DevGraph g, const i32 *__restrict__ list,
                                                    const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 Kp) {
     __shared__ u32 s_w[QH_DENSE_K / 2];
     __shared__ u32 s_seg[QMAP_QD ? QD_NT * (QD_QK > QS ? QD_QK : QS) / 4 : 1];
