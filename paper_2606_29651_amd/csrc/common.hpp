@@ -52,9 +52,7 @@ __device__ __forceinline__ void wave_run_add(T *dst, int si, int val) {
         else atomicAdd(&dst[si], (T)val);
         val = 0;
     }
-#ifndef RUN_ADD_NO_SKIP
     if (__ballot(val != 0) == 0) return;  // nothing to add anywhere in the wave
-#endif
     const int incl = wave_incl_sum(val);
     const int prev = __shfl_up(si, 1, WAVE);
     const u64 starts = __ballot(lane == 0 || prev != si);

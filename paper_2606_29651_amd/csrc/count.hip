@@ -1751,12 +1751,15 @@ __device__ __forceinline__ void qh_item_packed(const DevGraph &g, const QMeta &m
 #ifndef QHW_QK
 #define QHW_QK 16
 #endif
+#ifndef QHW_WPE
+#define QHW_WPE 4  // waves per SIMD the heavy wave kernel is compiled for
+#endif
 #define QHW_SEGB (QMAP_QHW ? WAVE * (QHW_QK > QS ? QHW_QK : QS) : 0)
 #define QHW_MIDB (QGMID_QHW ? 0 : 8 * QHW_DC)
 __host__ __device__ constexpr int qhw_wave_bytes(int hcw) {
     return ((QHW_MIDB + QHW_SEGB + 4 * hcw + 4 * (3 * QHW_DC + 1)) + 15) / 16 * 16;
 }
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QMAP_QHW ? 4 : 1))) k_qh_wave(DevGraph g, const i32 *__restrict__ list,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QHW_WPE))) k_qh_wave(DevGraph g, const i32 *__restrict__ list,
                                                  const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 K,
                                                  int hcw) {
     extern __shared__ __align__(16) char s_dyn[];
@@ -1789,7 +1792,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QMAP_Q
 #define QHB_HC QH_BLOCK_HC
 #define QHB_DC 256
 #ifndef QHB_QK
-#define QHB_QK 16  // wedges per thread kept in registers by the heavy workgroup kernel
+#define QHB_QK 8  // wedges per thread kept in registers by the heavy workgroup kernel
+                  // (2048, the class's default bound; 76 registers: six waves per SIMD)
 #endif
 #ifndef QHB_NT
 #define QHB_NT 256
@@ -1798,7 +1802,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QMAP_Q
 #define QHB_WPE 1
 #endif
 #ifndef QHB_GRID
-#define QHB_GRID 4  // workgroups per CU (the class's grid is given per 4)
+#define QHB_GRID 6  // workgroups per CU (the class's grid is given per 4): all resident
 #endif
 // The table (hcb entries, a power of two at least twice the class's wedge bound)
 // comes with the launch in dynamic LDS.
