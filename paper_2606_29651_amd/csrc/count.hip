@@ -1584,7 +1584,9 @@ __global__ void __launch_bounds__(256) k_q_wave(DevGraph g, const i32 *__restric
 // per item, at most hcb entries (dynamic LDS given with the launch).
 #define QLB_DC 256
 #define QLB_NT 256
+#ifndef QLB_QK
 #define QLB_QK 16
+#endif
 #define QLB_SEGB (QMAP_QLB ? QLB_NT * (QLB_QK > QS ? QLB_QK : QS) : 0)
 #define QLB_MIDB (QGMID_QLB ? 0 : 8 * QLB_DC)
 __host__ __device__ constexpr int qlb_bytes(int hcb) {
