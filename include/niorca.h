@@ -88,7 +88,7 @@ uint64_t niorca_workspace_bytes(const niorca_ctx *ctx);
  *                        up to ql_split, then windows doubling up to ql_block, each
  *                        with tables sized for its window (default 2048)
  *   "qh_wave"   0..2048  4-cycle wedges opposite a heavy largest vertex: wave hash
- *                        (default 1024; the per-wave table is sized from it)
+ *                        (default 512; the per-wave table is sized from it)
  *   "qh_block"  0..4096  ... workgroup hash (default 2048); above: dense LDS counters
  *   "heavy_k"   -1..32768 how many top-ranked vertices form the heavy range; -1
  *                        (default): 32768 when the maximum degree exceeds 8x the

@@ -34,7 +34,7 @@ struct niorca_ctx {
     bool ev_valid = false;
     // tunable class thresholds and the size of the heavy 4-cycle key range
     Thresholds th{TRI_WAVE_CAP, TRI_BLOCK_CAP, 0, 16, 4096, 0.f, 0.f, nullptr,
-                  512, 8192, 1024, 2048, 2048, 48, -1e30f};
+                  512, 8192, 512, 2048, 2048, 48, -1e30f};
     // size of the heavy 4-cycle key range; -1 = chosen per call from the degrees
     int32_t heavy_k = -1;
     // the last captured batched sequence and the shape it was captured for

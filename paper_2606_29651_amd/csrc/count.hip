@@ -1751,10 +1751,13 @@ __device__ __forceinline__ void qh_item_packed(const DevGraph &g, const QMeta &m
 // the class's wedge bound) comes with the launch, in dynamic LDS.
 #define QHW_DC 64
 #ifndef QHW_QK
-#define QHW_QK 16
+#define QHW_QK 8  // wedges per lane in registers: 512, the class's default bound
 #endif
 #ifndef QHW_WPE
-#define QHW_WPE 4  // waves per SIMD the heavy wave kernel is compiled for
+#define QHW_WPE 6  // waves per SIMD the heavy wave kernel is compiled for (80 registers)
+#endif
+#ifndef QHW_GRID
+#define QHW_GRID 6  // workgroups per CU (the class's grid is given per 4): all resident
 #endif
 #define QHW_SEGB (QMAP_QHW ? WAVE * (QHW_QK > QS ? QHW_QK : QS) : 0)
 #define QHW_MIDB (QGMID_QHW ? 0 : 8 * QHW_DC)
@@ -2081,7 +2084,7 @@ hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats 
         (void)part_rows;
         int hcw = 64;
         while ((i64)hcw < 2 * qh_wave_bound) hcw <<= 1;
-        hipLaunchKernelGGL(k_qh_wave, dim3(grid_wave), dim3(256), 4 * qhw_wave_bytes(hcw), s, g,
+        hipLaunchKernelGGL(k_qh_wave, dim3(grid_wave / 4 * QHW_GRID), dim3(256), 4 * qhw_wave_bytes(hcw), s, g,
                            lists_host[WC_QH_WAVE], st, Q, part, K, hcw);
         KMARK(9);
         int hcb = 64;
