@@ -800,7 +800,7 @@ __global__ void __launch_bounds__(256) k_probe_group(DevGraph g, const i32 *__re
     }
 }
 
-// One 256-thread workgroup per vertex, 64 < |N+(u)| <= TRI_BLOCK_CAP.
+// One PB_NT-thread workgroup per vertex, 64 < |N+(u)| <= TRI_BLOCK_CAP.
 #ifndef PB_NT
 #define PB_NT 512
 #endif
@@ -1291,11 +1291,12 @@ __device__ __forceinline__ QMeta q_meta(const DevGraph &g, i32 x) {
 }
 
 // Both sweeps over the item's wedges, chunk by chunk.  Each thread takes QS wedges
-// per step (independent loads in flight); their segments are found together by a
-// search over the chunk's prefix offsets in LDS.  When the whole item is one
-// chunk of at most NT*QK wedges, every thread keeps its wedges' keys and segments in
+// per step (independent loads in flight); their segments come from a search over
+// the chunk's prefix offsets in LDS or from a segment map.  When the whole item is
+// one chunk of at most NT*QK wedges, every thread keeps its wedges' keys (and,
+// unless the counter derives it from the key, where each key's count lives) in
 // registers: the keys are read from memory once, all loads of a thread in flight
-// together, and the second sweep needs neither loads nor searches; the thread that
+// together, and the second sweep needs neither loads nor lookups; the thread that
 // created a key's counter then credits C(c, 2) through cr, adds it to *local and
 // empties the counter, and the call returns true.  Otherwise (false) the counters
 // are left for the caller to harvest.

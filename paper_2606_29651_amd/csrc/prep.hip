@@ -251,7 +251,8 @@ __global__ void k_invert(i32 n, const u32 *__restrict__ order, i32 *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Relabelled rows: [N- in input order | N+ (unsorted yet)], one wave per row.
+// Relabelled rows: [N- in input order | N+ (unsorted yet)], one wave per row; the
+// row's bounds go to vmeta as well (its heavy start follows once N+ is sorted).
 // ---------------------------------------------------------------------------
 // Column ids outside [0, n) raise bad_input and are read as y itself, which keeps
 // every index in range; the host stops after this kernel when bad_input is set.
@@ -311,9 +312,11 @@ __global__ void k_relabel(i32 n, const i64 *__restrict__ rp, const i32 *__restri
 }
 
 // ---------------------------------------------------------------------------
-// Sorting of the N+ parts.  Rows of length <= 64 are sorted in registers by one
-// wave (bitonic network over the lanes); longer rows are queued for the block
-// kernel, which sorts in LDS.  hstart[y] = first slot of N+(y) holding an id >= h0.
+// Sorting of the N+ parts.  Rows of vertices of degree <= 16 are sorted four per
+// wave, one per 16-lane group; other rows of length <= 64 by one wave (bitonic
+// network over the lanes); longer rows are queued for the block kernel, which
+// sorts in LDS.  hstart[y] (and vmeta[y]'s last field) = first slot of N+(y)
+// holding an id >= h0.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ i32 bitonic64(i32 v) {
     int l = lane_id();
@@ -440,7 +443,8 @@ __global__ void __launch_bounds__(LSORT_NT) k_sort_upper_large(const i32 *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Mirror slots and per-vertex work of the 4-cycle passes, one wave per row y:
+// Mirror slots and per-vertex work of the 4-cycle passes, one wave per row y (or
+// one 16-lane group for rows of degree <= SG_MAXDEG):
 //   lower slot s (neighbour b < y): mirror[s] = slot of y inside N+(b);
 //   wlight[y] = sum over lower slots of (mirror[s] - row start of b): the wedges
 //               with y as the largest vertex;
