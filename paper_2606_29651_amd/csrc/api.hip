@@ -456,7 +456,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     STAGE_MARK(0);
     HIP_TRY(fill32(dst, sizeof(GraphStats), 0u, s));
     // ---- a1: degrees and rank order (stable radix sort of degrees) ----
-    hipLaunchKernelGGL(k_degree, dim3((n + nthr - 1) / nthr), dim3(nthr), 0, s, n, (i64)nnz, rp, deg, val, dst);
+    hipLaunchKernelGGL(k_degree, dim3(cu * 8), dim3(nthr), 0, s, n, (i64)nnz, rp, deg, val, dst);
     HIP_TRY(hipGetLastError());
     int bits = 1;
     while (bits < 31 && ((int64_t)1 << bits) <= (int64_t)n) bits++;

@@ -14,20 +14,28 @@
 // ---------------------------------------------------------------------------
 // A row whose bounds leave [0, nnz] or run backwards gets degree 0 and raises
 // bad_input, so no later kernel reads outside the input.
+// Grid-stride over the vertices; the maximum degree meets in LDS first, so that
+// the shared statistic takes one atomic per workgroup (one per wave serialised
+// tens of thousands of same-address atomics).
 __global__ void k_degree(i32 n, i64 nnz, const i64 *__restrict__ rp, u32 *__restrict__ deg,
                          u32 *__restrict__ vals, GraphStats *__restrict__ st) {
-    i32 v = blockIdx.x * blockDim.x + threadIdx.x;
-    int d = 0;
-    if (v < n) {
+    __shared__ int s_max;
+    if (threadIdx.x == 0) s_max = 0;
+    __syncthreads();
+    int dm = 0;
+    for (i32 v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         i64 b = rp[v], e = rp[v + 1];
         bool ok = b >= 0 && e >= b && e <= nnz && (v > 0 || b == 0) && (v < n - 1 || e == nnz);
         if (!ok) atomicOr(&st->bad_input, 1);
-        d = ok ? (int)(e - b) : 0;
+        const int d = ok ? (int)(e - b) : 0;
         deg[v] = (u32)d;
         vals[v] = (u32)v;
+        dm = max(dm, d);
     }
-    d = wave_max32(d);
-    if (lane_id() == 0 && d > 0) atomicMax(&st->dmax, d);
+    dm = wave_max32(dm);
+    if (lane_id() == 0 && dm > 0) atomicMax(&s_max, dm);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_max > 0) atomicMax(&st->dmax, s_max);
 }
 
 // ---------------------------------------------------------------------------
@@ -306,8 +314,19 @@ __global__ void k_relabel(i32 n, const i64 *__restrict__ rp, const i32 *__restri
             uppos += __popcll(mu);
         }
     }
-    if (lane_id() == 0 && dplus_max > 0) atomicMax(&st->dplus_max, dplus_max);
-    if (lane_id() == 0 && pairs > 0) atomicAdd((unsigned long long *)&st->pairs, (unsigned long long)pairs);
+    // the workgroup's statistics meet in LDS, then one atomic each
+    __shared__ int s_dmax;
+    __shared__ unsigned long long s_pairs;
+    if (threadIdx.x == 0) {
+        s_dmax = 0;
+        s_pairs = 0;
+    }
+    __syncthreads();
+    if (lane_id() == 0 && dplus_max > 0) atomicMax(&s_dmax, dplus_max);
+    if (lane_id() == 0 && pairs > 0) atomicAdd(&s_pairs, (unsigned long long)pairs);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_dmax > 0) atomicMax(&st->dplus_max, s_dmax);
+    if (threadIdx.x == 0 && s_pairs > 0) atomicAdd((unsigned long long *)&st->pairs, s_pairs);
     if (bad) atomicOr(&st->bad_input, 1);
 }
 
