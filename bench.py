@@ -100,6 +100,42 @@ def traffic_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_m
     return "\n".join(lines)
 
 
+SQ_COLS = ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD",
+           "SQ_INSTS_VMEM_WR", "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_ANY", "SQ_WAVE_CYCLES"]
+
+
+def counter_summary(paths):
+    """Text table of shader-sequencer counters per dispatch for each timed kernel, from
+    rocprofv3 --pmc counter CSVs (counters summed over the chip), with two ratios:
+    SALU per VALU instruction and the fraction of wave cycles spent waiting."""
+    import csv
+    acc, calls = {}, {}
+    for path in paths:
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                name = r["Kernel_Name"].replace("void ", "", 1)
+                short = next((k for k, sym in PROF_NAME.items() if name.startswith(sym)), None)
+                if short is None:
+                    continue
+                key = (short, r["Counter_Name"])
+                acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
+                calls.setdefault(key, set()).add(r["Dispatch_Id"])
+    per = {k: v / len(calls[k]) for k, v in acc.items()}
+    head = ["kernel"] + [c.replace("SQ_", "").lower() for c in SQ_COLS] + ["salu/valu", "wait_frac"]
+    lines = ["  ".join(f"{h:>14}" for h in head)]
+    for short in PROF_NAME:
+        row = [per.get((short, c)) for c in SQ_COLS]
+        if row[0] is None:
+            continue
+        valu, salu = per.get((short, "SQ_INSTS_VALU")), per.get((short, "SQ_INSTS_SALU"))
+        wait, cyc = per.get((short, "SQ_WAIT_ANY")), per.get((short, "SQ_WAVE_CYCLES"))
+        ratio = f"{salu / valu:.2f}" if valu and salu is not None else "-"
+        frac = f"{wait / cyc:.2f}" if cyc and wait is not None else "-"
+        lines.append("  ".join([f"{short:>14}"] + [f"{v:14.4g}" if v is not None else f"{'-':>14}" for v in row]
+                               + [f"{ratio:>14}", f"{frac:>14}"]))
+    return "\n".join(lines)
+
+
 def traffic_for(workload, kernel):
     """HBM bytes per launch of kernel from profiles/traffic_<workload>.txt, or None when
     there is no such summary or the kernel sources changed since it was taken."""
@@ -352,12 +388,18 @@ def main():
                                                             "COPY_WRITE_CSV"),
                     help="print the per-kernel HBM traffic summary from rocprofv3 --pmc counter CSVs of the "
                          "bench (FETCH_SIZE, WRITE_SIZE) and of --copy-calibration 1024, then exit")
+    ap.add_argument("--counter-summary", nargs="+", metavar="CSV",
+                    help="print shader-sequencer counters per dispatch of each timed kernel from rocprofv3 "
+                         "--pmc counter CSVs of the bench, then exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain int32->float32 copy of MIB MiB five times (reads and writes "
                          "MIB MiB each), to scale HBM byte counters taken under rocprofv3 --pmc")
     args = ap.parse_args()
     if args.traffic_summary:
         print(traffic_summary(*args.traffic_summary, copy_mib=1024))
+        return
+    if args.counter_summary:
+        print(counter_summary(args.counter_summary))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
