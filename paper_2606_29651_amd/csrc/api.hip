@@ -506,8 +506,8 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     STAGE_MARK(2);
     hipLaunchKernelGGL(k_sort_upper_small, dim3(cu * 8), dim3(nthr), 0, s, n, deg, nrp, nsplit, ncol, hstart, vmeta,
                        h0, longlist, longcount);
-    hipLaunchKernelGGL(k_sort_upper_large, dim3(cu), dim3(256), 0, s, nrp, nsplit, ncol, hstart, vmeta, h0,
-                       longlist, longcount);
+    hipLaunchKernelGGL(k_sort_upper_large, dim3(cu * LSORT_GRID), dim3(LSORT_NT), 0, s, nrp, nsplit, ncol, hstart,
+                       vmeta, h0, longlist, longcount);
     i64 *probes = (i64 *)(W + L.probes);
     float *feat = L.feat ? (float *)(W + L.feat) : nullptr;
     float *pred = L.pred ? (float *)(W + L.pred) : nullptr;

@@ -143,6 +143,12 @@ __global__ void k_sort_upper_large(const i32 *nrp, const i32 *nsplit, i32 *ncol,
 __global__ void k_mirror(i32 n, const u32 *ndeg, const i32 *nrp, const i32 *nsplit, const i32 *ncol,
                          const int4 *vmeta, i32 h0, i32 *mirror, i64 *wlight, i64 *wheavy, i64 *probes, float *feat);
 #define LSORT_CAP 16384
+#ifndef LSORT_NT
+#define LSORT_NT 512  // threads of the long-row sort
+#endif
+#ifndef LSORT_GRID
+#define LSORT_GRID 2  // its workgroups per CU (64 KiB of LDS each)
+#endif
 
 // count.hip
 hipError_t launch_classify(const DevGraph &g, const i64 *wl, const i64 *wh, const i64 *probes, const ListPtrs &lists,

@@ -416,7 +416,6 @@ __global__ void k_sort_upper_small(i32 n, const u32 *__restrict__ ndeg, const i3
     }
 }
 
-#define LSORT_NT 256
 __global__ void __launch_bounds__(LSORT_NT) k_sort_upper_large(const i32 *__restrict__ nrp,
                                                                const i32 *__restrict__ nsplit,
                                                                i32 *__restrict__ ncol, i32 *__restrict__ hstart,
