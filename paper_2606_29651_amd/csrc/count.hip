@@ -701,7 +701,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
 #define PW_QP 4   // probes per thread and round, wave items
 #endif
 #ifndef PB_QP
-#define PB_QP 4   // probes per thread and round, workgroup items
+#define PB_QP 8   // probes per thread and round, workgroup items
 #endif
 #ifndef PL_QP
 #define PL_QP 4   // probes per thread and round, large items
