@@ -7,9 +7,12 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 Contents
   * ``brute``          -- definition-level brute force in pure Python (tiny graphs).
   * ``niorca_ref.c``   -- plain C: the definition by connected-set enumeration
-                          (``enum_count``) and the paper's three-stage method
-                          (``stage1``/``stage2``/``stage3``/``count``), plus
-                          ``orbits_at`` for selected vertices of large graphs.
+                          (``enum_count``; ``enum_induced`` for the induced
+                          counts), the paper's three-stage method
+                          (``stage1``/``stage2``/``stage3``/``count``),
+                          ``orbits_at`` for selected vertices of large graphs, and
+                          whole-graph counts for exact checks at any size
+                          (``cycles4_total``, ``k4_total``, ``edge_k4``).
   * ``build()``        -- compiles ``niorca_ref.c`` with gcc into
                           ``oracle/libniorca_ref.so``.
 """
@@ -51,6 +54,10 @@ def _load():
         P = ctypes.c_void_p
         i32, i64 = ctypes.c_int32, ctypes.c_int64
         lib.oref_enum_count.argtypes = [i32, P, P, P]
+        lib.oref_enum_induced.argtypes = [i32, P, P, P]
+        lib.oref_cycles4_total.argtypes = [i32, P, P, P]
+        lib.oref_k4_total.argtypes = [i32, P, P, P]
+        lib.oref_edge_k4.argtypes = [i32, P, P, i64, P, P]
         lib.oref_stage1.argtypes = [i32, P, P, P]
         lib.oref_stage2.argtypes = [i32, P, P, P]
         lib.oref_stage3.argtypes = [i32, P, P, P, P, P, P]
@@ -59,7 +66,8 @@ def _load():
         lib.oref_set_threads.argtypes = [ctypes.c_int]
         lib.oref_num_threads.restype = ctypes.c_int
         for name in ("oref_enum_count", "oref_stage1", "oref_stage2", "oref_stage3",
-                     "oref_count", "oref_orbits_at"):
+                     "oref_count", "oref_orbits_at", "oref_enum_induced", "oref_cycles4_total",
+                     "oref_k4_total", "oref_edge_k4"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -97,6 +105,45 @@ def enum_count(row_ptr, col) -> np.ndarray:
     psi = np.zeros((max(n, 0), 15), dtype=np.int64)
     _check(_load().oref_enum_count(n, _ptr(rp), _ptr(cl), _ptr(psi)), "enum_count")
     return psi
+
+
+def enum_induced(row_ptr, col) -> np.ndarray:
+    """Induced orbit counts psi' int64[n, 15] (each connected vertex set S counted
+    once, as the graphlet G[S]: Section 3, Definition 2)."""
+    n, rp, cl = _csr(row_ptr, col)
+    psi = np.zeros((max(n, 0), 15), dtype=np.int64)
+    _check(_load().oref_enum_induced(n, _ptr(rp), _ptr(cl), _ptr(psi)), "enum_induced")
+    return psi
+
+
+def cycles4_total(row_ptr, col) -> int:
+    """Number of 4-cycles of the graph (each once)."""
+    n, rp, cl = _csr(row_ptr, col)
+    out = np.zeros(1, dtype=np.int64)
+    _check(_load().oref_cycles4_total(n, _ptr(rp), _ptr(cl), _ptr(out)), "cycles4_total")
+    return int(out[0])
+
+
+def k4_total(row_ptr, col) -> int:
+    """Number of 4-cliques of the graph (each once)."""
+    n, rp, cl = _csr(row_ptr, col)
+    out = np.zeros(1, dtype=np.int64)
+    _check(_load().oref_k4_total(n, _ptr(rp), _ptr(cl), _ptr(out)), "k4_total")
+    return int(out[0])
+
+
+def edge_k4(row_ptr, col, slots=None) -> np.ndarray:
+    """4-cliques through the edge of each CSR slot: int64[nnz], or int64[len(slots)]
+    for the listed slots."""
+    n, rp, cl = _csr(row_ptr, col)
+    if slots is None:
+        out = np.zeros(cl.shape[0], dtype=np.int64)
+        _check(_load().oref_edge_k4(n, _ptr(rp), _ptr(cl), 0, None, _ptr(out)), "edge_k4")
+        return out
+    sl = np.ascontiguousarray(slots, dtype=np.int64)
+    out = np.zeros(sl.shape[0], dtype=np.int64)
+    _check(_load().oref_edge_k4(n, _ptr(rp), _ptr(cl), sl.shape[0], _ptr(sl), _ptr(out)), "edge_k4")
+    return out
 
 
 def stage1(row_ptr, col) -> np.ndarray:

@@ -100,8 +100,10 @@ def classify(vertices, edges):
     return {v: base + levels.index(deg[v]) for v in vs}
 
 
-def orbit_counts(n: int, edge_list) -> np.ndarray:
-    """psi[x, k] for a simple undirected graph given as n and a list of (u, v)."""
+def orbit_counts(n: int, edge_list, induced: bool = False) -> np.ndarray:
+    """psi[x, k] for a simple undirected graph given as n and a list of (u, v).
+    With induced=True, psi'[x, k]: only the full edge set of G inside S counts
+    (Definition 2), so each connected vertex set S is one occurrence."""
     E = set()
     for a, b in edge_list:
         a, b = int(a), int(b)
@@ -114,7 +116,7 @@ def orbit_counts(n: int, edge_list) -> np.ndarray:
             inside = [e for e in itertools.combinations(S, 2) if e in E]
             if len(inside) < k - 1:
                 continue
-            for r in range(k - 1, len(inside) + 1):
+            for r in ([len(inside)] if induced else range(k - 1, len(inside) + 1)):
                 for sub in itertools.combinations(inside, r):
                     touched = {v for e in sub for v in e}
                     if len(touched) != k or not _connected(S, sub):
@@ -124,7 +126,7 @@ def orbit_counts(n: int, edge_list) -> np.ndarray:
     return psi
 
 
-def orbit_counts_csr(row_ptr, col) -> np.ndarray:
+def orbit_counts_csr(row_ptr, col, induced: bool = False) -> np.ndarray:
     row_ptr = np.asarray(row_ptr)
     col = np.asarray(col)
     n = row_ptr.shape[0] - 1
@@ -134,4 +136,4 @@ def orbit_counts_csr(row_ptr, col) -> np.ndarray:
             y = int(col[s])
             if x < y:
                 edges.append((x, y))
-    return orbit_counts(n, edges)
+    return orbit_counts(n, edges, induced)

@@ -15,15 +15,22 @@
  *     sparse graphs of a few thousand vertices and on small dense graphs.
  *
  *  2. oref_stage1/2/3, oref_count, oref_orbits_at -- the paper's three-stage
- *     method: Stage I per-edge triangle counts (Algorithm 1), Stage II K4 counts
- *     (Algorithm 2), Stage III f-variable probing over the four substructures of
+ *     method: Stage I per-edge triangle counts (Algorithm 1), Stage II the
+ *     4-cliques through each vertex (what Algorithm 2 computes, counted here from
+ *     the definition), Stage III f-variable probing over the four substructures of
  *     Table 1 followed by the non-induced equations of Section 5 and the Appendix.
+ *
+ *  3. oref_enum_induced -- the induced orbit counts (Definition 2), by the same
+ *     enumeration as 1; oref_cycles4_total, oref_k4_total, oref_edge_k4 --
+ *     whole-graph counts of 4-cycles and 4-cliques and the 4-cliques through each
+ *     edge, exact checks on outputs too large for the per-vertex oracle.
  *
  * Readings taken where the text is silent, ambiguous or garbled (each one is
  * checked against formulation 1 and Python brute force by the tests):
- *   - Algorithm 2: the neigh buffer is emptied for every (x, y) pair, the id
- *     tests are strict (y > x, z > y) and the pair loop starts after i, so each
- *     4-clique is found once, from its smallest vertex.
+ *   - Stage II: Algorithm 2 is not run as printed (its neigh buffer would have
+ *     to be emptied for every (x, y) pair, with strict id tests, to find each
+ *     4-clique once); its result, the 4-cliques through each vertex, is counted
+ *     from the definition instead.
  *   - psi_1, psi_2, psi_3 are the non-induced 3-vertex counts found while probing:
  *     psi_1 sums d(y)-1 over neighbours y, psi_2 counts neighbour pairs, psi_3
  *     counts triangles at x.
@@ -148,7 +155,10 @@ static int occurrence_orbits(int k, int npairs, const int *pi, const int *pj,
     return 0;
 }
 
-static void credit_set(const i64 *rp, const i32 *col, int k, const i32 *S, i64 *psi)
+/* Credits the occurrences on the connected vertex set S.  Non-induced (induced =
+ * 0): every subset of the edges of G inside S that connects S.  Induced (induced =
+ * 1): only the full edge set of G inside S, the subgraph G[S] (Definition 2). */
+static void credit_set(const i64 *rp, const i32 *col, int k, const i32 *S, i64 *psi, int induced)
 {
     static const int PI3[3] = {0, 0, 1}, PJ3[3] = {1, 2, 2};
     const int *pi = (k == 4) ? PI4 : PI3, *pj = (k == 4) ? PJ4 : PJ3;
@@ -156,6 +166,15 @@ static void credit_set(const i64 *rp, const i32 *col, int k, const i32 *S, i64 *
     unsigned present = 0;
     for (int p = 0; p < npairs; p++)
         if (slot_of(rp, col, S[pi[p]], S[pj[p]]) >= 0) present |= 1u << p;
+    if (induced) {
+        int orb[4];
+        if (occurrence_orbits(k, npairs, pi, pj, present, orb) == 0)
+            for (int v = 0; v < k; v++) {
+#pragma omp atomic
+                psi[(i64)S[v] * 15 + orb[v]] += 1;
+            }
+        return;
+    }
     /* every subset of the present pairs */
     for (unsigned sub = present;; sub = (sub - 1) & present) {
         int orb[4];
@@ -181,9 +200,9 @@ static int adjacent_to_set(const i64 *rp, const i32 *col, const i32 *S, int k, i
 }
 
 static void extend(const i64 *rp, const i32 *col, i32 *S, int k, i32 *ext, int next, i64 *psi,
-                   i32 *buf, i64 bufcap)
+                   i32 *buf, i64 bufcap, int induced)
 {
-    credit_set(rp, col, k, S, psi);
+    credit_set(rp, col, k, S, psi, induced);
     if (k == 4) return;
     /* ext[0..next) is the current extension set */
     for (int i = 0; i < next; i++) {
@@ -204,12 +223,13 @@ static void extend(const i64 *rp, const i32 *col, i32 *S, int k, i32 *ext, int n
             }
         }
         S[k] = w;
-        extend(rp, col, S, k + 1, ne, nn, psi, buf + nn, bufcap - nn);
+        extend(rp, col, S, k + 1, ne, nn, psi, buf + nn, bufcap - nn, induced);
     }
 }
 
-/* psi int64[n*15] (zeroed here).  Enumerates each connected vertex set once. */
-int oref_enum_count(i32 n, const i64 *rp, const i32 *col, i64 *psi)
+/* Orbit counts by enumerating each connected vertex set once; psi int64[n*15]
+ * (zeroed here); induced selects Definition 2 (G[S] only) over Definition 3. */
+static int enum_orbits(i32 n, const i64 *rp, const i32 *col, i64 *psi, int induced)
 {
     if (n < 0 || (n > 0 && (!rp || !col)) || !psi) return ORACLE_EINVAL;
     memset(psi, 0, sizeof(i64) * 15 * (size_t)n);
@@ -230,12 +250,25 @@ int oref_enum_count(i32 n, const i64 *rp, const i32 *col, i64 *psi)
                 S[0] = v;
                 int nn = 0;
                 for (i64 s = rp[v]; s < rp[v + 1]; s++) if (col[s] > v) buf[nn++] = col[s];
-                extend(rp, col, S, 1, buf, nn, psi, buf + nn, cap - nn);
+                extend(rp, col, S, 1, buf, nn, psi, buf + nn, cap - nn, induced);
             }
             free(buf);
         }
     }
     return err ? ORACLE_ENOMEM : ORACLE_OK;
+}
+
+/* Non-induced orbit counts psi_k (Section 3, Definitions 3-5), int64[n*15]. */
+int oref_enum_count(i32 n, const i64 *rp, const i32 *col, i64 *psi)
+{
+    return enum_orbits(n, rp, col, psi, 0);
+}
+
+/* Induced orbit counts psi'_k (Section 3, Definition 2: each connected vertex set S
+ * contributes the one graphlet G[S]), int64[n*15], same orbit numbering. */
+int oref_enum_induced(i32 n, const i64 *rp, const i32 *col, i64 *psi)
+{
+    return enum_orbits(n, rp, col, psi, 1);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -267,54 +300,47 @@ int oref_stage1(i32 n, const i64 *rp, const i32 *col, i32 *tri)
     return ORACLE_OK;
 }
 
-/* Stage II (Algorithm 2): for x, every neighbour y > x, the neighbours z > y of y
- * that are also neighbours of x go to neigh (emptied for every y); every adjacent
- * pair z < z' of neigh closes a 4-clique {x, y, z, z'} and all four get +1. */
+/* Stage II: K4[x] = the number of 4-cliques containing x (psi_14 of Section 5;
+ * Algorithm 2 computes these counts).  A 4-clique through x is x together with a
+ * triangle {a, b, c} of G inside N(x), so for every x the neighbours are marked
+ * and each such triangle a < b < c is found once: from its edge (a, b), b > a, and
+ * every c > b adjacent to a, to b and to x. */
 int oref_stage2(i32 n, const i64 *rp, const i32 *col, i64 *K4)
 {
     if (n < 0 || (n > 0 && (!rp || !col || !K4))) return ORACLE_EINVAL;
     if (n == 0) return ORACLE_OK;
-    memset(K4, 0, sizeof(i64) * (size_t)n);
-    i64 dmax = 0;
-    for (i32 v = 0; v < n; v++) if (deg_of(rp, v) > dmax) dmax = deg_of(rp, v);
     int err = 0;
 #pragma omp parallel
     {
         unsigned char *inx = (unsigned char *)calloc((size_t)n, 1);
-        i32 *neigh = (i32 *)malloc(sizeof(i32) * (size_t)(dmax + 1));
-        if (!inx || !neigh) {
+        unsigned char *ina = (unsigned char *)calloc((size_t)n, 1);
+        if (!inx || !ina) {
 #pragma omp atomic write
             err = 1;
         } else {
 #pragma omp for schedule(dynamic, 1)
             for (i32 x = 0; x < n; x++) {
+                i64 cliques = 0;
                 for (i64 s = rp[x]; s < rp[x + 1]; s++) inx[col[s]] = 1;
                 for (i64 s = rp[x]; s < rp[x + 1]; s++) {
-                    i32 y = col[s];
-                    if (y <= x) continue;
-                    i64 len = 0;
-                    for (i64 r = rp[y]; r < rp[y + 1]; r++) {
-                        i32 z = col[r];
-                        if (z > y && inx[z]) neigh[len++] = z;
+                    i32 a = col[s];
+                    for (i64 r = rp[a]; r < rp[a + 1]; r++) ina[col[r]] = 1;
+                    for (i64 r = rp[a]; r < rp[a + 1]; r++) {
+                        i32 b = col[r];
+                        if (b <= a || !inx[b]) continue;
+                        for (i64 q = rp[b]; q < rp[b + 1]; q++) {
+                            i32 c = col[q];
+                            if (c > b && inx[c] && ina[c]) cliques++;
+                        }
                     }
-                    for (i64 i = 0; i < len; i++)
-                        for (i64 j = i + 1; j < len; j++)
-                            if (slot_of(rp, col, neigh[i], neigh[j]) >= 0) {
-#pragma omp atomic
-                                K4[x] += 1;
-#pragma omp atomic
-                                K4[y] += 1;
-#pragma omp atomic
-                                K4[neigh[i]] += 1;
-#pragma omp atomic
-                                K4[neigh[j]] += 1;
-                            }
+                    for (i64 r = rp[a]; r < rp[a + 1]; r++) ina[col[r]] = 0;
                 }
                 for (i64 s = rp[x]; s < rp[x + 1]; s++) inx[col[s]] = 0;
+                K4[x] = cliques;
             }
         }
         free(inx);
-        free(neigh);
+        free(ina);
     }
     return err ? ORACLE_ENOMEM : ORACLE_OK;
 }
@@ -581,4 +607,233 @@ int oref_orbits_at(i32 n, const i64 *rp, const i32 *col, i32 nq, const i32 *xs,
         scratch_free(&sc);
     }
     return err;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Whole-graph counts used as exact checks on large outputs: the number of     */
+/* 4-cycles and of 4-cliques, and the 4-cliques through each edge.             */
+/* ------------------------------------------------------------------------- */
+
+/* The graph renumbered by a total order of the vertices, rows sorted: vertex
+ * r is the r-th vertex in the order (degree, id) ascending.  Any total order
+ * names every 4-cycle by its largest vertex and every 4-clique by its smallest;
+ * ordering by degree only keeps the lists scanned below short. */
+typedef struct {
+    i64 *rp;   /* [n+1] */
+    i32 *col;  /* [rp[n]] ranks, each row ascending */
+} ranked_t;
+
+static int cmp_u64(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : (x > y);
+}
+
+static int cmp_i32(const void *a, const void *b)
+{
+    i32 x = *(const i32 *)a, y = *(const i32 *)b;
+    return x < y ? -1 : (x > y);
+}
+
+static int ranked_build(i32 n, const i64 *rp, const i32 *col, ranked_t *R)
+{
+    R->rp = NULL;
+    R->col = NULL;
+    uint64_t *key = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n ? n : 1));
+    i32 *rank = (i32 *)malloc(sizeof(i32) * (size_t)(n ? n : 1));
+    R->rp = (i64 *)malloc(sizeof(i64) * (size_t)(n + 1));
+    R->col = (i32 *)malloc(sizeof(i32) * (size_t)(rp[n] ? rp[n] : 1));
+    if (!key || !rank || !R->rp || !R->col) {
+        free(key); free(rank); free(R->rp); free(R->col);
+        return ORACLE_ENOMEM;
+    }
+    for (i32 v = 0; v < n; v++) key[v] = ((uint64_t)deg_of(rp, v) << 32) | (uint32_t)v;
+    qsort(key, (size_t)n, sizeof(uint64_t), cmp_u64);
+    for (i32 r = 0; r < n; r++) rank[(i32)(key[r] & 0xffffffffu)] = r;
+    R->rp[0] = 0;
+    for (i32 r = 0; r < n; r++) R->rp[r + 1] = R->rp[r] + deg_of(rp, (i32)(key[r] & 0xffffffffu));
+#pragma omp parallel for schedule(dynamic, 256)
+    for (i32 r = 0; r < n; r++) {
+        i32 v = (i32)(key[r] & 0xffffffffu);
+        i64 o = R->rp[r];
+        for (i64 s = rp[v]; s < rp[v + 1]; s++) R->col[o++] = rank[col[s]];
+        qsort(R->col + R->rp[r], (size_t)(R->rp[r + 1] - R->rp[r]), sizeof(i32), cmp_i32);
+    }
+    free(key);
+    free(rank);
+    return ORACLE_OK;
+}
+
+static void ranked_free(ranked_t *R) { free(R->rp); free(R->col); }
+
+/* Number of 4-cycles of G, each once.  A 4-cycle is named by its largest vertex
+ * v and the vertex c opposite v; its other two vertices are common neighbours of
+ * v and c below v.  So for a fixed v the cycles number sum over c < v of
+ * C(k_c, 2), k_c = #{b < v : b adjacent to v and to c}. */
+int oref_cycles4_total(i32 n, const i64 *rp, const i32 *col, i64 *out)
+{
+    if (n < 0 || (n > 0 && (!rp || !col)) || !out) return ORACLE_EINVAL;
+    *out = 0;
+    if (n == 0) return ORACLE_OK;
+    ranked_t R;
+    if (ranked_build(n, rp, col, &R)) return ORACLE_ENOMEM;
+    int err = 0;
+    i64 total = 0;
+#pragma omp parallel reduction(+ : total)
+    {
+        i32 *k = (i32 *)calloc((size_t)n, sizeof(i32));
+        i32 *touched = (i32 *)malloc(sizeof(i32) * (size_t)n);
+        if (!k || !touched) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+#pragma omp for schedule(dynamic, 64)
+            for (i32 v = 0; v < n; v++) {
+                i64 nt = 0;
+                for (i64 s = R.rp[v]; s < R.rp[v + 1] && R.col[s] < v; s++) {
+                    i32 b = R.col[s];
+                    for (i64 q = R.rp[b]; q < R.rp[b + 1] && R.col[q] < v; q++) {
+                        i32 c = R.col[q];
+                        if (k[c]++ == 0) touched[nt++] = c;
+                    }
+                }
+                for (i64 i = 0; i < nt; i++) {
+                    i64 kc = k[touched[i]];
+                    total += kc * (kc - 1) / 2;
+                    k[touched[i]] = 0;
+                }
+            }
+        }
+        free(k);
+        free(touched);
+    }
+    ranked_free(&R);
+    if (err) return ORACLE_ENOMEM;
+    *out = total;
+    return ORACLE_OK;
+}
+
+/* Number of 4-cliques of G, each once.  A 4-clique is named by its smallest
+ * vertex u; the other three are neighbours of u above it, pairwise adjacent: a
+ * triangle of the graph H_u on the neighbours above u.  H_u is kept as bit rows
+ * (row i: the neighbours above u adjacent to the i-th one and above it), and
+ * every edge (i, p) of H_u closes as many triangles as rows i and p share bits. */
+int oref_k4_total(i32 n, const i64 *rp, const i32 *col, i64 *out)
+{
+    if (n < 0 || (n > 0 && (!rp || !col)) || !out) return ORACLE_EINVAL;
+    *out = 0;
+    if (n == 0) return ORACLE_OK;
+    ranked_t R;
+    if (ranked_build(n, rp, col, &R)) return ORACLE_ENOMEM;
+    int err = 0;
+    i64 total = 0;
+#pragma omp parallel reduction(+ : total)
+    {
+        i32 *pos = (i32 *)malloc(sizeof(i32) * (size_t)n);
+        uint64_t *rows = NULL;
+        i64 rows_cap = 0;
+        if (!pos) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+            for (i32 v = 0; v < n; v++) pos[v] = -1;
+#pragma omp for schedule(dynamic, 16)
+            for (i32 u = 0; u < n; u++) {
+                i64 a = R.rp[u], e = R.rp[u + 1];
+                while (a < e && R.col[a] < u) a++;        /* neighbours above u: R.col[a..e) */
+                i64 du = e - a;
+                if (du < 3) continue;
+                i64 words = (du + 63) / 64;
+                if (du * words > rows_cap) {
+                    free(rows);
+                    rows_cap = du * words;
+                    rows = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)rows_cap);
+                    if (!rows) {
+                        rows_cap = 0;
+#pragma omp atomic write
+                        err = 1;
+                        continue;
+                    }
+                }
+                memset(rows, 0, sizeof(uint64_t) * (size_t)(du * words));
+                for (i64 i = 0; i < du; i++) pos[R.col[a + i]] = (i32)i;
+                for (i64 i = 0; i < du; i++) {
+                    i32 v = R.col[a + i];
+                    for (i64 q = R.rp[v + 1] - 1; q >= R.rp[v] && R.col[q] > v; q--) {
+                        i32 p = pos[R.col[q]];
+                        if (p >= 0) rows[i * words + p / 64] |= 1ull << (p % 64);
+                    }
+                }
+                for (i64 i = 0; i < du; i++)
+                    for (i64 w = 0; w < words; w++) {
+                        uint64_t bits = rows[i * words + w];
+                        while (bits) {
+                            i64 p = w * 64 + __builtin_ctzll(bits);
+                            bits &= bits - 1;
+                            for (i64 x = 0; x < words; x++)
+                                total += __builtin_popcountll(rows[i * words + x] & rows[p * words + x]);
+                        }
+                    }
+                for (i64 i = 0; i < du; i++) pos[R.col[a + i]] = -1;
+            }
+        }
+        free(pos);
+        free(rows);
+    }
+    ranked_free(&R);
+    if (err) return ORACLE_ENOMEM;
+    *out = total;
+    return ORACLE_OK;
+}
+
+/* 4-cliques through edges: for CSR slot s = (a, b), ek4 = the number of edges
+ * {c, d} of G with c and d both common neighbours of a and b (each such edge makes
+ * {a, b, c, d} a 4-clique, and every 4-clique through a and b arises once).  For
+ * nq slots listed in slots (all rp[n] slots when slots is NULL); ek4 int64[nq]
+ * (or int64[rp[n]]). */
+int oref_edge_k4(i32 n, const i64 *rp, const i32 *col, i64 nq, const i64 *slots, i64 *ek4)
+{
+    if (n < 0 || (n > 0 && (!rp || !col)) || !ek4) return ORACLE_EINVAL;
+    if (n == 0) return ORACLE_OK;
+    const i64 nnz = rp[n];
+    if (!slots) nq = nnz;
+    for (i64 q = 0; slots && q < nq; q++) if (slots[q] < 0 || slots[q] >= nnz) return ORACLE_EINVAL;
+    int err = 0;
+#pragma omp parallel
+    {
+        unsigned char *inw = (unsigned char *)calloc((size_t)n, 1);
+        i32 *w = (i32 *)malloc(sizeof(i32) * (size_t)n);
+        if (!inw || !w) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+#pragma omp for schedule(dynamic, 16)
+            for (i64 q = 0; q < nq; q++) {
+                i64 s = slots ? slots[q] : q;
+                /* the row a that holds slot s */
+                i64 lo = 0, hi = n;
+                while (hi - lo > 1) {
+                    i64 mid = (lo + hi) / 2;
+                    if (rp[mid] <= s) lo = mid; else hi = mid;
+                }
+                i32 a = (i32)lo, b = col[s];
+                /* W = N(a) and N(b) by a sorted merge */
+                i64 nw = 0, i = rp[a], j = rp[b];
+                while (i < rp[a + 1] && j < rp[b + 1]) {
+                    if (col[i] < col[j]) i++;
+                    else if (col[i] > col[j]) j++;
+                    else { w[nw++] = col[i]; i++; j++; }
+                }
+                for (i64 k = 0; k < nw; k++) inw[w[k]] = 1;
+                i64 ends = 0;   /* each edge inside W is seen from both ends */
+                for (i64 k = 0; k < nw; k++)
+                    for (i64 r = rp[w[k]]; r < rp[w[k] + 1]; r++) ends += inw[col[r]];
+                for (i64 k = 0; k < nw; k++) inw[w[k]] = 0;
+                ek4[q] = ends / 2;
+            }
+        }
+        free(inw);
+        free(w);
+    }
+    return err ? ORACLE_ENOMEM : ORACLE_OK;
 }

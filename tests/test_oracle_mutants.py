@@ -30,11 +30,12 @@ MUTANTS = {
     "psi6_plus_f13": [("i64 h8 = fv[F13_14] + fv[F8_12], h6 = fv[F6_9] - fv[F13_14];",
                        "i64 h8 = fv[F13_14] + fv[F8_12], h6 = fv[F6_9] + fv[F13_14];")],
     "stage1_merge_skips": [("else { c++; i++; j++; }", "else { c++; i += 2; j++; }")],
-    # Algorithm 2 read literally: neigh filled across all y of one x
-    "alg2_neigh_not_reset": [
-        ("for (i64 s = rp[x]; s < rp[x + 1]; s++) inx[col[s]] = 1;\n",
-         "for (i64 s = rp[x]; s < rp[x + 1]; s++) inx[col[s]] = 1;\n                i64 len = 0;\n"),
-        ("                    i64 len = 0;\n", "")],
+    # Stage II: triangles inside N(x) found from both orders of their last two
+    # vertices, or without checking that the third vertex closes the triangle
+    "k4_third_vertex_unordered": [("if (c > b && inx[c] && ina[c]) cliques++;",
+                                   "if (c != a && inx[c] && ina[c]) cliques++;")],
+    "k4_third_vertex_not_adjacent": [("if (c > b && inx[c] && ina[c]) cliques++;",
+                                      "if (c > b && inx[c]) cliques++;")],
     # paths x - y - z that run back to x
     "paths_return_to_x": [("if (z == x || sc->tx[z] >= 0) continue;", "if (sc->tx[z] >= 0) continue;", -1)],
     # paths whose far end is a neighbour of x (the second, summing pass only)
