@@ -9,12 +9,17 @@ timed region starts, outputs stay there.
 
 Prints one JSON line.  `value` is the plain form on the workload; `forms` adds
 the degree-binned and MLP-binned forms (on the workload and on R-MAT scale 22)
-and the batched form (50,000 small graphs, hipGraph-captured, autotuned).
+and the batched form (50,000 small graphs, hipGraph-captured, with the tuned
+knobs of paper_2606_29651_amd/tuning.txt; --retune searches them again), next to
+the plain form on the same graphs counted as one disjoint union.
 `roofline` is for the dominant kernel of the timed steps: its algorithmic bytes
 (the CSR words and row metadata the method itself must read for the work units
 that launch processed, reported by the library's work classes) over its HIP-event
-duration on the launching stream.  `cpu_baseline` times the CPU oracle on a
-bounded random vertex sample and scales it to the whole graph.
+duration on the launching stream, against 8 TB/s and against the copy bandwidth
+measured in the same run.  `cpu_baseline` times the CPU oracle's three stages:
+Stage I over the whole graph, Stages II and III on a bounded random vertex sample
+scaled to all vertices; it also holds the complete three-stage run on the tiny
+Erdos-Renyi configuration on all cores and on one.
 """
 from __future__ import annotations
 
@@ -30,7 +35,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TUNE_FILE = os.path.join(ROOT, "paper_2606_29651_amd", "tuning.json")
+TUNE_FILE = os.path.join(ROOT, "paper_2606_29651_amd", "tuning.txt")
+# The paper's own figure for its method (multicore CPU; no absolute rates are printed).
+PAPER_CONTEXT = ("NI-ORCA reports up to 30x over sequential orbit counters (EVOKE, ORCA, JESSE, CORA) at 32-64 "
+                 "threads on 2x AMD EPYC 7713 (128 cores) and 2x Intel Xeon Gold 6438Y+ (64 cores), eight "
+                 "real-world graphs of 12.5k-16.5M edges; not comparable with this machine or these graphs")
 
 
 def log(msg):
@@ -157,6 +166,16 @@ def traffic_for(workload, kernel):
     return rows.get(kernel)
 
 
+def git_rev():
+    """HEAD of the checkout bench.py runs from, or None where there is no .git."""
+    import subprocess
+    try:
+        r = subprocess.run(["git", "rev-parse", "HEAD"], cwd=ROOT, capture_output=True, text=True, timeout=10)
+        return r.stdout.strip() or None if r.returncode == 0 else None
+    except (OSError, subprocess.SubprocessError):
+        return None
+
+
 def kernel_bytes(kernel, stats):
     cnt, work, slots = stats[KERNEL_CLASS[kernel]]
     if kernel.startswith("probe"):
@@ -182,26 +201,59 @@ def time_count(ni, ctx, rp, cl, out, flags, steps, warmup):
     return ms, avg_s, avg_k
 
 
-def cpu_baseline(g, budget_s: float = 15.0, seed: int = 7):
-    """Time the CPU oracle (per-vertex entry) on a random vertex sample."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(g, budget_s: float = 15.0, seed: int = 7, seed_tiny: int = 42):
+    """The CPU oracle's three stages on the same graph: Stage I (oracle.stage1) over
+    every edge, then Stages II and III (oracle.stage23_at) on uniformly drawn vertices
+    until about budget_s seconds have passed, scaled by n / sample.  Also the full
+    three-stage oracle.count on the tiny Erdos-Renyi configuration, all threads and one."""
     import oracle
+    import graphgen as gg
     oracle.build(force=False)
-    rng = np.random.default_rng(seed)
-    n = g.n
     threads = oracle.num_threads()
-    done, elapsed, batch = 0, 0.0, 16
-    order = rng.permutation(n).astype(np.int32)
-    while elapsed < budget_s and done < n:
+    t0 = time.perf_counter()
+    tri = oracle.stage1(g.row_ptr, g.col)
+    s1 = time.perf_counter() - t0
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(g.n).astype(np.int32)
+    done, s23, batch = 0, 0.0, 64
+    while s23 < budget_s and done < g.n:
         xs = order[done: done + batch]
         t0 = time.perf_counter()
-        oracle.orbits_at(g.row_ptr, g.col, xs)
-        elapsed += time.perf_counter() - t0
+        oracle.stage23_at(g.row_ptr, g.col, tri, xs)
+        s23 += time.perf_counter() - t0
         done += len(xs)
-        batch = min(batch * 2, 4096)
-    full_s = elapsed * n / max(done, 1)
+        batch = min(batch * 2, 1 << 16)
+    del tri
+    full_s = s1 + s23 * g.n / max(done, 1)
+    tiny = gg.config_graph("er_tiny", seed=seed_tiny)
+    tiny_rate = {}
+    for t in (threads, 1):
+        oracle.set_threads(t)
+        best = None
+        for _ in range(3):
+            t0 = time.perf_counter()
+            oracle.count(tiny.row_ptr, tiny.col)
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        tiny_rate[f"threads_{t}"] = tiny.m / best
+    oracle.set_threads(threads)
     return {"value": g.m / full_s, "unit": "edges/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} uniformly drawn vertices of the same graph timed in {elapsed:.1f} s "
-                      f"with oracle.orbits_at (per-vertex paper method), scaled by n/{done}"}
+            "sample": f"Stage I (sorted merges) over all {g.m} edges in {s1:.1f} s; Stages II and III on {done} "
+                      f"uniformly drawn vertices in {s23:.1f} s, scaled by n/{done}",
+            "cpu_model": cpu_model(),
+            "er_tiny_full_edges_per_s": {k: round(v, 1) for k, v in tiny_rate.items()},
+            "paper": PAPER_CONTEXT}
 
 
 def stage1_work(c):
@@ -313,61 +365,86 @@ def forms(args, ni, ctx, g, rp, cl, out, base_ms):
                      "plain_stage_ms": {k: round(v, 3) for k, v in pl_st.items()}}
     del rrp, rcl, rout, rref
     torch.cuda.empty_cache()
-    # batched: 50,000 small graphs, autotuned parameters, captured hipGraph
+    # batched: 50,000 small graphs, tuned knobs, captured hipGraph
     t0 = time.time()
     graphs = gg.batch_mix(args.batch_graphs, 20, 2000, seed=args.seed)
     vtx_off, brp, bcol = gg.pack_batch(graphs)
     bm = int(brp[-1] // 2)
     log(f"[bench] batch of {len(graphs)} graphs, n={vtx_off[-1]} m={bm} in {time.time() - t0:.1f}s")
-    # tune on a tenth of the batch
-    sub = graphs[: max(1, len(graphs) // 10)]
-    s_off, s_rp, s_col = gg.pack_batch(sub)
-    d_srp, d_scol = torch.from_numpy(s_rp).cuda(), torch.from_numpy(s_col).cuda()
-    s_out = torch.empty((int(s_off[-1]), 15), dtype=torch.int64, device="cuda")
     tctx = ni.Context(0)
-    cands = autotune.grid(heavy_k=[0, 4096, 32768], tri_wave=[32, 64], qh_wave=[256, 512, 1024], ql_wave=[256, 512])
-    tuned = autotune.tune(tctx, lambda: ni.count_batched(s_off, d_srp, d_scol, out=s_out, ctx=tctx), cands,
-                          repeats=2)
-    autotune.save(TUNE_FILE, "batch_mix", {"best": tuned["best"], "ms_on_tenth": tuned["ms"]})
-    del d_srp, d_scol, s_out
+    if args.retune or not autotune.load(TUNE_FILE, "batch_mix"):
+        # tune on a seeded random tenth of the batch
+        pick = np.sort(np.random.default_rng(args.seed + 1).choice(len(graphs), max(1, len(graphs) // 10),
+                                                                    replace=False))
+        s_off, s_rp, s_col = gg.pack_batch([graphs[i] for i in pick])
+        d_srp, d_scol = torch.from_numpy(s_rp).cuda(), torch.from_numpy(s_col).cuda()
+        s_out = torch.empty((int(s_off[-1]), 15), dtype=torch.int64, device="cuda")
+        cands = autotune.grid(heavy_k=[0, 4096, 32768], tri_wave=[32, 64], qh_wave=[256, 512, 1024],
+                              ql_wave=[256, 512])
+        tuned = autotune.tune(tctx, lambda: ni.count_batched(s_off, d_srp, d_scol, out=s_out, ctx=tctx), cands,
+                              repeats=3)
+        autotune.save(TUNE_FILE, "batch_mix", tuned["best"],
+                      note=f"fastest of {len(cands)} on a random tenth of the batch, {tuned['ms']:.2f} ms")
+        del d_srp, d_scol, s_out
+    tctx.load_tuning(TUNE_FILE, "batch_mix")
+    knobs = autotune.load(TUNE_FILE, "batch_mix")
     d_brp, d_bcol = torch.from_numpy(brp).cuda(), torch.from_numpy(bcol).cuda()
     b_out = torch.empty((int(vtx_off[-1]), 15), dtype=torch.int64, device="cuda")
     stream = torch.cuda.Stream()
     ni.count_batched(vtx_off, d_brp, d_bcol, out=b_out, ctx=tctx, stream=stream, flags=ni.GRAPH_CAPTURE)
     stream.synchronize()
-    reps = 3
+    reps = 5
     t1 = time.perf_counter()
     for _ in range(reps):
         ni.count_batched(vtx_off, d_brp, d_bcol, out=b_out, ctx=tctx, stream=stream, flags=ni.GRAPH_CAPTURE)
     stream.synchronize()
     b_ms = 1000.0 * (time.perf_counter() - t1) / reps
-    # the same batch through the plain per-call path (no capture) for comparison
     b_ref = b_out.clone()
+    # the same launch sequence uncaptured
     t1 = time.perf_counter()
     ni.count_batched(vtx_off, d_brp, d_bcol, out=b_out, ctx=tctx, stream=stream)
     stream.synchronize()
     nb_ms = 1000.0 * (time.perf_counter() - t1)
-    res["batch_mix"] = {"graphs": len(graphs), "n": int(vtx_off[-1]), "m": bm, "captured_ms": b_ms,
-                        "value": bm / (b_ms * 1e-3), "uncaptured_ms": nb_ms,
-                        "identical": bool(torch.equal(b_out, b_ref)), "tuned": tuned["best"]}
+    same = bool(torch.equal(b_out, b_ref))
     tctx.close()
+    # the plain form on the same graphs: niorca_count of their disjoint union (global ids)
+    u_col = torch.from_numpy(bcol).cuda()
+    u_col += torch.repeat_interleave(torch.from_numpy(vtx_off[:-1]).cuda().to(torch.int32),
+                                     torch.from_numpy(np.diff(brp[vtx_off])).cuda())
+    pctx = ni.Context(0)
+    p_ms, _, _ = time_count(ni, pctx, d_brp, u_col, b_out, 0, reps, 1)
+    same = same and bool(torch.equal(b_out, b_ref))
+    pctx.close()
+    res["batch_mix"] = {"graphs": len(graphs), "n": int(vtx_off[-1]), "m": bm, "captured_ms": b_ms,
+                        "value": bm / (b_ms * 1e-3), "uncaptured_ms": nb_ms, "plain_union_ms": p_ms,
+                        "plain_union_value": bm / (p_ms * 1e-3), "identical": same, "tuned": knobs}
+    del d_brp, d_bcol, b_out, b_ref, u_col
+    torch.cuda.empty_cache()
     return res
 
 
-def copy_calibration(mib):
-    """A copy kernel of known traffic: 4 B read and 4 B written per element."""
+def copy_bandwidth(mib=1024, reps=10):
+    """GB/s of a plain device copy (4 B read and 4 B written per element), timed with
+    events on torch's stream."""
     import torch
     n = mib * (1 << 20) // 4
     src = torch.arange(n, dtype=torch.int32, device="cuda")
     dst = torch.empty(n, dtype=torch.float32, device="cuda")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(5):
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
         dst.copy_(src)
-    torch.cuda.synchronize()
-    ms = 1000.0 * (time.perf_counter() - t0) / 5
-    print(json.dumps({"copy_calibration": {"elements": n, "read_bytes": 4 * n, "write_bytes": 4 * n,
-                                           "ms": ms, "GBps": 8 * n / (ms * 1e-3) / 1e9}}))
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return {"elements": n, "read_bytes": 4 * n, "write_bytes": 4 * n, "ms": ms, "GBps": 8 * n / (ms * 1e-3) / 1e9}
+
+
+def copy_calibration(mib):
+    """A copy kernel of known traffic: 4 B read and 4 B written per element."""
+    print(json.dumps({"copy_calibration": copy_bandwidth(mib, 5)}))
 
 
 def main():
@@ -381,6 +458,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="all", choices=["all", "none"])
     ap.add_argument("--batch-graphs", type=int, default=50000)
+    ap.add_argument("--retune", action="store_true",
+                    help="search the batched form's knobs again and rewrite paper_2606_29651_amd/tuning.txt")
     ap.add_argument("--er-series", default="default", choices=["default", "full", "none"],
                     help="Erdos-Renyi points timed with the forms: n = 4M at average degree 8, 16, 32 "
                          "(default), all of n in {1,2,4,8,16}M x degree {8,16,32} (full), or none")
@@ -426,8 +505,11 @@ def main():
     log("[bench] stage ms " + json.dumps({k: round(v, 3) for k, v in stage_ms.items()}))
     log("[bench] kernel ms " + json.dumps({k: round(v, 3) for k, v in kernel_ms.items()}))
     dom, bytes_dom, ach = roofline_of(kernel_ms, stats)
+    cb = copy_bandwidth()
+    log(f"[bench] copy bandwidth {cb['GBps']:.0f} GB/s")
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_for(args.workload, dom),
+            "copy_GBps": round(cb["GBps"], 1), "frac_of_copy": round(ach / cb["GBps"], 4),
             "kernel_ms": round(kernel_ms[dom], 4), "algorithmic_bytes": int(bytes_dom),
             "units": {"class": KERNEL_CLASS[dom], "items": stats[KERNEL_CLASS[dom]][0],
                       "work": stats[KERNEL_CLASS[dom]][1], "slots": stats[KERNEL_CLASS[dom]][2]}}
@@ -444,7 +526,8 @@ def main():
         "vs_baseline": None,
         "dtype": "int64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": g.n, "m": g.m, "form": "plain", "seed": args.seed},
+        "config": {"workload": args.workload, "n": g.n, "m": g.m, "form": "plain", "seed": args.seed,
+                   "csr_sha256": g.sha256(), "source_digest": source_digest(), "git_rev": git_rev()},
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "kernel_ms": {k: round(v, 4) for k, v in kernel_ms.items()},
         "roofline": roof,

@@ -29,6 +29,16 @@
  *     (they share its workspace).  Different contexts are independent.
  *   - Errors: every entry point returns a niorca_status; on failure nothing has
  *     been enqueued unless stated, and niorca_last_error() describes the cause.
+ *   - Malformed input: row bounds outside [0, nnz] and column ids outside [0, n)
+ *     are detected on the device and never lead to a read or write outside the
+ *     buffers (niorca_count refuses them with EINVAL; calls that do not wait report
+ *     them through niorca_device_status).  The other preconditions (rows sorted,
+ *     no duplicate, no self-loop, symmetric) are not checked unless NIORCA_VALIDATE
+ *     is given; a graph violating them gets meaningless counts.
+ *   - Size limits: n < 2^31, nnz < 2^31 (ENOTIMPL above), and every vertex has at
+ *     most 16384 neighbours of higher degree rank |N+(v)| (ENOTIMPL above; a
+ *     simple graph reaches it only with more than 1.3e8 edges, since |N+(v)| is at
+ *     most sqrt(2|E|)).
  */
 #ifndef NIORCA_H
 #define NIORCA_H
@@ -56,6 +66,7 @@ typedef enum {
 #define NIORCA_BIN_MLP    0x4u  /* Stage I work classes from the loaded work model (niorca_set_cost_model) */
 #define NIORCA_COUNTERS   0x8u  /* record per-vertex work counters (niorca_work_counters) */
 #define NIORCA_TIMING     0x10u /* record HIP events between stages (niorca_stage_times) */
+#define NIORCA_INDUCED    0x20u /* write the induced counts psi'_k instead (see niorca_count) */
 
 typedef struct niorca_ctx niorca_ctx;
 
@@ -93,6 +104,9 @@ uint64_t niorca_workspace_bytes(const niorca_ctx *ctx);
  *   "heavy_k"   -1..32768 how many top-ranked vertices form the heavy range; -1
  *                        (default): 32768 when the maximum degree exceeds 8x the
  *                        mean degree, else 0; 4096 in niorca_count_batched
+ *   "bin_mode"  0..2     work binning of calls whose flags ask for none, including the
+ *                        intermediate entry points: 0 capacity only (default), 1 as
+ *                        NIORCA_BIN_DEGREE, 2 as NIORCA_BIN_MLP (needs a cost model)
  *   "bin_deg_thread" (NIORCA_BIN_DEGREE) degree up to which a vertex with |N+| <= 8
  *               goes to the one-lane Stage I class (default 16)
  *   "bin_deg_group"  (NIORCA_BIN_DEGREE) degree up to which a vertex with |N+| <= 16
@@ -116,9 +130,18 @@ niorca_status niorca_set_param(niorca_ctx *ctx, const char *name, int64_t value)
  *   row_ptr  device int64[n+1]; col device int32[nnz] (see conventions)
  *   out      device int64[n*15], row-major: out[x*15 + k] = psi_k(x)
  *   flags    NIORCA_* bits
+ * With NIORCA_INDUCED, out[x*15 + k] = psi'_k(x) instead: the counts of induced
+ * graphlets (Section 3, Definition 2: one occurrence per connected vertex set S,
+ * the subgraph of all edges inside S), same numbering.  They follow from the
+ * non-induced counts of the same vertex by the triangular system relating them
+ * (the section on ORCA and NI-ORCA prints three of its equations, e.g.
+ * psi'_13 = f13_14 / 2 - 3 psi_14).
  * Waits once on `stream` to read a few graph statistics (degree maximum, work
  * class sizes) that size the launches and the overflow check; everything after
- * that is enqueued without waiting. */
+ * that is enqueued without waiting.  With NIORCA_VALIDATE it also waits at the end
+ * and returns EINTERNAL if the device's evenness check of the halved equations
+ * (Section 5: every halving is exact) failed; otherwise niorca_device_status
+ * reports that check. */
 niorca_status niorca_count(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
                            const int32_t *col, int64_t *out, void *stream, uint32_t flags);
 
@@ -128,12 +151,16 @@ niorca_status niorca_count(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_
  * int64[total_n*15] in packed vertex order.  vtx_off is a HOST int64[num_graphs+1]
  * array with vtx_off[0] = 0; each graph has at most 16385 vertices.
  * The batch is counted as one disjoint union, one launch sequence for all graphs,
- * with launch sizes taken from host-known bounds, so nothing waits on the device.
- * With NIORCA_GRAPH_CAPTURE (non-null stream; not with VALIDATE or TIMING) that
- * sequence is captured once into a hipGraph and replayed by later calls of the same
- * shape (sizes, buffers, vtx_off and tuning parameters).  Bad ids inside the packed
- * CSR give wrong counts, never an out-of-bounds access; NIORCA_VALIDATE checks them
- * (and waits). */
+ * with launch sizes taken from host-known bounds (no row longer than the largest
+ * graph's n - 1), so nothing waits on the device.  NIORCA_INDUCED as for
+ * niorca_count.  With NIORCA_GRAPH_CAPTURE (non-null stream; not with VALIDATE or
+ * TIMING) that sequence is captured once into a hipGraph and replayed by later calls
+ * of the same shape (sizes, buffers, vtx_off, flags and tuning parameters).  A row
+ * longer than the bound, a row bound outside [0, nnz] or a column id outside its
+ * graph is refused on the device (that vertex is counted as isolated, nothing
+ * outside the buffers is touched) and reported by niorca_device_status; unsorted,
+ * duplicated or asymmetric rows give meaningless counts.  NIORCA_VALIDATE checks
+ * the whole precondition first (and waits). */
 #define NIORCA_GRAPH_CAPTURE 0x100u
 niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graphs, const int64_t *vtx_off, int64_t nnz,
                                    const int64_t *row_ptr, const int32_t *col, int64_t *out,
@@ -150,10 +177,31 @@ niorca_status niorca_edge_triangles(niorca_ctx *ctx, int32_t n, int64_t nnz, con
 niorca_status niorca_k4(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
                         const int32_t *col, int64_t *k4, void *stream);
 
+/* Per-edge Stage II: k4e[s] = number of 4-cliques containing both ends of the edge
+ * in input CSR slot s (Algorithm 2 finds each 4-clique once; here it is credited to
+ * its six edges).  These per-edge counts, with tri of niorca_edge_triangles, are
+ * the per-edge inputs 5-vertex methods start from (Section 3, complexity of the
+ * 4- and 5-vertex counts).  k4e is device int64[nnz], written completely. */
+niorca_status niorca_edge_k4(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
+                             const int32_t *col, int64_t *k4e, void *stream);
+
 /* Stage III-a: the nine f-variables of Table 1 per vertex, device int64[n*9] in the
  * order f12_14, f10_13, f13_14, f11_13, f5_8, f6_9, f9_12, f4_8, f8_12. */
 niorca_status niorca_fvars(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
                            const int32_t *col, int64_t *fvars, void *stream);
+
+/* Waits on `stream` for the last call on this context and reports what its kernels
+ * flagged: EINVAL if a row bound, a column id or a row length was outside the graph
+ * or its bound (the vertex was counted as isolated), EINTERNAL if a halved equation
+ * had an odd numerator (Section 5 says every halving is exact, so this means a
+ * fault), OK otherwise (also when nothing was counted yet). */
+niorca_status niorca_device_status(niorca_ctx *ctx, void *stream);
+
+/* Applies the knobs stored under `key` in a tuning file through niorca_set_param.
+ * The file is text, one "key name value" triple per line ('#' starts a comment), as
+ * the package's autotuner writes it.  EINVAL if the file cannot be read, holds no
+ * line for `key`, or a value is out of range (lines before it stay applied). */
+niorca_status niorca_load_tuning(niorca_ctx *ctx, const char *path, const char *key);
 
 /* Durations in ms, measured with HIP events on the call's stream, of the stages of
  * the last niorca_count made with NIORCA_TIMING; waits for that call to finish.

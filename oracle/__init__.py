@@ -33,9 +33,10 @@ F_NAMES = ["f12_14", "f10_13", "f13_14", "f11_13", "f5_8", "f6_9", "f9_12", "f4_
 
 
 def build(force: bool = True) -> str:
-    """Compile the C oracle (gcc -O2 -fopenmp) and return the library path."""
+    """Compile the C oracle (gcc -O2 -fopenmp) and return the library path (also
+    when the library is older than its source)."""
     global _lib
-    if force or not os.path.exists(_LIB):
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_SRC) > os.path.getmtime(_LIB):
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
                "-Wno-unused-function", "-o", tmp, _SRC]
@@ -58,6 +59,7 @@ def _load():
         lib.oref_cycles4_total.argtypes = [i32, P, P, P]
         lib.oref_k4_total.argtypes = [i32, P, P, P]
         lib.oref_edge_k4.argtypes = [i32, P, P, i64, P, P]
+        lib.oref_stage23_at.argtypes = [i32, P, P, P, i32, P, P]
         lib.oref_stage1.argtypes = [i32, P, P, P]
         lib.oref_stage2.argtypes = [i32, P, P, P]
         lib.oref_stage3.argtypes = [i32, P, P, P, P, P, P]
@@ -67,7 +69,7 @@ def _load():
         lib.oref_num_threads.restype = ctypes.c_int
         for name in ("oref_enum_count", "oref_stage1", "oref_stage2", "oref_stage3",
                      "oref_count", "oref_orbits_at", "oref_enum_induced", "oref_cycles4_total",
-                     "oref_k4_total", "oref_edge_k4"):
+                     "oref_k4_total", "oref_edge_k4", "oref_stage23_at"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -188,6 +190,18 @@ def count_with_intermediates(row_ptr, col):
     k4 = stage2(row_ptr, col)
     psi, fv = stage3(row_ptr, col, tri, k4, want_fvars=True)
     return psi, tri, k4, fv
+
+
+def stage23_at(row_ptr, col, tri, xs) -> np.ndarray:
+    """psi int64[len(xs), 15] of selected vertices from the whole graph's Stage I
+    counts tri (stage1): Stage II and Stage III for those vertices only."""
+    n, rp, cl = _csr(row_ptr, col)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    xs = np.ascontiguousarray(xs, dtype=np.int32)
+    psi = np.zeros((xs.shape[0], 15), dtype=np.int64)
+    _check(_load().oref_stage23_at(n, _ptr(rp), _ptr(cl), _ptr(tri), xs.shape[0], _ptr(xs), _ptr(psi)),
+           "stage23_at")
+    return psi
 
 
 def orbits_at(row_ptr, col, xs, want_fvars: bool = False):

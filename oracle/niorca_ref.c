@@ -837,3 +837,56 @@ int oref_edge_k4(i32 n, const i64 *rp, const i32 *col, i64 nq, const i64 *slots,
     }
     return err ? ORACLE_ENOMEM : ORACLE_OK;
 }
+
+/* Stages II and III for selected vertices, given the Stage I counts of the whole
+ * graph (tri from oref_stage1): K4 of each x counted as in oref_stage2, then the
+ * Stage III probe and equations of oref_stage3.  Used to time the three stages on
+ * a vertex sample of a graph too large for a full run; psi int64[nq*15]. */
+int oref_stage23_at(i32 n, const i64 *rp, const i32 *col, const i32 *tri, i32 nq, const i32 *xs,
+                    i64 *psi)
+{
+    if (n < 0 || nq < 0 || (nq > 0 && (!rp || !col || !tri || !xs || !psi))) return ORACLE_EINVAL;
+    for (i32 q = 0; q < nq; q++) if (xs[q] < 0 || xs[q] >= n) return ORACLE_EINVAL;
+    if (nq == 0) return ORACLE_OK;
+    int err = 0;
+#pragma omp parallel
+    {
+        scratch_t sc;
+        unsigned char *inx = (unsigned char *)calloc((size_t)n, 1);
+        unsigned char *ina = (unsigned char *)calloc((size_t)n, 1);
+        if (scratch_init(&sc, n, 0) != 0 || !inx || !ina) {
+#pragma omp atomic write
+            err = ORACLE_ENOMEM;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (i32 q = 0; q < nq; q++) {
+                i32 x = xs[q];
+                i64 cliques = 0;
+                for (i64 s = rp[x]; s < rp[x + 1]; s++) inx[col[s]] = 1;
+                for (i64 s = rp[x]; s < rp[x + 1]; s++) {
+                    i32 a = col[s];
+                    for (i64 r = rp[a]; r < rp[a + 1]; r++) ina[col[r]] = 1;
+                    for (i64 r = rp[a]; r < rp[a + 1]; r++) {
+                        i32 b = col[r];
+                        if (b <= a || !inx[b]) continue;
+                        for (i64 u = rp[b]; u < rp[b + 1]; u++) {
+                            i32 c = col[u];
+                            if (c > b && inx[c] && ina[c]) cliques++;
+                        }
+                    }
+                    for (i64 r = rp[a]; r < rp[a + 1]; r++) ina[col[r]] = 0;
+                }
+                for (i64 s = rp[x]; s < rp[x + 1]; s++) inx[col[s]] = 0;
+                int e = stage3_vertex(rp, col, tri, cliques, x, &sc, psi + (i64)q * 15, NULL);
+                if (e) {
+#pragma omp atomic write
+                    err = e;
+                }
+            }
+        }
+        scratch_free(&sc);
+        free(inx);
+        free(ina);
+    }
+    return err;
+}

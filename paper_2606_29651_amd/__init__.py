@@ -6,7 +6,9 @@ are torch CUDA (HIP) tensors; the library is called on torch's current stream.
 There is no CPU path: if the library or a GPU is missing, calls raise.
 
     count(row_ptr, col)          -> int64[n, 15]   psi_k(x), k = 0..14
+    count(..., flags=INDUCED)    -> int64[n, 15]   induced counts psi'_k(x)
     edge_triangles(row_ptr, col) -> int32[nnz]     Stage I, per input CSR slot
+    edge_k4(row_ptr, col)        -> int64[nnz]     4-cliques through each edge
     k4(row_ptr, col)             -> int64[n]       Stage II
     fvars(row_ptr, col)          -> int64[n, 9]    Stage III-a (Table 1 order)
 """
@@ -23,7 +25,7 @@ LIB_PATH = os.path.join(HERE, "libniorca.so")
 
 OK, EINVAL, ENOTSIMPLE, EOVERFLOW, ENOMEM, EDEVICE, ENOTIMPL, EINTERNAL = range(8)
 STATUS_NAMES = ["OK", "EINVAL", "ENOTSIMPLE", "EOVERFLOW", "ENOMEM", "EDEVICE", "ENOTIMPL", "EINTERNAL"]
-VALIDATE, BIN_DEGREE, BIN_MLP, COUNTERS, TIMING = 0x1, 0x2, 0x4, 0x8, 0x10
+VALIDATE, BIN_DEGREE, BIN_MLP, COUNTERS, TIMING, INDUCED = 0x1, 0x2, 0x4, 0x8, 0x10, 0x20
 GRAPH_CAPTURE = 0x100
 F_NAMES = ["f12_14", "f10_13", "f13_14", "f11_13", "f5_8", "f6_9", "f9_12", "f4_8", "f8_12"]
 
@@ -32,7 +34,8 @@ EXPORTS = ["niorca_create", "niorca_destroy", "niorca_last_error", "niorca_set_w
            "niorca_workspace_bytes", "niorca_set_param", "niorca_count", "niorca_count_batched",
            "niorca_edge_triangles", "niorca_k4", "niorca_fvars", "niorca_work_counters",
            "niorca_set_cost_model", "niorca_stage_times", "niorca_last_features", "niorca_mlp_train",
-           "niorca_mlp_predict", "niorca_kernel_times", "niorca_class_stats"]
+           "niorca_mlp_predict", "niorca_kernel_times", "niorca_class_stats", "niorca_edge_k4",
+           "niorca_device_status", "niorca_load_tuning"]
 KERNEL_NAMES = ["probe_thread", "probe_wave", "probe_block", "probe_large", "ql_wave", "ql_block", "ql_global",
                 "qh_wave", "qh_block", "qh_dense", "qh_global", "probe_group"]
 CLASS_NAMES = ["tri_wave", "tri_thread", "tri_block", "tri_large", "ql_wave", "ql_block", "ql_global",
@@ -76,6 +79,9 @@ def load_library():
         lib.niorca_count_batched.argtypes = [P, i32, P, i64, P, P, P, P, u32]
         lib.niorca_edge_triangles.argtypes = [P, i32, i64, P, P, P, P]
         lib.niorca_k4.argtypes = [P, i32, i64, P, P, P, P]
+        lib.niorca_edge_k4.argtypes = [P, i32, i64, P, P, P, P]
+        lib.niorca_device_status.argtypes = [P, P]
+        lib.niorca_load_tuning.argtypes = [P, ctypes.c_char_p, ctypes.c_char_p]
         lib.niorca_fvars.argtypes = [P, i32, i64, P, P, P, P]
         lib.niorca_work_counters.argtypes = [P, i32, P, P]
         lib.niorca_set_cost_model.argtypes = [P, P, i32, ctypes.c_float, ctypes.c_float, ctypes.c_float]
@@ -123,6 +129,15 @@ class Context:
 
     def set_param(self, name: str, value: int):
         self.check(self.lib.niorca_set_param(self.h, name.encode(), int(value)), f"set_param({name})")
+
+    def load_tuning(self, path: str, key: str):
+        """Apply the knobs stored under key in a tuning file (niorca_load_tuning)."""
+        self.check(self.lib.niorca_load_tuning(self.h, path.encode(), key.encode()), f"load_tuning({key})")
+
+    def device_status(self, stream=None):
+        """Wait for the last call on this context and raise if its kernels flagged bad
+        input rows or an odd halved numerator (niorca_device_status)."""
+        self.check(self.lib.niorca_device_status(self.h, _stream_ptr(stream)), "niorca_device_status")
 
     def set_workspace_limit(self, nbytes: int):
         self.check(self.lib.niorca_set_workspace_limit(self.h, int(nbytes)), "set_workspace_limit")
@@ -212,6 +227,16 @@ def k4(row_ptr, col, ctx: Context = None, stream=None) -> torch.Tensor:
     ctx = ctx or context(row_ptr.device.index)
     out = torch.empty(n, dtype=torch.int64, device=row_ptr.device)
     ctx.check(ctx.lib.niorca_k4(ctx.h, n, nnz, _p(row_ptr), _p(col), _p(out), _stream_ptr(stream)), "niorca_k4")
+    return out
+
+
+def edge_k4(row_ptr, col, ctx: Context = None, stream=None) -> torch.Tensor:
+    """int64[nnz]: the number of 4-cliques through the edge of each input CSR slot."""
+    row_ptr, col, n, nnz = _graph(row_ptr, col)
+    ctx = ctx or context(row_ptr.device.index)
+    out = torch.empty(nnz, dtype=torch.int64, device=row_ptr.device)
+    ctx.check(ctx.lib.niorca_edge_k4(ctx.h, n, nnz, _p(row_ptr), _p(col), _p(out), _stream_ptr(stream)),
+              "niorca_edge_k4")
     return out
 
 

@@ -2,15 +2,15 @@
 range) of niorca_count / niorca_count_batched.
 
 A tuning run times each candidate parameter set on a representative workload
-(median of a few calls, HIP events inside the library) and keeps the fastest.
-Results are stored as JSON keyed by a workload label, so a later run can load
-them instead of searching again.  Counts never depend on these parameters; only
-which kernel shape handles a vertex does.
+(median of a few calls) and keeps the fastest.  Results are stored in a text
+file of "key name value" lines keyed by a workload label, the format the library
+reads itself (niorca_load_tuning), so a later run loads them instead of searching
+again.  Counts never depend on these parameters; only which kernel shape handles a
+vertex does.
 """
 from __future__ import annotations
 
 import itertools
-import json
 import os
 import time
 from typing import Callable, Dict, Iterable, List
@@ -56,20 +56,28 @@ def tune(ctx, run: Callable[[], None], candidates: Iterable[Dict[str, int]], rep
     return {"best": best[0], "ms": best[1], "table": table}
 
 
-def save(path: str, key: str, result: Dict) -> None:
-    data = {}
+def save(path: str, key: str, params: Dict[str, int], note: str = "") -> None:
+    """Replace the lines of `key` in the tuning file with params (other keys stay)."""
+    keep = []
     if os.path.exists(path):
         with open(path) as f:
-            data = json.load(f)
-    data[key] = result
+            keep = [ln for ln in f if not (ln.split() and ln.split()[0] == key)]
+    lines = [f"{key} {name} {int(v)}" + (f"  # {note}" if note and i == 0 else "") + "\n"
+             for i, (name, v) in enumerate(sorted(params.items()))]
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
-        json.dump(data, f, indent=1, sort_keys=True)
+        f.writelines(keep + lines)
     os.replace(tmp, path)
 
 
 def load(path: str, key: str):
+    """{name: value} stored under key, or None."""
     if not os.path.exists(path):
         return None
+    out = {}
     with open(path) as f:
-        return json.load(f).get(key)
+        for ln in f:
+            p = ln.split("#")[0].split()
+            if len(p) == 3 and p[0] == key:
+                out[p[1]] = int(p[2])
+    return out or None

@@ -45,6 +45,7 @@ struct niorca_ctx {
     uint64_t gz_off = 0, gz_bytes = 0;
     int64_t tri_cache_records = (int64_t)1 << 32;  // at most 32 GiB of kept triangles for the tau pass
     int64_t large_lds_max = PL_LDS_MAX;            // LDS bytes the large probe kernel may take
+    int bin_default = 0;  // binning of calls whose flags ask for none: 0 none, 1 degree, 2 learned
 };
 
 static niorca_status fail(niorca_ctx *c, niorca_status s, const char *fmt, ...) {
@@ -180,6 +181,10 @@ extern "C" niorca_status niorca_set_param(niorca_ctx *ctx, const char *name, int
     } else if (k == "large_lds") {
         if (value < 0 || value > PL_LDS_MAX) return bad(0, PL_LDS_MAX);
         ctx->large_lds_max = value;
+    } else if (k == "bin_mode") {
+        if (value < 0 || value > 2) return bad(0, 2);
+        if (value == 2 && !ctx->mlp_dev) return fail(ctx, NIORCA_EINVAL, "bin_mode 2 needs a cost model");
+        ctx->bin_default = (int)value;
     } else if (k == "qh_block") {
         if (value < 0 || value > QH_BLOCK_HC / 2) return bad(0, QH_BLOCK_HC / 2);
         ctx->th.qh_block = value;
@@ -227,10 +232,12 @@ __global__ void k_validate(int32_t n, int64_t nnz, const int64_t *__restrict__ r
     if (flag) atomicOr(bad, 1);
 }
 
-// Stage I values in input slot order: t of input slot (x, a) from the relabelled layout.
-__global__ void k_tri_to_input(int32_t n, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
-                               const i32 *__restrict__ perm, DevGraph g, const i32 *__restrict__ t,
-                               int32_t *__restrict__ tri) {
+// Per-edge values in input slot order: the value of input slot (x, a) is kept on
+// the N+ slot of the edge in the relabelled layout (Stage I t, per-edge 4-cliques).
+template <typename T>
+__global__ void k_slot_to_input(int32_t n, const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                const i32 *__restrict__ perm, DevGraph g, const T *__restrict__ t,
+                                T *__restrict__ tri) {
     int waves = gridDim.x * (blockDim.x / WAVE);
     int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     for (int32_t x = wid; x < n; x += waves) {
@@ -280,7 +287,11 @@ struct Outputs {
     int64_t *fvars = nullptr;  // [n*9] input order
     int32_t *tri = nullptr;    // [nnz] input slot order
     int64_t *k4 = nullptr;     // [n] input order
+    int64_t *ek4 = nullptr;    // [nnz] input slot order: 4-cliques through each edge
 };
+
+// Internal flag of run(): Stage I/II also credits the 4-cliques through each edge.
+#define RUN_EDGE_K4 0x80000000u
 
 // Bounds the host already knows (batched calls): with them the pipeline needs no
 // wait on the device, so the whole sequence can be captured into a hipGraph.
@@ -310,7 +321,7 @@ static niorca_status check_graph_args(niorca_ctx *ctx, int32_t n, int64_t nnz, c
 struct Layout {
     uint64_t st, deg, val, k2, v2, hist, scan, perm, nrp, nsplit, hstart, lng, ncol, mirror, t, wl, wh, vmeta;
     uint64_t lists[WC_COUNT];
-    uint64_t acc, tcoff, tccnt, tcbump, tcrec, probes, feat, pred, counters;
+    uint64_t acc, tcoff, tccnt, tcbump, tcrec, probes, feat, pred, counters, ek4;
     uint64_t base_end;  // everything above needs no graph statistics
     uint64_t large, part, gcnt, colg, voff;
     uint64_t total;
@@ -336,10 +347,12 @@ static void layout_base(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz
     L.acc = A.take<i64>((uint64_t)n * 10);
     L.tcoff = A.take<i64>(n); L.tccnt = A.take<i32>(n); L.tcbump = A.take<u64>(1);
     L.probes = A.take<i64>(n);
-    const bool feats = (flags & (NIORCA_BIN_MLP | NIORCA_COUNTERS)) != 0;
+    const bool mlp = (flags & NIORCA_BIN_MLP) || (!(flags & NIORCA_BIN_DEGREE) && ctx->bin_default == 2);
+    const bool feats = mlp || (flags & NIORCA_COUNTERS);
     L.feat = feats ? A.take<float>((uint64_t)n * 6) : 0;
-    L.pred = (flags & NIORCA_BIN_MLP) ? A.take<float>(n) : 0;
+    L.pred = mlp ? A.take<float>(n) : 0;
     L.counters = (flags & NIORCA_COUNTERS) ? A.take<i64>((uint64_t)n * NUM_COUNTERS) : 0;
+    L.ek4 = (flags & RUN_EDGE_K4) ? A.take<i64>((uint64_t)nnz + 64) : 0;
     L.base_end = A.off;
 }
 
@@ -394,6 +407,16 @@ static hipError_t fill32(void *p, i64 bytes, u32 v, hipStream_t s) {
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_fill32, dim3((u32)blocks), dim3(256), 0, s, (u32 *)p, words, v);
     return hipGetLastError();
+}
+
+// A call that stopped after Stage I/II: its statistics (device_status) stay
+// readable, the counters and features of an earlier count do not.
+static void mark_partial(niorca_ctx *ctx, uint64_t st_off, char *W) {
+    ctx->last_stats_dev = st_off;
+    ctx->last_ws = W;
+    ctx->last_n = -1;
+    ctx->last_counters = 0;
+    ctx->last_feat = 0;
 }
 
 static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *rp, const int32_t *col,
@@ -456,7 +479,10 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     STAGE_MARK(0);
     HIP_TRY(fill32(dst, sizeof(GraphStats), 0u, s));
     // ---- a1: degrees and rank order (stable radix sort of degrees) ----
-    hipLaunchKernelGGL(k_degree, dim3(cu * 8), dim3(nthr), 0, s, n, (i64)nnz, rp, deg, val, dst);
+    // bounded runs size their per-row buffers from the host's degree bound: longer
+    // rows are refused by the degree pass (degree 0, bad_input)
+    const i64 dcap = hb ? (i64)hb->dmax : (i64)INT32_MAX;
+    hipLaunchKernelGGL(k_degree, dim3(cu * 8), dim3(nthr), 0, s, n, (i64)nnz, dcap, rp, deg, val, dst);
     HIP_TRY(hipGetLastError());
     int bits = 1;
     while (bits < 31 && ((int64_t)1 << bits) <= (int64_t)n) bits++;
@@ -516,7 +542,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
                        wh, probes, feat);
     HIP_TRY(hipGetLastError());
     Thresholds th = ctx->th;
-    th.bin_mode = (flags & NIORCA_BIN_MLP) ? 2 : ((flags & NIORCA_BIN_DEGREE) ? 1 : 0);
+    th.bin_mode = (flags & NIORCA_BIN_MLP) ? 2 : ((flags & NIORCA_BIN_DEGREE) ? 1 : ctx->bin_default);
     if (th.bin_mode == 2) {
         HIP_TRY(mlp_predict(n, feat, ctx->mlp_dev, pred, s));
         th.pred = pred;
@@ -550,19 +576,36 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
                      chunk_for((i64)cu * 2, 1 << 17, 1 << 18), chunk_for((i64)cu * 8 * 16, 256, 1 << 12)};
     HIP_TRY(fill32(tca.bump, sizeof(u64), 0u, s));
     STAGE_MARK(4);
+    if (o.ek4) {
+        // Stage I/II with the 4-cliques through every edge (on its N+ slot)
+        i64 *ek4 = (i64 *)(W + L.ek4);
+        HIP_TRY(fill32(ek4, sizeof(i64) * nnz, 0u, s));
+        HIP_TRY(launch_probe(2, g, lh, dst, t, acc.K4, ek4, tca, large_scratch, L.large_slice, L.large_cap,
+                             L.large_hc, L.large_blocks, ctx->large_lds_max, cu * 8, cu * 2, nullptr, nokev, s));
+        hipLaunchKernelGGL(k_slot_to_input<i64>, dim3(cu * 8), dim3(nthr), 0, s, n, rp, col, perm, g,
+                           (const i64 *)ek4, o.ek4);
+        HIP_TRY(hipGetLastError());
+        mark_partial(ctx, L.st, W);
+        return NIORCA_OK;
+    }
     HIP_TRY(launch_probe(0, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, L.large_slice, L.large_cap,
                          L.large_hc, L.large_blocks, ctx->large_lds_max, cu * 8, cu * 2, counters, kev, s));
     STAGE_MARK(5);
     if (o.tri) {
-        hipLaunchKernelGGL(k_tri_to_input, dim3(cu * 8), dim3(nthr), 0, s, n, rp, col, perm, g, t, o.tri);
+        hipLaunchKernelGGL(k_slot_to_input<i32>, dim3(cu * 8), dim3(nthr), 0, s, n, rp, col, perm, g,
+                           (const i32 *)t, (i32 *)o.tri);
         HIP_TRY(hipGetLastError());
     }
     if (o.k4 && !o.psi && !o.fvars) {
         hipLaunchKernelGGL(k_k4_to_input, dim3((n + nthr - 1) / nthr), dim3(nthr), 0, s, n, val, acc.K4, o.k4);
         HIP_TRY(hipGetLastError());
+        mark_partial(ctx, L.st, W);
         return NIORCA_OK;
     }
-    if (!o.psi && !o.fvars) return NIORCA_OK;
+    if (!o.psi && !o.fvars) {
+        mark_partial(ctx, L.st, W);
+        return NIORCA_OK;
+    }
     // ---- Stage III-a: neighbour sums, tau, 4-cycles ----
     HIP_TRY(launch_sums(g, t, acc, cu * 8, s));
     STAGE_MARK(6);
@@ -574,7 +617,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
                      th.ql_wave, th.ql_block, th.ql_split, th.qh_wave, th.qh_block, kev, s));
     STAGE_MARK(8);
     // ---- Stage III-b: equations ----
-    HIP_TRY(launch_solve(g, acc, o.psi, o.fvars, dst, cu * 8, s));
+    HIP_TRY(launch_solve(g, acc, o.psi, o.fvars, dst, cu * 8, (flags & NIORCA_INDUCED) != 0, s));
     STAGE_MARK(9);
     ctx->ev_valid = timing;
     if (o.k4) {
@@ -588,6 +631,13 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     ctx->last_feat = feat ? L.feat : 0;
     ctx->last_order = L.val;
     ctx->last_ws = W;
+    if (flags & NIORCA_VALIDATE) {
+        // validated calls wait anyway: report the equations' evenness check too
+        GraphStats fin{};
+        HIP_TRY(hipMemcpyAsync(&fin, dst, sizeof(GraphStats), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (fin.err) return fail(ctx, NIORCA_EINTERNAL, "an equation's numerator that must be even was odd");
+    }
     return NIORCA_OK;
 }
 
@@ -598,7 +648,8 @@ extern "C" niorca_status niorca_count(niorca_ctx *ctx, int32_t n, int64_t nnz, c
     niorca_status st = check_graph_args(ctx, n, nnz, row_ptr, col);
     if (st) return st;
     if (n > 0 && !out) return fail(ctx, NIORCA_EINVAL, "out is NULL");
-    const uint32_t known = NIORCA_VALIDATE | NIORCA_BIN_DEGREE | NIORCA_BIN_MLP | NIORCA_COUNTERS | NIORCA_TIMING;
+    const uint32_t known =
+        NIORCA_VALIDATE | NIORCA_BIN_DEGREE | NIORCA_BIN_MLP | NIORCA_COUNTERS | NIORCA_TIMING | NIORCA_INDUCED;
     if (flags & ~known) return fail(ctx, NIORCA_EINVAL, "unknown flag bits 0x%x", flags & ~known);
     if ((flags & NIORCA_BIN_MLP) && !ctx->mlp_dev)
         return fail(ctx, NIORCA_EINVAL, "NIORCA_BIN_MLP needs a cost model (niorca_set_cost_model)");
@@ -617,6 +668,16 @@ extern "C" niorca_status niorca_edge_triangles(niorca_ctx *ctx, int32_t n, int64
     Outputs o;
     o.tri = tri;
     return run(ctx, n, nnz, row_ptr, col, o, as_stream(stream), 0, nullptr);
+}
+
+extern "C" niorca_status niorca_edge_k4(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
+                                        const int32_t *col, int64_t *k4e, void *stream) {
+    niorca_status st = check_graph_args(ctx, n, nnz, row_ptr, col);
+    if (st) return st;
+    if (nnz > 0 && !k4e) return fail(ctx, NIORCA_EINVAL, "k4e is NULL");
+    Outputs o;
+    o.ek4 = k4e;
+    return run(ctx, n, nnz, row_ptr, col, o, as_stream(stream), RUN_EDGE_K4, nullptr);
 }
 
 extern "C" niorca_status niorca_k4(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
@@ -640,8 +701,9 @@ extern "C" niorca_status niorca_fvars(niorca_ctx *ctx, int32_t n, int64_t nnz, c
 }
 
 // Packed batch -> one disjoint union: column ids local to graph g become global by
-// adding vtx_off[g] (one wave per row; the graph of a row by binary search).
-__global__ void k_localize(int32_t total_n, int32_t G, const int64_t *__restrict__ voff,
+// adding vtx_off[g] (one wave per row; the graph of a row by binary search).  An id
+// outside [0, n_g) becomes -1, which the relabel pass refuses (bad_input).
+__global__ void k_localize(int32_t total_n, int32_t G, int64_t nnz, const int64_t *__restrict__ voff,
                            const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
                            int32_t *__restrict__ colg) {
     int waves = gridDim.x * (blockDim.x / WAVE);
@@ -652,8 +714,13 @@ __global__ void k_localize(int32_t total_n, int32_t G, const int64_t *__restrict
             int mid = (lo + hi) >> 1;
             if (voff[mid] <= x) lo = mid; else hi = mid;
         }
-        const int32_t base = (int32_t)voff[lo];
-        for (int64_t s = rp[x] + lane_id(); s < rp[x + 1]; s += WAVE) colg[s] = col[s] + base;
+        const int32_t base = (int32_t)voff[lo], ng = (int32_t)(voff[lo + 1] - voff[lo]);
+        const int64_t b = rp[x], e = rp[x + 1];
+        if (b < 0 || e < b || e > nnz) continue;  // the degree pass refuses this row
+        for (int64_t s = b + lane_id(); s < e; s += WAVE) {
+            const int32_t c = col[s];
+            colg[s] = (c >= 0 && c < ng) ? c + base : -1;
+        }
     }
 }
 
@@ -670,7 +737,7 @@ extern "C" niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graph
     if (num_graphs < 0) return fail(ctx, NIORCA_EINVAL, "num_graphs is negative");
     if (num_graphs == 0) return NIORCA_OK;
     if (!vtx_off) return fail(ctx, NIORCA_EINVAL, "vtx_off is NULL");
-    const uint32_t known = NIORCA_VALIDATE | NIORCA_GRAPH_CAPTURE | NIORCA_TIMING;
+    const uint32_t known = NIORCA_VALIDATE | NIORCA_GRAPH_CAPTURE | NIORCA_TIMING | NIORCA_INDUCED;
     if (flags & ~known) return fail(ctx, NIORCA_EINVAL, "unknown or unsupported flag bits 0x%x", flags & ~known);
     const bool capture = (flags & NIORCA_GRAPH_CAPTURE) != 0;
     if (capture && (flags & (NIORCA_VALIDATE | NIORCA_TIMING)))
@@ -714,7 +781,8 @@ extern "C" niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graph
     o.psi = out;
     const int cu = ctx->num_cu;
     if (!capture) {
-        hipLaunchKernelGGL(k_localize, dim3(cu * 8), dim3(256), 0, s, n, num_graphs, dvoff, row_ptr, col, colg);
+        hipLaunchKernelGGL(k_localize, dim3(cu * 8), dim3(256), 0, s, n, num_graphs, nnz, dvoff, row_ptr, col,
+                           colg);
         HIP_TRY(hipGetLastError());
         return run(ctx, n, nnz, row_ptr, colg, o, s, flags, &hb);
     }
@@ -725,7 +793,7 @@ extern "C" niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graph
                        ctx->ws_bytes, vh, (uint64_t)ctx->heavy_k, (uint64_t)ctx->tri_cache_records,
                        (uint64_t)ctx->th.tri_wave, (uint64_t)ctx->th.tri_block, (uint64_t)ctx->th.ql_wave,
                        (uint64_t)ctx->th.ql_block, (uint64_t)ctx->th.qh_wave, (uint64_t)ctx->th.qh_block,
-                       (uint64_t)ctx->th.ql_split, (uint64_t)ctx->large_lds_max})
+                       (uint64_t)ctx->th.ql_split, (uint64_t)ctx->large_lds_max, (uint64_t)flags})
         key = mix64(key, v);
     if (!ctx->gexec || ctx->gkey != key) {
         if (ctx->gexec) {
@@ -733,7 +801,8 @@ extern "C" niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graph
             ctx->gexec = nullptr;
         }
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        hipLaunchKernelGGL(k_localize, dim3(cu * 8), dim3(256), 0, s, n, num_graphs, dvoff, row_ptr, col, colg);
+        hipLaunchKernelGGL(k_localize, dim3(cu * 8), dim3(256), 0, s, n, num_graphs, nnz, dvoff, row_ptr, col,
+                           colg);
         niorca_status rs = run(ctx, n, nnz, row_ptr, colg, o, s, flags & ~(uint32_t)NIORCA_GRAPH_CAPTURE, &hb);
         hipGraph_t graph = nullptr;
         hipError_t ce = hipStreamEndCapture(s, &graph);
@@ -905,6 +974,45 @@ extern "C" niorca_status niorca_kernel_times(niorca_ctx *ctx, float *ms, int32_t
     static const int first[NIORCA_NUM_KERNEL_TIMES] = {0, 1, 2, 3, 5, 6, 7, 8, 9, 10, 11, 13};
     for (int i = 0; i < NIORCA_NUM_KERNEL_TIMES; i++)
         HIP_TRY(hipEventElapsedTime(&ms[i], ctx->kev[first[i]], ctx->kev[first[i] + 1]));
+    return NIORCA_OK;
+}
+
+extern "C" niorca_status niorca_device_status(niorca_ctx *ctx, void *stream) {
+    if (!ctx) return NIORCA_EINVAL;
+    ctx->err.clear();
+    if (!ctx->ws || ctx->last_ws != ctx->ws) return NIORCA_OK;  // nothing counted on this workspace yet
+    HIP_TRY(hipSetDevice(ctx->device));
+    hipStream_t s = as_stream(stream);
+    GraphStats hs;
+    HIP_TRY(hipMemcpyAsync(&hs, ctx->ws + ctx->last_stats_dev, sizeof hs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hs.bad_input)
+        return fail(ctx, NIORCA_EINVAL, "row_ptr or col held values outside the graph or its degree bound");
+    if (hs.err) return fail(ctx, NIORCA_EINTERNAL, "an equation's numerator that must be even was odd");
+    return NIORCA_OK;
+}
+
+extern "C" niorca_status niorca_load_tuning(niorca_ctx *ctx, const char *path, const char *key) {
+    if (!ctx) return NIORCA_EINVAL;
+    ctx->err.clear();
+    if (!path || !key) return fail(ctx, NIORCA_EINVAL, "path or key is NULL");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(ctx, NIORCA_EINVAL, "cannot read %s", path);
+    char line[512];
+    int applied = 0;
+    niorca_status st = NIORCA_OK;
+    while (st == NIORCA_OK && fgets(line, sizeof line, f)) {
+        char *hash = strchr(line, '#');
+        if (hash) *hash = 0;
+        char k[128], name[128];
+        long long v;
+        if (sscanf(line, "%127s %127s %lld", k, name, &v) != 3 || strcmp(k, key) != 0) continue;
+        st = niorca_set_param(ctx, name, (int64_t)v);
+        applied++;
+    }
+    fclose(f);
+    if (st) return st;
+    if (!applied) return fail(ctx, NIORCA_EINVAL, "no entry for %s in %s", key, path);
     return NIORCA_OK;
 }
 

@@ -338,7 +338,10 @@ __device__ __forceinline__ void seg_map_scan(const i32 *off, int len, i32 eb, i3
     item_sync<NT>();
 }
 
-enum { PROBE_TRI = 0, PROBE_TAU = 1 };
+// Probe pass modes: Stage I/II (triangles and 4-cliques), tau, and Stage I/II with
+// the 4-cliques through every edge credited as well (the `tau` argument of the
+// kernels then carries that per-slot int64 array).
+enum { PROBE_TRI = 0, PROBE_TAU = 1, PROBE_EK4 = 2 };
 
 #ifndef TAU_RK
 #define TAU_RK 4  // triangle records per thread in flight in the tau pass
@@ -417,7 +420,8 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
                                            int pitch, i32 *__restrict__ t, i64 *__restrict__ K4,
                                            i64 *__restrict__ tau, i64 *red, i32 *red32, const TriCache &tc,
                                            ItemState *S, i64 *__restrict__ counters) {
-    const i64 t_start = (counters && MODE == PROBE_TRI) ? (i64)clock64() : 0;
+    constexpr bool TRI = MODE != PROBE_TAU;  // Stage I/II work (with or without per-edge 4-cliques)
+    const i64 t_start = (counters && TRI) ? (i64)clock64() : 0;
     const i32 u = pm.u, base = pm.base, du = pm.du;
     if (MODE == PROBE_TAU && pm.tcnt == 0) return;  // no triangle at u: nothing to add
     if (MODE == PROBE_TAU && pm.tcnt >= 0) {
@@ -478,7 +482,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
         // acc serves the tau pass only; the triangle pass leaves it alone, so that
         // its kernels need no LDS for it
         if (MODE == PROBE_TAU) M.acc[i] = 0;
-        if (MODE == PROBE_TRI) {
+        if (TRI) {
             M.tcnt[i] = 0;
             for (int k = 0; k < nw; k++) M.A[i * pitch + k] = 0u;
         }
@@ -486,7 +490,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
     item_sync<NT>();
     item_scan<NT>(M.off, du, tid, red32);
     const i32 total = M.off[du];
-    if (MODE == PROBE_TRI && tid == 0) {
+    if (TRI && tid == 0) {
         // room for every possible triangle of this item: min(probes, C(du, 2))
         i64 ub = min((i64)total, (i64)du * (du - 1) / 2);
         S->item_ok = 0;
@@ -520,7 +524,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
         }
     }
     item_sync<NT>();
-    const bool keep = MODE == PROBE_TRI && S->item_ok;
+    const bool keep = TRI && S->item_ok;
     const i64 item_base = keep ? S->item_base : 0;
     i64 tau_local = 0;
     // rounds of NT*QP probes: each thread locates its QP probes together, then
@@ -589,7 +593,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
                 }
             }
             if (p < 0) continue;
-            if (MODE == PROBE_TRI) {
+            if (TRI) {
                 atomicAdd(&M.tcnt[i], 1);
                 atomicAdd(&M.tcnt[p], 1);
                 atomicAdd(&t[q], 1);
@@ -607,7 +611,7 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
         }
     }
     item_sync<NT>();
-    if (MODE == PROBE_TRI) {
+    if (TRI) {
         if (tid == 0) {
             if (keep) {
                 tc.off[u] = item_base;
@@ -647,12 +651,17 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
                 if (c) {
                     atomicAdd(&sk[i], c);
                     atomicAdd(&sk[p], c);
+                    // the record's probe slot is the edge (nb[i], nb[p]) itself
+                    if constexpr (MODE == PROBE_EK4) atomic_add_i64(&tau[(i32)(rec >> 32)], c);
                 }
             }
             item_sync<NT>();
             for (int j = tid; j < du; j += NT) {
                 const i64 sj = sk[j];
                 if (sj) atomic_add_i64(&K4[M.nb ? M.nb[j] : g.ncol[base + j]], sj >> 1);
+                // sj / 2 = the 4-cliques through u and nb[j] with u lowest
+                if constexpr (MODE == PROBE_EK4)
+                    if (sj) atomic_add_i64(&tau[base + j], sj >> 1);
                 s_local += sj;
             }
         } else {
@@ -665,11 +674,27 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
                         bits &= bits - 1;
                         int i = wd * 32 + b;
                         words_scanned += nw;
-                        for (int k = 0; k < nw; k++) sj += __popc(A[i * pitch + k] & A[j * pitch + k]);
+                        if constexpr (MODE == PROBE_EK4) {
+                            i32 c = 0;
+                            for (int k = 0; k < nw; k++) c += __popc(A[i * pitch + k] & A[j * pitch + k]);
+                            sj += c;
+                            if (i < j && c) {
+                                // edge (nb[i], nb[j]): nb[j] lies in N+(nb[i]), found by search
+                                const i32 vi = M.nb ? M.nb[i] : g.ncol[base + i];
+                                const i32 vj = M.nb ? M.nb[j] : g.ncol[base + j];
+                                const i32 q = lower_bound_i32(g.ncol, vmeta_at(g, vi, VM_NSPLIT),
+                                                              vmeta_at(g, vi, VM_END), vj);
+                                atomic_add_i64(&tau[q], c);
+                            }
+                        } else {
+                            for (int k = 0; k < nw; k++) sj += __popc(A[i * pitch + k] & A[j * pitch + k]);
+                        }
                     }
                 }
                 // sj = 2 x (triangles of H_u through j) = 2 x (4-cliques containing u and nb[j])
                 if (sj) atomic_add_i64(&K4[M.nb ? M.nb[j] : g.ncol[base + j]], sj >> 1);
+                if constexpr (MODE == PROBE_EK4)
+                    if (sj) atomic_add_i64(&tau[base + j], sj >> 1);
                 s_local += sj;
             }
         }
@@ -822,7 +847,7 @@ __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__
     __shared__ i32 s_red32[PB_NT / WAVE];
     __shared__ ItemState s_st;
     // the triangle pass reads neighbours from the row again (its LDS is full)
-    ProbeMem M{s_hkey, s_hpos, s_off, MODE == PROBE_TRI ? nullptr : s_nb, s_beg, s_tcnt, s_A, s_acc, s_A, s_seg,
+    ProbeMem M{s_hkey, s_hpos, s_off, MODE != PROBE_TAU ? nullptr : s_nb, s_beg, s_tcnt, s_A, s_acc, s_A, s_seg,
                s_tcnt};
     if (threadIdx.x == 0) {
         s_st.chunk_cur = s_st.chunk_end = 0;
@@ -852,7 +877,7 @@ __global__ void __launch_bounds__(256) k_probe_thread(DevGraph g, const i32 *__r
     constexpr int C = TRI_THREAD_CAP;
     const i32 cnt = st->cnt[WC_TRI_THREAD];
     for (i32 it = blockIdx.x * blockDim.x + threadIdx.x; it < cnt; it += gridDim.x * blockDim.x) {
-        const i64 t_start = (counters && MODE == PROBE_TRI) ? (i64)clock64() : 0;
+        const i64 t_start = (counters && MODE != PROBE_TAU) ? (i64)clock64() : 0;
         const i32 u = list[it];
         const i32 base = g.nsplit[u];
         const i32 du = g.nrp[u + 1] - base;
@@ -880,7 +905,7 @@ __global__ void __launch_bounds__(256) k_probe_thread(DevGraph g, const i32 *__r
                 for (int j = 0; j < C; j++)
                     if (j > i && nu[j] == w) p = j;
                 if (p < 0) continue;
-                if (MODE == PROBE_TRI) {
+                if (MODE != PROBE_TAU) {
 #pragma unroll
                     for (int j = 0; j < C; j++) tcl[j] += (j == i) + (j == p);
                     atomicAdd(&t[q], 1);
@@ -893,7 +918,7 @@ __global__ void __launch_bounds__(256) k_probe_thread(DevGraph g, const i32 *__r
                 }
             }
         }
-        if (MODE == PROBE_TRI) {
+        if (MODE != PROBE_TAU) {
             i64 s = 0, tri2 = 0, words = 0;
 #pragma unroll
             for (int j = 0; j < C; j++) {
@@ -905,10 +930,21 @@ __global__ void __launch_bounds__(256) k_probe_thread(DevGraph g, const i32 *__r
 #pragma unroll
                 for (int i = 0; i < C; i++)
                     if ((rj >> i) & 1u) {
-                        sj += __popc(((u32)(A >> (i * C)) & 0xffu) & rj);
+                        const i32 c = __popc(((u32)(A >> (i * C)) & 0xffu) & rj);
+                        sj += c;
                         words++;
+                        if constexpr (MODE == PROBE_EK4) {
+                            if (i < j && c) {
+                                // edge (nu[i], nu[j]): nu[j] lies in N+(nu[i])
+                                const i32 q = lower_bound_i32(g.ncol, vmeta_at(g, nu[i], VM_NSPLIT),
+                                                              vmeta_at(g, nu[i], VM_END), nu[j]);
+                                atomic_add_i64(&tau[q], c);
+                            }
+                        }
                     }
                 if (sj) atomic_add_i64(&K4[nu[j]], sj >> 1);
+                if constexpr (MODE == PROBE_EK4)
+                    if (sj) atomic_add_i64(&tau[base + j], sj >> 1);
                 s += sj;
             }
             if (s) atomic_add_i64(&K4[u], s / 6);
@@ -1088,7 +1124,34 @@ __device__ __forceinline__ void solve_vertex(i64 d, i64 T, i64 psi1, i64 St, i64
     psi[14] = k4;
 }
 
-template <int W>
+// Induced counts psi'_k from the non-induced psi_k of one vertex.  An induced
+// occurrence of a graphlet on a vertex set S contains, as non-induced occurrences
+// on S, its connected spanning subgraphs: psi = C psi', C unit upper triangular in
+// this orbit numbering (C[k][j] = in how many connected spanning subgraphs of the
+// graphlet of orbit j a vertex of orbit j has orbit k).  These are the rows of
+// C^-1; three of them are the induced equations printed next to the non-induced
+// ones (Section 5, relating ORCA and NI-ORCA): psi'_13 = psi_13 - 3 psi_14,
+// psi'_11 = psi_11 - 2 psi_13 + 3 psi_14, psi'_10 = psi_10 - 2 psi_12 - 2 psi_13
+// + 6 psi_14.
+__device__ __forceinline__ void induced_from_noninduced(const i64 *p, i64 *o) {
+    o[0] = p[0];
+    o[1] = p[1] - 2 * p[3];
+    o[2] = p[2] - p[3];
+    o[3] = p[3];
+    o[4] = p[4] - 2 * p[8] - 2 * p[9] - p[10] + 4 * p[12] + 2 * p[13] - 6 * p[14];
+    o[5] = p[5] - 2 * p[8] - p[10] - 2 * p[11] + 2 * p[12] + 4 * p[13] - 6 * p[14];
+    o[6] = p[6] - p[9] - p[10] + 2 * p[12] + p[13] - 3 * p[14];
+    o[7] = p[7] - p[11] + p[13] - p[14];
+    o[8] = p[8] - p[12] - p[13] + 3 * p[14];
+    o[9] = p[9] - 2 * p[12] + 3 * p[14];
+    o[10] = p[10] - 2 * p[12] - 2 * p[13] + 6 * p[14];
+    o[11] = p[11] - 2 * p[13] + 3 * p[14];
+    o[12] = p[12] - 3 * p[14];
+    o[13] = p[13] - 3 * p[14];
+    o[14] = p[14];
+}
+
+template <int W, bool INDUCED>
 __device__ __forceinline__ void solve_one(const DevGraph &g, const Accum &acc, i64 *__restrict__ out,
                                           i64 *__restrict__ fvars, i32 x, bool active, int l, int *err) {
     i32 b0 = 0, e0 = 0;
@@ -1110,6 +1173,12 @@ __device__ __forceinline__ void solve_one(const DevGraph &g, const Accum &acc, i
     i64 f[9], psi[15];
     solve_vertex(e0 - b0, acc.Tp[2 * (i64)x], acc.Tp[2 * (i64)x + 1], acc.St[x], acc.Stt[x], acc.Std[x], acc.Sd[x],
                  acc.Sdd[x], ST, Sp, acc.tau[x], acc.Q[x], acc.K4[x], f, psi, err);
+    if constexpr (INDUCED) {
+        i64 ni[15];
+#pragma unroll
+        for (int k = 0; k < 15; k++) ni[k] = psi[k];
+        induced_from_noninduced(ni, psi);
+    }
     const i64 xo = g.order[x];
     if (out && l < 15) {
         i64 v = 0;
@@ -1125,6 +1194,7 @@ __device__ __forceinline__ void solve_one(const DevGraph &g, const Accum &acc, i
     }
 }
 
+template <bool INDUCED>
 __global__ void __launch_bounds__(256) k_solve(DevGraph g, Accum acc, i64 *__restrict__ out,
                                                i64 *__restrict__ fvars, GraphStats *__restrict__ st) {
     const int waves = gridDim.x * (blockDim.x / WAVE);
@@ -1134,9 +1204,10 @@ __global__ void __launch_bounds__(256) k_solve(DevGraph g, Accum acc, i64 *__res
     int err = 0;
     for (i32 xb = wid * GPW; xb < cut; xb += waves * GPW) {
         const i32 x = xb + lane_id() / SG;
-        solve_one<SG>(g, acc, out, fvars, x, x < cut, lane_id() % SG, &err);
+        solve_one<SG, INDUCED>(g, acc, out, fvars, x, x < cut, lane_id() % SG, &err);
     }
-    for (i32 x = g.n - 1 - wid; x >= cut; x -= waves) solve_one<WAVE>(g, acc, out, fvars, x, true, lane_id(), &err);
+    for (i32 x = g.n - 1 - wid; x >= cut; x -= waves)
+        solve_one<WAVE, INDUCED>(g, acc, out, fvars, x, true, lane_id(), &err);
     if (err) atomicOr(&st->err, 1);
 }
 
@@ -1153,8 +1224,9 @@ __device__ __forceinline__ void q_segment(const DevGraph &g, i32 x, i32 s, i32 s
         beg = vmeta_at(g, v, VM_BEGIN);
         end = g.mirror[s];
     } else {
-        beg = (x >= g.h0 && s < sp) ? g.mirror[s] + 1 : vmeta_at(g, v, VM_HSTART);
         end = vmeta_at(g, v, VM_END);
+        // (the clamp only matters for an asymmetric input, whose mirror may be the row end)
+        beg = (x >= g.h0 && s < sp) ? min(g.mirror[s] + 1, end) : vmeta_at(g, v, VM_HSTART);
     }
 }
 
@@ -1996,7 +2068,20 @@ hipError_t launch_probe(int mode, const DevGraph &g, i32 *const *lists_host, con
     TriCache tw{tca.rec, tca.cap, tca.bump, tca.off, tca.cnt, tca.chunk_wave};
     TriCache tb{tca.rec, tca.cap, tca.bump, tca.off, tca.cnt, tca.chunk_block};
     TriCache tg{tca.rec, tca.cap, tca.bump, tca.off, tca.cnt, tca.chunk_group};
-    if (mode == PROBE_TRI) {
+    if (mode == PROBE_EK4) {
+        // Stage I/II with per-edge 4-cliques into `tau` (an int64 per slot)
+        hipLaunchKernelGGL(k_probe_thread<PROBE_EK4>, dim3(grid_wave), dim3(256), 0, s, g,
+                           lists_host[WC_TRI_THREAD], st, t, K4, tau, tw, (i64 *)nullptr);
+        hipLaunchKernelGGL(k_probe_wave<PROBE_EK4>, dim3(grid_wave), dim3(256), 0, s, g, lists_host[WC_TRI_WAVE], st,
+                           t, K4, tau, tw, (i64 *)nullptr);
+        hipLaunchKernelGGL(k_probe_block<PROBE_EK4>, dim3(grid_block), dim3(PB_NT), 0, s, g,
+                           lists_host[WC_TRI_BLOCK], st, t, K4, tau, tb, (i64 *)nullptr);
+        if (large_blocks > 0)
+            launch_large<PROBE_EK4>(g, lists_host[WC_TRI_LARGE], st, t, K4, tau, tb, large_scratch, large_slice,
+                                    large_cap, large_hc, large_blocks, large_lds_max, (i64 *)nullptr, s);
+        hipLaunchKernelGGL(k_probe_group<PROBE_EK4>, dim3(grid_wave), dim3(256), 0, s, g,
+                           lists_host[WC_TRI_GROUP], st, t, K4, tau, tg, (i64 *)nullptr);
+    } else if (mode == PROBE_TRI) {
         KMARK(0);
         hipLaunchKernelGGL(k_probe_thread<PROBE_TRI>, dim3(grid_wave), dim3(256), 0, s, g,
                            lists_host[WC_TRI_THREAD], st, t, K4, tau, tw, counters);
@@ -2038,9 +2123,12 @@ hipError_t launch_sums(const DevGraph &g, const i32 *t, const Accum &acc, int gr
 }
 
 hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvars, GraphStats *st, int grid,
-                        hipStream_t s) {
+                        bool induced, hipStream_t s) {
     if (g.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_solve, dim3(grid), dim3(256), 0, s, g, acc, out, fvars, st);
+    if (induced)
+        hipLaunchKernelGGL(k_solve<true>, dim3(grid), dim3(256), 0, s, g, acc, out, fvars, st);
+    else
+        hipLaunchKernelGGL(k_solve<false>, dim3(grid), dim3(256), 0, s, g, acc, out, fvars, st);
     return hipGetLastError();
 }
 

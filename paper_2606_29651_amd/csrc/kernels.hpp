@@ -132,7 +132,7 @@ hipError_t scan_u32_to_i32(const u32 *in, i64 len, i32 *out, i32 *ws, int write_
 hipError_t scan_i32_to_i32(const i32 *in, i64 len, i32 *out, i32 *ws, int write_total, hipStream_t s);
 hipError_t radix_sort_pairs(u32 *k, u32 *v, u32 *k2, u32 *v2, i64 n, int bits, i32 *hist, i32 *scan_ws,
                             hipStream_t s);
-__global__ void k_degree(i32 n, i64 nnz, const i64 *rp, u32 *deg, u32 *vals, GraphStats *st);
+__global__ void k_degree(i32 n, i64 nnz, i64 dcap, const i64 *rp, u32 *deg, u32 *vals, GraphStats *st);
 __global__ void k_invert(i32 n, const u32 *order, i32 *perm);
 __global__ void k_relabel(i32 n, const i64 *rp, const i32 *col, const u32 *order, const i32 *perm,
                           const u32 *ndeg, const i32 *nrp, i32 *nsplit, i32 *ncol, int4 *vmeta, GraphStats *st);
@@ -180,7 +180,7 @@ hipError_t mlp_standardise_targets(i64 n, const float *y, double *part, int nblo
 hipError_t mlp_fold_output(float *P, const float *ms, hipStream_t s);
 hipError_t launch_sums(const DevGraph &g, const i32 *t, const Accum &acc, int grid, hipStream_t s);
 hipError_t launch_solve(const DevGraph &g, const Accum &acc, i64 *out, i64 *fvars, GraphStats *st, int grid,
-                        hipStream_t s);
+                        bool induced, hipStream_t s);
 hipError_t launch_q(const DevGraph &g, i32 *const *lists_host, const GraphStats *st, i64 *Q, i32 *gscratch,
                     i64 gslice, int gblocks, int grid_wave, int grid_block, int grid_dense, i64 *part, int part_rows,
                     i64 ql_wave_bound, i64 ql_block_bound, i64 ql_split, i64 qh_wave_bound, i64 qh_block_bound,

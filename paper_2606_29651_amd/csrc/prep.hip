@@ -12,12 +12,14 @@
 // ---------------------------------------------------------------------------
 // Degrees and the first statistics.
 // ---------------------------------------------------------------------------
-// A row whose bounds leave [0, nnz] or run backwards gets degree 0 and raises
-// bad_input, so no later kernel reads outside the input.
+// A row whose bounds leave [0, nnz], run backwards or hold more than dcap entries
+// (a bound on the degree the caller knows, which sizes the per-row buffers) gets
+// degree 0 and raises bad_input, so no later kernel reads or writes outside its
+// buffers.
 // Grid-stride over the vertices; the maximum degree meets in LDS first, so that
 // the shared statistic takes one atomic per workgroup (one per wave serialised
 // tens of thousands of same-address atomics).
-__global__ void k_degree(i32 n, i64 nnz, const i64 *__restrict__ rp, u32 *__restrict__ deg,
+__global__ void k_degree(i32 n, i64 nnz, i64 dcap, const i64 *__restrict__ rp, u32 *__restrict__ deg,
                          u32 *__restrict__ vals, GraphStats *__restrict__ st) {
     __shared__ int s_max;
     if (threadIdx.x == 0) s_max = 0;
@@ -25,7 +27,7 @@ __global__ void k_degree(i32 n, i64 nnz, const i64 *__restrict__ rp, u32 *__rest
     int dm = 0;
     for (i32 v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         i64 b = rp[v], e = rp[v + 1];
-        bool ok = b >= 0 && e >= b && e <= nnz && (v > 0 || b == 0) && (v < n - 1 || e == nnz);
+        bool ok = b >= 0 && e >= b && e <= nnz && e - b <= dcap && (v > 0 || b == 0) && (v < n - 1 || e == nnz);
         if (!ok) atomicOr(&st->bad_input, 1);
         const int d = ok ? (int)(e - b) : 0;
         deg[v] = (u32)d;
@@ -496,7 +498,7 @@ __device__ __forceinline__ void mirror_row(i32 y, bool active, int l, const i32 
             i32 m = lower_bound_i32(ncol, vb.y, bend, y);
             mirror[s] = m;
             wl += m - bb;
-            i32 st = (y >= h0) ? m + 1 : vb.w;
+            i32 st = (y >= h0) ? min(m + 1, bend) : vb.w;  // (m = bend only for asymmetric input)
             wh += bend - st;
         } else {
             wh += bend - vb.w;

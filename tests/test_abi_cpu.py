@@ -40,3 +40,24 @@ def test_binding_refuses_host_tensors():
     import paper_2606_29651_amd as ni
     with pytest.raises((ValueError, TypeError)):
         ni.count(torch.zeros(3, dtype=torch.int64), torch.zeros(0, dtype=torch.int32))
+
+
+def test_tuning_file_roundtrip(tmp_path):
+    """The autotuner's file is the text the library reads (key name value lines)."""
+    from paper_2606_29651_amd import autotune
+    p = str(tmp_path / "t.txt")
+    autotune.save(p, "a", {"tri_wave": 32, "heavy_k": 0}, note="first")
+    autotune.save(p, "b", {"qh_wave": 256})
+    autotune.save(p, "a", {"tri_wave": 64})
+    assert autotune.load(p, "a") == {"tri_wave": 64}
+    assert autotune.load(p, "b") == {"qh_wave": 256}
+    assert autotune.load(p, "c") is None
+    lines = [ln.split("#")[0].split() for ln in open(p) if ln.split("#")[0].strip()]
+    assert all(len(x) == 3 and x[2].lstrip("-").isdigit() for x in lines)
+
+
+def test_committed_tuning_file_parses():
+    from paper_2606_29651_amd import autotune
+    path = os.path.join(ROOT, "paper_2606_29651_amd", "tuning.txt")
+    got = autotune.load(path, "batch_mix")
+    assert got and set(got) <= set(autotune.DEFAULTS)

@@ -118,3 +118,51 @@ def test_degree_overflow_guard(ni):
     assert e.value.status == ni.EOVERFLOW
     torch.cuda.synchronize()
     ctx.close()
+
+
+def test_oriented_degree_limit_enotimpl(ni):
+    """|N+(v)| above 16384 (the largest row the orientation pass sorts in LDS) is
+    refused with ENOTIMPL after the degree statistics, before any counting kernel:
+    K_16386 is the smallest simple graph that reaches it (its lowest-ranked vertex
+    has 16385 neighbours above it)."""
+    import torch
+    n = 16386
+    # K_n in CSR directly: row x lists every other vertex, ascending
+    col = np.broadcast_to(np.arange(n, dtype=np.int32), (n, n))[~np.eye(n, dtype=bool)]
+    row_ptr = np.arange(n + 1, dtype=np.int64) * (n - 1)
+    ctx = ni.Context(0)
+    try:
+        with pytest.raises(ni.NiorcaError) as e:
+            ni.count(torch.from_numpy(row_ptr).cuda(), torch.from_numpy(np.ascontiguousarray(col)).cuda(), ctx=ctx)
+        assert e.value.status == ni.ENOTIMPL
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
+
+
+def test_tuning_file_and_bin_mode_errors(ni, tmp_path):
+    import torch
+    ctx = ni.Context(0)
+    try:
+        path = tmp_path / "t.txt"
+        path.write_text("# comment\nmine tri_wave 32\nmine heavy_k 0  # trailing\nother tri_wave 99\n")
+        ctx.load_tuning(str(path), "mine")
+        with pytest.raises(ni.NiorcaError) as e:
+            ctx.load_tuning(str(path), "absent")
+        assert e.value.status == ni.EINVAL
+        with pytest.raises(ni.NiorcaError) as e:
+            ctx.load_tuning(str(path), "other")  # 99 is out of range for tri_wave
+        assert e.value.status == ni.EINVAL
+        with pytest.raises(ni.NiorcaError):
+            ctx.load_tuning(str(tmp_path / "missing.txt"), "mine")
+        with pytest.raises(ni.NiorcaError):
+            ctx.set_param("bin_mode", 2)  # no cost model loaded
+        with pytest.raises(ni.NiorcaError):
+            ctx.set_param("bin_mode", 3)
+        g = gg.config_graph("er_tiny")
+        got = ni.count(torch.from_numpy(g.row_ptr).cuda(), torch.from_numpy(g.col).cuda(), ctx=ctx)
+        import oracle
+        assert np.array_equal(got.cpu().numpy(), oracle.count(g.row_ptr, g.col))
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()

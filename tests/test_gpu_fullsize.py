@@ -1,8 +1,21 @@
-"""Full-size parity on the measured workloads (Chung-Lu n = 4M, ~39M edges; ER
-n = 4M, average degree 32; R-MAT scale 22), in the launch configuration bench.py
-times: the whole n x 15 matrix is computed on the GPU; the CPU oracle recomputes
-sampled vertices one by one (uniform sample plus vertices of high degree), and
-orbit-sum identities that hold for any graph are checked on the complete output."""
+"""Full-size parity on the measured workloads (Chung-Lu n = 4M, ~39M edges; R-MAT
+scale 22; every point of the Erdos-Renyi series n in {1,2,4,8,16}M x average degree
+{8,16,32}), in the launch configuration bench.py times.
+
+The whole n x 15 matrix is computed on the GPU, then checked three ways:
+  * exactly, against the CPU oracle, on sampled vertices recomputed one by one: a
+    uniform sample, vertices of degree 300-2500, the eight highest degrees (on R-MAT
+    these include every class of hub, up to the d >= 2^16 vertices whose 4-cycle
+    counters live in global memory) and the ranks at the edges of the heavy 4-cycle
+    key range;
+  * on every vertex, through orbit-sum identities whose right-hand sides come from
+    the degrees, the GPU's own Stage I output, and the oracle's whole-graph counts of
+    4-cycles and 4-cliques (sum psi_8 = 4 #C4 and sum psi_14 = 4 #K4 exactly);
+  * the induced counts (NIORCA_INDUCED) against the non-induced ones through the
+    matrix of the subgraph relation derived by brute force on the nine graphlets,
+    and, on R-MAT, the degree- and MLP-binned forms against the plain one and the
+    4-cliques per edge against their sums and sampled oracle values.
+"""
 import sys
 import time
 
@@ -10,8 +23,12 @@ import numpy as np
 import pytest
 
 import graphgen as gg
+from orbit_relations import subgraph_matrix
 
 pytestmark = pytest.mark.gpu
+
+ER_POINTS = [f"er_{n}m_{d}" for n in (1, 2, 4, 8, 16) for d in (8, 16, 32)]
+HEAVY_K = 32768
 
 
 def _say(msg):
@@ -19,30 +36,61 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def column_identities(psi, g, tri_edges):
+def column_identities(psi, g, tri_edges, c4, k4):
     """Sums over all vertices that equal graphlet counts times orbit sizes."""
     s = psi.sum(0, dtype=np.int64)
     d = g.degrees().astype(np.int64)
-    e = g.edges()
+    src = np.repeat(np.arange(g.n, dtype=np.int64), d)
+    low = src < g.col  # each undirected edge once
+    a, b = src[low], g.col[low].astype(np.int64)
     c2 = int((d * (d - 1) // 2).sum())
     c3 = int((d * (d - 1) * (d - 2) // 6).sum())
     assert s[0] == 2 * g.m
     assert s[1] == 2 * c2 and s[2] == c2
     assert s[3] % 3 == 0
     T = int(s[3] // 3)
-    p4 = int(((d[e[:, 0]] - 1) * (d[e[:, 1]] - 1)).sum()) - 3 * T
+    p4 = int(((d[a] - 1) * (d[b] - 1)).sum()) - 3 * T
     assert s[4] == 2 * p4 and s[5] == 2 * p4
     assert s[6] == 3 * c3 and s[7] == c3
-    assert s[8] % 4 == 0 and s[14] % 4 == 0
+    assert s[8] == 4 * c4, (int(s[8]), c4)
+    assert s[14] == 4 * k4, (int(s[14]), k4)
     tt = int((psi[:, 3] * (d - 2)).sum())
     assert s[9] == tt and s[11] == tt and s[10] == 2 * tt
     # per undirected edge, from the GPU's Stage I output (each edge appears twice)
-    dia = int((tri_edges.astype(np.int64) * (tri_edges.astype(np.int64) - 1) // 2).sum() // 2)
+    t64 = tri_edges.astype(np.int64)
+    assert int(t64.sum()) == 6 * T
+    dia = int((t64 * (t64 - 1) // 2).sum() // 2)
     assert s[12] == 2 * dia and s[13] == 2 * dia
 
 
-@pytest.mark.parametrize("workload", ["chung_lu_4m", "er_4m_32", "rmat22"])
-def test_full_size_sampled(workload):
+# The oracle's per-vertex Stage III visits every pair of neighbours of a sampled
+# vertex; above this degree that alone takes minutes of one CPU thread (R-MAT's
+# largest hub, d = 162,951, has 1.3e10 pairs), so such vertices are checked through
+# the identities only.
+SAMPLE_MAX_DEG = 100_000
+
+
+def sample_vertices(g, rng):
+    d = g.degrees()
+    uniform = rng.choice(g.n, 48, replace=False)
+    mid = np.flatnonzero((d >= 300) & (d <= 2500))
+    mids = rng.choice(mid, min(6, len(mid)), replace=False) if len(mid) else np.zeros(0, np.int64)
+    order = np.lexsort((np.arange(g.n), d))  # degree rank, ties by id (the library's order)
+    top = order[d[order] <= SAMPLE_MAX_DEG][-8:]
+    # ranks just inside and just outside the heavy range, and in its middle
+    ranks = [g.n - HEAVY_K - 1, g.n - HEAVY_K, g.n - HEAVY_K // 2, g.n - 2 * HEAVY_K]
+    edge = order[[r for r in ranks if 0 <= r < g.n]]
+    return np.unique(np.concatenate([uniform, mids, top, edge])).astype(np.int32)
+
+
+def _count(ni, rp, cl, **kw):
+    import torch
+    out = ni.count(rp, cl, **kw)
+    torch.cuda.synchronize()
+    return out
+
+
+def _full_size(workload, extra):
     import torch
     import oracle
     import paper_2606_29651_amd as ni
@@ -52,21 +100,81 @@ def test_full_size_sampled(workload):
     _say(f"[gpu] {workload} generated n={g.n} m={g.m} in {time.time() - t0:.0f}s")
     rp = torch.from_numpy(g.row_ptr).cuda()
     cl = torch.from_numpy(g.col).cuda()
-    psi = ni.count(rp, cl).cpu().numpy()
-    tri = ni.edge_triangles(rp, cl).cpu().numpy()
-    torch.cuda.synchronize()
-    del rp, cl
-    _say(f"[gpu] {workload} counted; checking identities")
-    column_identities(psi, g, tri)
-    rng = np.random.default_rng(2024)
-    d = g.degrees()
-    uniform = rng.choice(g.n, 48, replace=False)
-    mid = np.flatnonzero((d >= 300) & (d <= 2500))
-    if len(mid) == 0:
-        mid = np.argsort(d)[-64:]
-    hubs = rng.choice(mid, min(6, len(mid)), replace=False)
-    xs = np.unique(np.concatenate([uniform, hubs])).astype(np.int32)
+    ctx = ni.Context(0)
+    try:
+        psi_d = _count(ni, rp, cl, ctx=ctx)
+        ctx.device_status()
+        tri = ni.edge_triangles(rp, cl, ctx=ctx).cpu().numpy()
+        ind = _count(ni, rp, cl, ctx=ctx, flags=ni.INDUCED).cpu().numpy()
+        psi = psi_d.cpu().numpy()
+        if extra:
+            extra(ni, ctx, g, rp, cl, psi_d)
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
+    del rp, cl, psi_d
+    torch.cuda.empty_cache()
+    _say(f"[gpu] {workload} counted; whole-graph oracle counts")
+    t0 = time.time()
+    c4 = oracle.cycles4_total(g.row_ptr, g.col)
+    k4 = oracle.k4_total(g.row_ptr, g.col)
+    _say(f"[gpu] {workload} #C4={c4} #K4={k4} in {time.time() - t0:.0f}s; identities")
+    column_identities(psi, g, tri, c4, k4)
+    C = subgraph_matrix()
+    assert np.array_equal(ind @ C.T, psi)
+    del ind, tri
+    xs = sample_vertices(g, np.random.default_rng(2024))
     t0 = time.time()
     ref = oracle.orbits_at(g.row_ptr, g.col, xs)
-    _say(f"[gpu] oracle on {len(xs)} vertices of {workload} in {time.time() - t0:.0f}s")
-    assert np.array_equal(psi[xs], ref)
+    _say(f"[gpu] oracle on {len(xs)} vertices of {workload} (max degree {g.degrees()[xs].max()}) "
+         f"in {time.time() - t0:.0f}s")
+    if not np.array_equal(psi[xs], ref):
+        bad = np.argwhere(psi[xs] != ref)
+        pytest.fail(f"{len(bad)} sampled entries differ; first (vertex, orbit) "
+                    f"{[(int(xs[i]), int(k)) for i, k in bad[:6]]}")
+
+
+def _rmat_extra(ni, ctx, g, rp, cl, psi_d):
+    """Binned forms equal the plain one; 4-cliques per edge against sums and the oracle."""
+    import torch
+    import oracle
+    deg = _count(ni, rp, cl, ctx=ctx, flags=ni.BIN_DEGREE)
+    assert torch.equal(deg, psi_d)
+    del deg
+    # a work model trained on this graph's own counters, thresholds that move items
+    _count(ni, rp, cl, ctx=ctx, flags=ni.COUNTERS)
+    c = ni.work_counters(g.n, ctx=ctx)
+    X = ni.last_features(g.n, ctx=ctx)
+    keep = c[:, 6] > 0
+    y = torch.log2(1.0 + (c[keep, 0] + 4 * c[keep, 1] + c[keep, 2]).double()).float()
+    model, mse = ni.mlp_train(X[keep].contiguous(), y.contiguous(), epochs=1, batch=8192, ctx=ctx)
+    _say(f"[gpu] rmat22 work model mse {mse:.3f}")
+    ni.set_cost_model(model, 8.0, 15.0, 11.0, ctx=ctx)
+    mlp = _count(ni, rp, cl, ctx=ctx, flags=ni.BIN_MLP)
+    assert torch.equal(mlp, psi_d)
+    del mlp, c, X
+    ek = ni.edge_k4(rp, cl, ctx=ctx)
+    torch.cuda.synchronize()
+    ek_h = ek.cpu().numpy()
+    del ek
+    k4v = psi_d[:, 14].cpu().numpy()
+    rows = np.add.reduceat(ek_h, g.row_ptr[:-1])
+    rows[g.degrees() == 0] = 0
+    assert np.array_equal(rows, 3 * k4v)
+    rng = np.random.default_rng(7)
+    d = g.degrees()
+    src = np.repeat(np.arange(g.n), d)
+    # uniform slots plus slots of the highest-degree vertex
+    hub = int(np.argmax(d))
+    slots = np.unique(np.concatenate([rng.choice(g.nnz, 400, replace=False),
+                                      g.row_ptr[hub] + rng.choice(d[hub], 100, replace=False)]))
+    t0 = time.time()
+    ref = oracle.edge_k4(g.row_ptr, g.col, slots)
+    _say(f"[gpu] rmat22 oracle edge_k4 on {len(slots)} slots in {time.time() - t0:.0f}s "
+         f"(max {int(ref.max())}, hub {hub} deg {d[hub]}, src of first {int(src[slots[0]])})")
+    assert np.array_equal(ek_h[slots], ref)
+
+
+@pytest.mark.parametrize("workload", ["chung_lu_4m", "rmat22"] + ER_POINTS)
+def test_full_size(workload):
+    _full_size(workload, _rmat_extra if workload == "rmat22" else None)

@@ -296,3 +296,14 @@ def check_invariants(psi, gc):
 def test_c_oracle_invariants(oracle_lib, make):
     g = make()
     check_invariants(oracle_lib.count(g.row_ptr, g.col), global_counts(g))
+
+
+@pytest.mark.parametrize("make", MEDIUM)
+def test_c_stage23_at_matches_full(oracle_lib, make):
+    """Stages II and III on selected vertices from the whole graph's Stage I counts
+    (the CPU baseline's timed sample) equal the full three-stage run."""
+    g = make()
+    full = oracle_lib.count(g.row_ptr, g.col)
+    tri = oracle_lib.stage1(g.row_ptr, g.col)
+    xs = np.unique(np.concatenate([np.arange(0, g.n, 5), np.argsort(-g.degrees())[:5]])).astype(np.int32)
+    assert np.array_equal(oracle_lib.stage23_at(g.row_ptr, g.col, tri, xs), full[xs])
