@@ -60,6 +60,7 @@ def _load():
         lib.oref_k4_total.argtypes = [i32, P, P, P]
         lib.oref_edge_k4.argtypes = [i32, P, P, i64, P, P]
         lib.oref_stage23_at.argtypes = [i32, P, P, P, i32, P, P]
+        lib.oref_cycles4_at.argtypes = [i32, P, P, i32, P, P]
         lib.oref_stage1.argtypes = [i32, P, P, P]
         lib.oref_stage2.argtypes = [i32, P, P, P]
         lib.oref_stage3.argtypes = [i32, P, P, P, P, P, P]
@@ -69,7 +70,7 @@ def _load():
         lib.oref_num_threads.restype = ctypes.c_int
         for name in ("oref_enum_count", "oref_stage1", "oref_stage2", "oref_stage3",
                      "oref_count", "oref_orbits_at", "oref_enum_induced", "oref_cycles4_total",
-                     "oref_k4_total", "oref_edge_k4", "oref_stage23_at"):
+                     "oref_k4_total", "oref_edge_k4", "oref_stage23_at", "oref_cycles4_at"):
             getattr(lib, name).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -190,6 +191,16 @@ def count_with_intermediates(row_ptr, col):
     k4 = stage2(row_ptr, col)
     psi, fv = stage3(row_ptr, col, tri, k4, want_fvars=True)
     return psi, tri, k4, fv
+
+
+def cycles4_at(row_ptr, col, xs) -> np.ndarray:
+    """psi_8 (4-cycles through x) of selected vertices, int64[len(xs)], from the
+    definition: pairs of common neighbours with every vertex opposite x."""
+    n, rp, cl = _csr(row_ptr, col)
+    xs = np.ascontiguousarray(xs, dtype=np.int32)
+    out = np.zeros(xs.shape[0], dtype=np.int64)
+    _check(_load().oref_cycles4_at(n, _ptr(rp), _ptr(cl), xs.shape[0], _ptr(xs), _ptr(out)), "cycles4_at")
+    return out
 
 
 def stage23_at(row_ptr, col, tri, xs) -> np.ndarray:

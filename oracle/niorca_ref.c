@@ -277,26 +277,34 @@ int oref_enum_induced(i32 n, const i64 *rp, const i32 *col, i64 *psi)
 
 /* Stage I (Algorithm 1): the i-th edge (x, y), x < y, taken in CSR order, gets
  * tri = |N(x) and N(y)| by a sorted merge.  The value is stored in both CSR slots
- * of the edge (tri int32[row_ptr[n]]) so later stages can read it from either end. */
+ * of the edge (tri int32[row_ptr[n]]) so later stages can read it from either end.
+ * The loop runs over the edges themselves (in parallel chunks of slots), so a
+ * vertex with a long row does not leave one thread all of its merges. */
 int oref_stage1(i32 n, const i64 *rp, const i32 *col, i32 *tri)
 {
     if (n < 0 || (n > 0 && (!rp || !col)) || (n > 0 && rp[n] > 0 && !tri)) return ORACLE_EINVAL;
+    if (n == 0) return ORACLE_OK;
+    const i64 nnz = rp[n];
+    i32 *src = (i32 *)malloc(sizeof(i32) * (size_t)(nnz ? nnz : 1));
+    if (!src) return ORACLE_ENOMEM;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (i32 x = 0; x < n; x++)
+        for (i64 s = rp[x]; s < rp[x + 1]; s++) src[s] = x;
 #pragma omp parallel for schedule(dynamic, 64)
-    for (i32 x = 0; x < n; x++) {
-        for (i64 s = rp[x]; s < rp[x + 1]; s++) {
-            i32 y = col[s];
-            if (y < x) continue;
-            i64 i = rp[x], j = rp[y];
-            i32 c = 0;
-            while (i < rp[x + 1] && j < rp[y + 1]) {
-                if (col[i] < col[j]) i++;
-                else if (col[i] > col[j]) j++;
-                else { c++; i++; j++; }
-            }
-            tri[s] = c;
-            tri[slot_of(rp, col, y, x)] = c;
+    for (i64 s = 0; s < nnz; s++) {
+        i32 x = src[s], y = col[s];
+        if (y < x) continue;
+        i64 i = rp[x], j = rp[y];
+        i32 c = 0;
+        while (i < rp[x + 1] && j < rp[y + 1]) {
+            if (col[i] < col[j]) i++;
+            else if (col[i] > col[j]) j++;
+            else { c++; i++; j++; }
         }
+        tri[s] = c;
+        tri[slot_of(rp, col, y, x)] = c;
     }
+    free(src);
     return ORACLE_OK;
 }
 
@@ -544,6 +552,9 @@ int oref_orbits_at(i32 n, const i64 *rp, const i32 *col, i32 nq, const i32 *xs,
     i64 nrows = 0;
     for (i32 v = 0; v < n; v++) if (need[v]) rows[nrows++] = v;
     int err = 0;
+    /* t(y, z) = |N(y) and N(z)| (Algorithm 1), with N(y) marked: the members of N(z)
+     * are tested against the marks, or, when N(z) is much longer than N(y), the
+     * members of N(y) are searched in the sorted N(z) instead */
 #pragma omp parallel
     {
         unsigned char *mark = (unsigned char *)calloc((size_t)n, 1);
@@ -554,11 +565,16 @@ int oref_orbits_at(i32 n, const i64 *rp, const i32 *col, i32 nq, const i32 *xs,
 #pragma omp for schedule(dynamic, 1)
             for (i64 i = 0; i < nrows; i++) {
                 i32 y = rows[i];
+                i64 dy = deg_of(rp, y);
                 for (i64 r = rp[y]; r < rp[y + 1]; r++) mark[col[r]] = 1;
                 for (i64 r = rp[y]; r < rp[y + 1]; r++) {
                     i32 z = col[r];
                     i32 c = 0;
-                    for (i64 u = rp[z]; u < rp[z + 1]; u++) c += mark[col[u]];
+                    if (deg_of(rp, z) <= 16 * dy) {
+                        for (i64 u = rp[z]; u < rp[z + 1]; u++) c += mark[col[u]];
+                    } else {
+                        for (i64 u = rp[y]; u < rp[y + 1]; u++) c += slot_of(rp, col, z, col[u]) >= 0;
+                    }
                     tri_scratch[r] = c;
                 }
                 for (i64 r = rp[y]; r < rp[y + 1]; r++) mark[col[r]] = 0;
@@ -887,6 +903,48 @@ int oref_stage23_at(i32 n, const i64 *rp, const i32 *col, const i32 *tri, i32 nq
         scratch_free(&sc);
         free(inx);
         free(ina);
+    }
+    return err;
+}
+
+/* psi_8 of selected vertices from its definition: the 4-cycles through x are the
+ * pairs of common neighbours of x and a vertex z != x opposite it, so psi_8(x) =
+ * sum over z != x of C(|N(x) and N(z)|, 2), with the common neighbours counted
+ * over every path x - y - z.  out int64[nq]. */
+int oref_cycles4_at(i32 n, const i64 *rp, const i32 *col, i32 nq, const i32 *xs, i64 *out)
+{
+    if (n < 0 || nq < 0 || (nq > 0 && (!rp || !col || !xs || !out))) return ORACLE_EINVAL;
+    for (i32 q = 0; q < nq; q++) if (xs[q] < 0 || xs[q] >= n) return ORACLE_EINVAL;
+    int err = 0;
+#pragma omp parallel
+    {
+        i64 *common = (i64 *)calloc((size_t)(n ? n : 1), sizeof(i64));
+        i32 *touched = (i32 *)malloc(sizeof(i32) * (size_t)(n ? n : 1));
+        if (!common || !touched) {
+#pragma omp atomic write
+            err = ORACLE_ENOMEM;
+        } else {
+#pragma omp for schedule(dynamic, 1)
+            for (i32 q = 0; q < nq; q++) {
+                i32 x = xs[q];
+                i64 nt = 0, total = 0;
+                for (i64 s = rp[x]; s < rp[x + 1]; s++) {
+                    i32 y = col[s];
+                    for (i64 r = rp[y]; r < rp[y + 1]; r++) {
+                        i32 z = col[r];
+                        if (z == x) continue;
+                        if (common[z]++ == 0) touched[nt++] = z;
+                    }
+                }
+                for (i64 i = 0; i < nt; i++) {
+                    total += common[touched[i]] * (common[touched[i]] - 1) / 2;
+                    common[touched[i]] = 0;
+                }
+                out[q] = total;
+            }
+        }
+        free(common);
+        free(touched);
     }
     return err;
 }

@@ -63,11 +63,11 @@ def column_identities(psi, g, tri_edges, c4, k4):
     assert s[12] == 2 * dia and s[13] == 2 * dia
 
 
-# The oracle's per-vertex Stage III visits every pair of neighbours of a sampled
-# vertex; above this degree that alone takes minutes of one CPU thread (R-MAT's
-# largest hub, d = 162,951, has 1.3e10 pairs), so such vertices are checked through
-# the identities only.
-SAMPLE_MAX_DEG = 100_000
+# The oracle's per-vertex Stages II and III visit every pair of neighbours of a
+# sampled vertex and every triangle through it; above this degree that takes minutes
+# of one CPU thread on R-MAT, whose hubs are adjacent to each other.  The highest
+# degrees are checked column by column through the direct forms instead.
+SAMPLE_MAX_DEG = 5000
 
 
 def sample_vertices(g, rng):
@@ -80,7 +80,43 @@ def sample_vertices(g, rng):
     # ranks just inside and just outside the heavy range, and in its middle
     ranks = [g.n - HEAVY_K - 1, g.n - HEAVY_K, g.n - HEAVY_K // 2, g.n - 2 * HEAVY_K]
     edge = order[[r for r in ranks if 0 <= r < g.n]]
+    edge = edge[d[edge] <= SAMPLE_MAX_DEG]
     return np.unique(np.concatenate([uniform, mids, top, edge])).astype(np.int32)
+
+
+def direct_forms(g, tri, xs, oracle):
+    """Columns of psi for the vertices xs from their definitions, given the oracle's
+    Stage I counts tri of every slot: the counts of 2- and 3-vertex graphlets, the
+    3-star, 4-path and tailed-triangle orbits from degrees and per-edge triangles,
+    4-cycles through x (oracle.cycles4_at) and the diamond's degree-3 orbit.  Returns
+    {column: int64[len(xs)]}; columns 12 and 14 (triangles of triangles) are left to
+    the whole-graph identities."""
+    d = g.degrees().astype(np.int64)
+    rp = g.row_ptr
+    t = tri.astype(np.int64)
+    cs = np.concatenate([[0], np.cumsum(t)])
+    T = (cs[rp[1:]] - cs[rp[:-1]]) // 2                      # triangles at every vertex
+    dn = d[g.col] - 1
+    cd = np.concatenate([[0], np.cumsum(dn)])
+    psi1 = cd[rp[1:]] - cd[rp[:-1]]                           # sum over N(v) of d - 1
+    out = {k: np.zeros(len(xs), np.int64) for k in (0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 13)}
+    for i, x in enumerate(xs):
+        a, b = rp[x], rp[x + 1]
+        nb, tx, dx = g.col[a:b], t[a:b], d[x]
+        out[0][i] = dx
+        out[1][i] = psi1[x]
+        out[2][i] = dx * (dx - 1) // 2
+        out[3][i] = T[x]
+        out[4][i] = psi1[nb].sum() - dx * (dx - 1) - 2 * T[x]   # ends of 4-paths x-a-b-c
+        out[5][i] = (dx - 1) * psi1[x] - 2 * T[x]                # inner vertex of 4-paths
+        out[6][i] = ((d[nb] - 1) * (d[nb] - 2) // 2).sum()       # leaf of a 3-star at a neighbour
+        out[7][i] = dx * (dx - 1) * (dx - 2) // 6
+        out[9][i] = (T[nb] - tx).sum()                           # tail of a tailed triangle
+        out[10][i] = (tx * (d[nb] - 2)).sum()                    # its degree-2 triangle vertices
+        out[11][i] = T[x] * (dx - 2)                             # its hub
+        out[13][i] = (tx * (tx - 1) // 2).sum()                  # diamond, degree 3
+    out[8] = oracle.cycles4_at(g.row_ptr, g.col, np.asarray(xs, np.int32))
+    return out
 
 
 def _count(ni, rp, cl, **kw):
@@ -114,24 +150,36 @@ def _full_size(workload, extra):
         ctx.close()
     del rp, cl, psi_d
     torch.cuda.empty_cache()
-    _say(f"[gpu] {workload} counted; whole-graph oracle counts")
+    _say(f"[gpu] {workload} counted; oracle Stage I over every edge")
+    t0 = time.time()
+    tri_o = oracle.stage1(g.row_ptr, g.col)
+    _say(f"[gpu] {workload} oracle Stage I in {time.time() - t0:.0f}s")
+    assert np.array_equal(tri, tri_o)  # Stage I, every slot
+    del tri
     t0 = time.time()
     c4 = oracle.cycles4_total(g.row_ptr, g.col)
     k4 = oracle.k4_total(g.row_ptr, g.col)
     _say(f"[gpu] {workload} #C4={c4} #K4={k4} in {time.time() - t0:.0f}s; identities")
-    column_identities(psi, g, tri, c4, k4)
+    column_identities(psi, g, tri_o, c4, k4)
     C = subgraph_matrix()
     assert np.array_equal(ind @ C.T, psi)
-    del ind, tri
+    del ind
     xs = sample_vertices(g, np.random.default_rng(2024))
     t0 = time.time()
-    ref = oracle.orbits_at(g.row_ptr, g.col, xs)
-    _say(f"[gpu] oracle on {len(xs)} vertices of {workload} (max degree {g.degrees()[xs].max()}) "
-         f"in {time.time() - t0:.0f}s")
+    ref = oracle.stage23_at(g.row_ptr, g.col, tri_o, xs)
+    _say(f"[gpu] oracle Stages II-III on {len(xs)} vertices of {workload} "
+         f"(max degree {g.degrees()[xs].max()}) in {time.time() - t0:.0f}s")
     if not np.array_equal(psi[xs], ref):
         bad = np.argwhere(psi[xs] != ref)
         pytest.fail(f"{len(bad)} sampled entries differ; first (vertex, orbit) "
                     f"{[(int(xs[i]), int(k)) for i, k in bad[:6]]}")
+    d = g.degrees()
+    hubs = np.lexsort((np.arange(g.n), d))[-8:].astype(np.int32)
+    t0 = time.time()
+    forms = direct_forms(g, tri_o, hubs, oracle)
+    _say(f"[gpu] direct forms on the 8 highest degrees (up to {d[hubs].max()}) in {time.time() - t0:.0f}s")
+    for k, want in forms.items():
+        assert np.array_equal(psi[hubs, k], want), (k, hubs.tolist(), psi[hubs, k].tolist(), want.tolist())
 
 
 def _rmat_extra(ni, ctx, g, rp, cl, psi_d):
@@ -158,9 +206,9 @@ def _rmat_extra(ni, ctx, g, rp, cl, psi_d):
     ek_h = ek.cpu().numpy()
     del ek
     k4v = psi_d[:, 14].cpu().numpy()
-    rows = np.add.reduceat(ek_h, g.row_ptr[:-1])
-    rows[g.degrees() == 0] = 0
-    assert np.array_equal(rows, 3 * k4v)
+    cs = np.concatenate([[0], np.cumsum(ek_h)])
+    assert np.array_equal(cs[g.row_ptr[1:]] - cs[g.row_ptr[:-1]], 3 * k4v)
+    del cs
     rng = np.random.default_rng(7)
     d = g.degrees()
     src = np.repeat(np.arange(g.n), d)

@@ -235,6 +235,7 @@ MUTANTS = {
                                       [("total += __builtin_popcountll(rows[i * words + x] & rows[p * words + x]);",
                                         "total += (x == 0);")]),
     "edge_k4_ends_not_halved": ("oref_edge_k4", [("ek4[q] = ends / 2;", "ek4[q] = ends;")]),
+    "c4_at_counts_x_itself": ("oref_cycles4_at", [("                        if (z == x) continue;\n", "")]),
     "edge_k4_union_not_common": ("oref_edge_k4", [("else { w[nw++] = col[i]; i++; j++; }",
                                                    "else { w[nw++] = col[i]; i++; j++; }\n                }\n"
                                                    "                while (i < rp[a + 1]) { if (col[i] != b) "
@@ -257,7 +258,12 @@ def _call(lib, fn, g):
     P = ctypes.c_void_p
     rp, cl = g.row_ptr.ctypes.data_as(P), g.col.ctypes.data_as(P)
     f = getattr(lib, fn)
-    if fn == "oref_enum_induced":
+    if fn == "oref_cycles4_at":
+        out = np.zeros(g.n, np.int64)
+        f.argtypes = [ctypes.c_int32, P, P, ctypes.c_int32, P, P]
+        xs = np.arange(g.n, dtype=np.int32)
+        rc = f(g.n, rp, cl, g.n, xs.ctypes.data_as(P), out.ctypes.data_as(P))
+    elif fn == "oref_enum_induced":
         out = np.zeros((g.n, 15), np.int64)
         f.argtypes = [ctypes.c_int32, P, P, P]
         rc = f(g.n, rp, cl, out.ctypes.data_as(P))
@@ -273,6 +279,8 @@ def _call(lib, fn, g):
 
 
 def _expected(fn, g):
+    if fn == "oref_cycles4_at":
+        return brute.orbit_counts_csr(g.row_ptr, g.col)[:, 8]
     if fn == "oref_enum_induced":
         return brute.orbit_counts_csr(g.row_ptr, g.col, induced=True)
     if fn == "oref_edge_k4":
@@ -305,7 +313,36 @@ def test_pins_reject_global_mutant(name, mutant_graphs):
 def test_unmutated_global_functions_pass(mutant_graphs):
     with tempfile.TemporaryDirectory() as td:
         lib = _build("clean", [], td)
-        for fn in ("oref_enum_induced", "oref_cycles4_total", "oref_k4_total", "oref_edge_k4"):
+        for fn in ("oref_enum_induced", "oref_cycles4_total", "oref_k4_total", "oref_edge_k4", "oref_cycles4_at"):
             for g in mutant_graphs:
                 rc, out = _call(lib, fn, g)
                 assert rc == 0 and np.array_equal(out, _expected(fn, g)), (fn, g.name)
+
+
+def test_cycles4_at_vs_enumeration(oracle_lib):
+    """psi_8 of selected vertices from common-neighbour pairs equals the definition-
+    level enumeration's column 8."""
+    for g in [gg.config_graph("er_tiny"), gg.chung_lu(3000, 2.2, 8.0, 300.0, seed=2),
+              gg.planted_cliques(400, 0.02, [14, 10, 8, 6], seed=6), gg.complete(12)]:
+        xs = np.unique(np.concatenate([np.arange(0, g.n, 3), np.argsort(-g.degrees())[:4]])).astype(np.int32)
+        ref = oracle_lib.enum_count(g.row_ptr, g.col)[xs, 8]
+        assert np.array_equal(oracle_lib.cycles4_at(g.row_ptr, g.col, xs), ref)
+
+
+@pytest.mark.parametrize("make", [
+    lambda: gg.config_graph("er_tiny"),
+    lambda: gg.chung_lu(3000, 2.2, 8.0, 300.0, seed=2),
+    lambda: gg.planted_cliques(400, 0.02, [14, 10, 8, 6], seed=6),
+    lambda: gg.barabasi_albert(600, 5, seed=8),
+    lambda: gg.complete(11),
+])
+def test_direct_forms_vs_enumeration(oracle_lib, make):
+    """The per-column direct forms the full-size GPU test applies to the highest-degree
+    vertices, against the definition-level enumeration."""
+    from test_gpu_fullsize import direct_forms
+    g = make()
+    ref = oracle_lib.enum_count(g.row_ptr, g.col)
+    tri = oracle_lib.stage1(g.row_ptr, g.col)
+    xs = np.unique(np.concatenate([np.arange(0, g.n, 4), np.argsort(-g.degrees())[:5]])).astype(np.int32)
+    for k, got in direct_forms(g, tri, xs, oracle_lib).items():
+        assert np.array_equal(got, ref[xs, k]), k
