@@ -145,6 +145,24 @@ niorca_status niorca_set_param(niorca_ctx *ctx, const char *name, int64_t value)
 niorca_status niorca_count(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
                            const int32_t *col, int64_t *out, void *stream, uint32_t flags);
 
+/* niorca_count for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same computation,
+ * with the workspace in a fixed device array of NIORCA_NOALLOC_BYTES that the
+ * library holds on every GPU it runs on until the process ends; the call makes no
+ * hipMalloc, hipFree or other allocation.  Graphs whose workspace does not fit are
+ * refused with ENOMEM, the message giving the size needed (about 12 bytes per CSR
+ * slot and 300 per vertex, plus 16 MiB when the graph has hubs: 10^5 vertices with
+ * 2x10^6 edges fit); Stage I triangles that do not fit the space left are probed
+ * again in the tau pass, which changes no count.
+ * Flags: VALIDATE, BIN_DEGREE, BIN_MLP, INDUCED (not TIMING or COUNTERS).  Every
+ * call on a GPU shares that GPU's array, whatever the context: calls that overlap
+ * in time on one GPU race and give wrong counts.  Afterwards niorca_device_status
+ * reads the shared array (valid until the next call on the device), and the
+ * per-vertex introspection calls (counters, features, class statistics) refuse. */
+#define NIORCA_NOALLOC_BYTES (128ull << 20)
+niorca_status niorca_count_noalloc(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
+                                   const int32_t *col, int64_t *out, void *stream, uint32_t flags);
+
 /* Many small graphs in one call.  Graph g owns vertices vtx_off[g]..vtx_off[g+1]-1
  * of a packed CSR whose row_ptr is global (device int64[total_n+1], nnz = row_ptr[total_n])
  * and whose column ids are LOCAL to the graph (0..n_g-1); out is device

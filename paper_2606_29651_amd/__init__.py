@@ -35,7 +35,7 @@ EXPORTS = ["niorca_create", "niorca_destroy", "niorca_last_error", "niorca_set_w
            "niorca_edge_triangles", "niorca_k4", "niorca_fvars", "niorca_work_counters",
            "niorca_set_cost_model", "niorca_stage_times", "niorca_last_features", "niorca_mlp_train",
            "niorca_mlp_predict", "niorca_kernel_times", "niorca_class_stats", "niorca_edge_k4",
-           "niorca_device_status", "niorca_load_tuning"]
+           "niorca_device_status", "niorca_load_tuning", "niorca_count_noalloc"]
 KERNEL_NAMES = ["probe_thread", "probe_wave", "probe_block", "probe_large", "ql_wave", "ql_block", "ql_global",
                 "qh_wave", "qh_block", "qh_dense", "qh_global", "probe_group"]
 CLASS_NAMES = ["tri_wave", "tri_thread", "tri_block", "tri_large", "ql_wave", "ql_block", "ql_global",
@@ -77,6 +77,7 @@ def load_library():
         lib.niorca_set_param.argtypes = [P, ctypes.c_char_p, i64]
         lib.niorca_count.argtypes = [P, i32, i64, P, P, P, P, u32]
         lib.niorca_count_batched.argtypes = [P, i32, P, i64, P, P, P, P, u32]
+        lib.niorca_count_noalloc.argtypes = [P, i32, i64, P, P, P, P, u32]
         lib.niorca_edge_triangles.argtypes = [P, i32, i64, P, P, P, P]
         lib.niorca_k4.argtypes = [P, i32, i64, P, P, P, P]
         lib.niorca_edge_k4.argtypes = [P, i32, i64, P, P, P, P]
@@ -210,6 +211,19 @@ def count(row_ptr: torch.Tensor, col: torch.Tensor, flags: int = 0, out: torch.T
         out = torch.empty((n, 15), dtype=torch.int64, device=row_ptr.device)
     ctx.check(ctx.lib.niorca_count(ctx.h, n, nnz, _p(row_ptr), _p(col), _p(out), _stream_ptr(stream), flags),
               "niorca_count")
+    return out
+
+
+def count_noalloc(row_ptr: torch.Tensor, col: torch.Tensor, out: torch.Tensor, flags: int = 0,
+                  ctx: Context = None, stream=None) -> torch.Tensor:
+    """count() into a caller-provided out (int64[n, 15]) with the library's fixed
+    device scratch as workspace: no device allocation in the call."""
+    row_ptr, col, n, nnz = _graph(row_ptr, col)
+    ctx = ctx or context(row_ptr.device.index)
+    if out.dtype != torch.int64 or out.shape != (n, 15) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous int64 tensor of shape (n, 15)")
+    ctx.check(ctx.lib.niorca_count_noalloc(ctx.h, n, nnz, _p(row_ptr), _p(col), _p(out), _stream_ptr(stream),
+                                           flags), "niorca_count_noalloc")
     return out
 
 

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -46,7 +47,37 @@ struct niorca_ctx {
     int64_t tri_cache_records = (int64_t)1 << 32;  // at most 32 GiB of kept triangles for the tau pass
     int64_t large_lds_max = PL_LDS_MAX;            // LDS bytes the large probe kernel may take
     int bin_default = 0;  // binning of calls whose flags ask for none: 0 none, 1 degree, 2 learned
+    // set for the duration of a niorca_count_noalloc call: the fixed scratch it runs in
+    char *fixed_ws = nullptr;
+    uint64_t fixed_bytes = 0;
 };
+
+// ---------------------------------------------------------------------------
+// The fixed workspace of niorca_count_noalloc: one device array, of which every GPU
+// the library runs on holds its own copy until the process ends.  Host code never
+// passes `scratch` itself to a kernel (in host code the name is a stand-in, not a
+// device address): niorca_create looks up each device's address of it once, with
+// that device current, and every later use goes through that address.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[NIORCA_NOALLOC_BYTES];
+#define MAX_DEVICES 64
+static char *g_scratch[MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// Device address of `scratch` on the current device `device` (looked up once).
+static hipError_t scratch_address(int device, char **out) {
+    *out = nullptr;
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch[device] = (char *)p;
+    }
+    *out = g_scratch[device];
+    return hipSuccess;
+}
 
 static niorca_status fail(niorca_ctx *c, niorca_status s, const char *fmt, ...) {
     char buf[512];
@@ -105,6 +136,12 @@ extern "C" niorca_status niorca_create(niorca_ctx **out, int device) {
     if (hipSetDevice(device) != hipSuccess) return NIORCA_EDEVICE;
     niorca_ctx *c = new niorca_ctx();
     c->device = device;
+    char *sp = nullptr;
+    if (scratch_address(device, &sp) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return NIORCA_EDEVICE;
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cu = prop.multiProcessorCount;
@@ -365,11 +402,12 @@ static int32_t heavy_range(const niorca_ctx *ctx, int32_t n, int64_t nnz, int dm
     return (int64_t)dmax > 8 * (mean > 1 ? mean : 1) ? QH_DENSE_K : 0;
 }
 
-static void layout_rest(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz, int dmax, int dplus_max,
-                        i64 pairs, bool bounded, Arena &A) {
+// small: a fixed workspace (niorca_count_noalloc), where the scratch of the large
+// Stage I class and of the 4-cycle global counters is kept to a few slices.
+static void layout_rest_with(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz, int dmax, int dplus_max,
+                             i64 tc_cap, bool bounded, bool small, Arena &A) {
     const int cu = ctx->num_cu;
-    // triangle records for the tau pass: no more than the graph can have
-    L.tc_cap = ctx->tri_cache_records < pairs ? ctx->tri_cache_records : pairs;
+    L.tc_cap = tc_cap;
     L.tcrec = A.take<u64>((uint64_t)(L.tc_cap > 0 ? L.tc_cap : 1));
     const int32_t hk = heavy_range(ctx, n, nnz, dmax, bounded);
     L.h0 = n > hk ? n - hk : 0;
@@ -377,7 +415,7 @@ static void layout_rest(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz
     L.large_cap = dplus_max > ctx->th.tri_block ? dplus_max : 0;
     L.large_hc = 1;
     while (L.large_hc < 2 * L.large_cap) L.large_hc <<= 1;
-    L.large_blocks = L.large_cap ? 2 * cu : 0;
+    L.large_blocks = L.large_cap ? (small ? (2 * cu < 32 ? 2 * cu : 32) : 2 * cu) : 0;
     L.large_slice = L.large_cap ? probe_large_slice_bytes(L.large_cap, L.large_hc, ctx->large_lds_max) : 0;
     L.large = A.take<char>((uint64_t)L.large_slice * L.large_blocks);
     L.part_rows = QH_PART_ROWS;
@@ -385,6 +423,8 @@ static void layout_rest(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz
     // int32 counters over all vertices for the rare 4-cycle items that overflow LDS
     if (bounded) {
         L.gblocks = 2;
+    } else if (small) {
+        L.gblocks = 8;
     } else {
         // one slice per CU, within 8 GiB of the 288 GB
         const i64 fit = ((i64)8 << 30) / ((2 * (i64)n + 64) * 4);
@@ -393,6 +433,23 @@ static void layout_rest(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz
     L.gslice = 2 * (i64)n + 64;
     L.gcnt = A.take<i32>((uint64_t)L.gslice * L.gblocks);
     L.total = A.off;
+}
+
+// budget > 0: the layout must end within budget bytes (a fixed workspace); the
+// triangle records kept for the tau pass then get what the rest leaves (vertices
+// whose records do not fit are probed again).
+static void layout_rest(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz, int dmax, int dplus_max,
+                        i64 pairs, bool bounded, Arena &A, uint64_t budget = 0) {
+    // triangle records for the tau pass: no more than the graph can have
+    i64 cap = ctx->tri_cache_records < pairs ? ctx->tri_cache_records : pairs;
+    if (budget) {
+        Layout D = L;
+        Arena B = A;
+        layout_rest_with(D, ctx, n, nnz, dmax, dplus_max, 0, bounded, true, B);
+        const i64 room = B.off < budget ? (i64)((budget - B.off) / sizeof(u64)) : 0;
+        if (cap > room) cap = room;
+    }
+    layout_rest_with(L, ctx, n, nnz, dmax, dplus_max, cap, bounded, budget != 0, A);
 }
 
 // Fill kernels (no memset nodes: the sequence may be captured into a hipGraph).
@@ -441,11 +498,20 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     if (hb) layout_rest(L, ctx, n, nnz, hb->dmax, hb->dplus_max, BOUNDED_TRI_CACHE, true, A);
     const uint64_t need_now = hb ? A.off : L.base_end;
 
+    // a fixed workspace (niorca_count_noalloc) is never allocated, only checked
+    const bool fixed = ctx->fixed_ws != nullptr;
+    auto have = [&](uint64_t need) -> niorca_status {
+        if (!fixed) return ensure_ws(ctx, need);
+        if (need > ctx->fixed_bytes)
+            return fail(ctx, NIORCA_ENOMEM, "this graph needs %llu bytes of workspace; the fixed scratch holds %llu",
+                        (unsigned long long)need, (unsigned long long)ctx->fixed_bytes);
+        return NIORCA_OK;
+    };
     // Validation first (it reads only the input).
     if (flags & NIORCA_VALIDATE) {
-        niorca_status st = ensure_ws(ctx, need_now);
+        niorca_status st = have(need_now);
         if (st) return st;
-        int *bad = (int *)(ctx->ws + L.st);
+        int *bad = (int *)((fixed ? ctx->fixed_ws : ctx->ws) + L.st);
         HIP_TRY(fill32(bad, sizeof(int), 0u, s));
         if (n > 0) hipLaunchKernelGGL(k_validate, dim3(cu * 8), dim3(nthr), 0, s, n, nnz, rp, col, bad);
         HIP_TRY(hipGetLastError());
@@ -456,10 +522,10 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     }
     if (n == 0) return NIORCA_OK;
     {
-        niorca_status st = ensure_ws(ctx, need_now);
+        niorca_status st = have(need_now);
         if (st) return st;
     }
-    char *W = ctx->ws;
+    char *W = fixed ? ctx->fixed_ws : ctx->ws;
     GraphStats *dst = (GraphStats *)(W + L.st);
     u32 *deg = (u32 *)(W + L.deg), *val = (u32 *)(W + L.val), *k2 = (u32 *)(W + L.k2), *v2 = (u32 *)(W + L.v2);
     i32 *hist = (i32 *)(W + L.hist), *scanw = (i32 *)(W + L.scan);
@@ -505,11 +571,11 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
             return fail(ctx, NIORCA_EOVERFLOW, "maximum degree %d could overflow int64 counts", hs.dmax);
         if (hs.dplus_max > LSORT_CAP)
             return fail(ctx, NIORCA_ENOTIMPL, "an oriented out-degree of %d exceeds %d", hs.dplus_max, LSORT_CAP);
-        layout_rest(L, ctx, n, nnz, hs.dmax, hs.dplus_max, hs.pairs, false, A);
-        niorca_status st = ensure_ws(ctx, A.off);
+        layout_rest(L, ctx, n, nnz, hs.dmax, hs.dplus_max, hs.pairs, false, A, fixed ? ctx->fixed_bytes : 0);
+        niorca_status st = have(A.off);
         if (st) return st;
         // The workspace grew and moved: start again; this time it is large enough.
-        if (ctx->ws != W) return run(ctx, n, nnz, rp, col, o, s, flags & ~(uint32_t)NIORCA_VALIDATE, hb);
+        if (!fixed && ctx->ws != W) return run(ctx, n, nnz, rp, col, o, s, flags & ~(uint32_t)NIORCA_VALIDATE, hb);
     } else {
         hs.dmax = hb->dmax;
         hs.dplus_max = hb->dplus_max;
@@ -521,9 +587,11 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     // The global 4-cycle counters are returned to zero by the kernels that use them,
     // so they are cleared only when their place in the workspace changes -- and on
     // every bounded (possibly captured) run, whose replays may follow other calls.
-    if (hb || ctx->gz_ws != W || ctx->gz_off != L.gcnt || ctx->gz_bytes != (uint64_t)L.gslice * L.gblocks * 4) {
+    // A fixed workspace is shared by every context on the device: always cleared.
+    if (hb || fixed || ctx->gz_ws != W || ctx->gz_off != L.gcnt ||
+        ctx->gz_bytes != (uint64_t)L.gslice * L.gblocks * 4) {
         HIP_TRY(fill32(gscratch, (i64)L.gslice * L.gblocks * 4, 0u, s));
-        ctx->gz_ws = W;
+        ctx->gz_ws = fixed ? nullptr : W;
         ctx->gz_off = L.gcnt;
         ctx->gz_bytes = (uint64_t)L.gslice * L.gblocks * 4;
     }
@@ -658,6 +726,30 @@ extern "C" niorca_status niorca_count(niorca_ctx *ctx, int32_t n, int64_t nnz, c
     Outputs o;
     o.psi = out;
     return run(ctx, n, nnz, row_ptr, col, o, as_stream(stream), flags, nullptr);
+}
+
+extern "C" niorca_status niorca_count_noalloc(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
+                                              const int32_t *col, int64_t *out, void *stream, uint32_t flags) {
+    niorca_status st = check_graph_args(ctx, n, nnz, row_ptr, col);
+    if (st) return st;
+    if (n > 0 && !out) return fail(ctx, NIORCA_EINVAL, "out is NULL");
+    const uint32_t known = NIORCA_VALIDATE | NIORCA_BIN_DEGREE | NIORCA_BIN_MLP | NIORCA_INDUCED;
+    if (flags & ~known) return fail(ctx, NIORCA_EINVAL, "unknown or unsupported flag bits 0x%x", flags & ~known);
+    if ((flags & NIORCA_BIN_MLP) && !ctx->mlp_dev)
+        return fail(ctx, NIORCA_EINVAL, "NIORCA_BIN_MLP needs a cost model (niorca_set_cost_model)");
+    if ((flags & NIORCA_BIN_MLP) && (flags & NIORCA_BIN_DEGREE))
+        return fail(ctx, NIORCA_EINVAL, "choose one of NIORCA_BIN_MLP and NIORCA_BIN_DEGREE");
+    HIP_TRY(hipSetDevice(ctx->device));
+    char *sp = nullptr;
+    HIP_TRY(scratch_address(ctx->device, &sp));
+    Outputs o;
+    o.psi = out;
+    ctx->fixed_ws = sp;
+    ctx->fixed_bytes = NIORCA_NOALLOC_BYTES;
+    st = run(ctx, n, nnz, row_ptr, col, o, as_stream(stream), flags, nullptr);
+    ctx->fixed_ws = nullptr;
+    ctx->fixed_bytes = 0;
+    return st;
 }
 
 extern "C" niorca_status niorca_edge_triangles(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t *row_ptr,
@@ -980,11 +1072,17 @@ extern "C" niorca_status niorca_kernel_times(niorca_ctx *ctx, float *ms, int32_t
 extern "C" niorca_status niorca_device_status(niorca_ctx *ctx, void *stream) {
     if (!ctx) return NIORCA_EINVAL;
     ctx->err.clear();
-    if (!ctx->ws || ctx->last_ws != ctx->ws) return NIORCA_OK;  // nothing counted on this workspace yet
+    // the last call's statistics: in the context's workspace, or in the fixed scratch
+    // after niorca_count_noalloc (until the next call on the device overwrites it)
+    char *sp = nullptr;
+    if (ctx->last_ws && ctx->last_ws != ctx->ws && scratch_address(ctx->device, &sp) == hipSuccess &&
+        ctx->last_ws != sp)
+        return NIORCA_OK;
+    if (!ctx->last_ws) return NIORCA_OK;  // nothing counted yet
     HIP_TRY(hipSetDevice(ctx->device));
     hipStream_t s = as_stream(stream);
     GraphStats hs;
-    HIP_TRY(hipMemcpyAsync(&hs, ctx->ws + ctx->last_stats_dev, sizeof hs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&hs, ctx->last_ws + ctx->last_stats_dev, sizeof hs, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (hs.bad_input)
         return fail(ctx, NIORCA_EINVAL, "row_ptr or col held values outside the graph or its degree bound");
