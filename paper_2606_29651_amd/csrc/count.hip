@@ -343,13 +343,9 @@ __device__ __forceinline__ void seg_map_scan(const i32 *off, int len, i32 eb, i3
 // kernels then carries that per-slot int64 array).
 enum { PROBE_TRI = 0, PROBE_TAU = 1, PROBE_EK4 = 2 };
 
-#ifndef TAU_RK
 #define TAU_RK 4  // triangle records per thread in flight in the tau pass
-#endif
 
-#ifndef QS
 #define QS 8  // wedges per thread per step in the 4-cycle sweeps
-#endif
 
 // Row pitch (in words) of the bitset of H_u: odd, so that lanes reading word k of
 // consecutive rows hit distinct LDS banks.
@@ -415,7 +411,7 @@ __device__ __forceinline__ PMeta p_meta(const DevGraph &g, const TriCache &tc, i
     return m;
 }
 
-template <int NT, int MODE, int QP, int MP = 0, int MAXDU = (1 << 30), bool PMAP_SCAN = false>
+template <int NT, int MODE, int QP, int MP = 0, int MAXDU = (1 << 30)>
 __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, int tid, const ProbeMem &M, int hc,
                                            int pitch, i32 *__restrict__ t, i64 *__restrict__ K4,
                                            i64 *__restrict__ tau, i64 *red, i32 *red32, const TriCache &tc,
@@ -550,12 +546,8 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
                 }
                 if (FEW || mapped) {
                     item_sync<NT>();  // the previous block's map has been read
-                    if constexpr (PMAP_SCAN && NT >= WAVE) {
-                        seg_map_scan<NT, MP>(M.off, du, eb, total, tid, M.seg, red32, FEW ? 0 : sfirst);
-                    } else {
-                        q_segmap<NT, MP>(M.off, du, eb, total, tid, M.seg, FEW ? 0 : sfirst);
-                        item_sync<NT>();
-                    }
+                    q_segmap<NT, MP>(M.off, du, eb, total, tid, M.seg, FEW ? 0 : sfirst);
+                    item_sync<NT>();
                 }
             }
             if (FEW || mapped) {
@@ -722,31 +714,13 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
 }
 
 // One wave per vertex, |N+(u)| <= 64, four items per 256-thread block.
-#ifndef PW_QP
 #define PW_QP 4   // probes per thread and round, wave items
-#endif
-#ifndef PB_QP
 #define PB_QP 8   // probes per thread and round, workgroup items
-#endif
-#ifndef PL_QP
 #define PL_QP 4   // probes per thread and round, large items
-#endif
-#ifndef PW_MP
 #define PW_MP 16  // probes per thread of a segment-map block, wave items (0: search)
-#endif
-#ifndef PB_MP
 #define PB_MP 8   // the same, workgroup items
-#endif
-#ifndef PW_MAPSCAN
-#define PW_MAPSCAN 0  // Stage I maps built by seg_map_scan (1) or q_segmap (0)
-#endif
-#ifndef PB_MAPSCAN
-#define PB_MAPSCAN 0
-#endif
-#ifndef PW_WPE
 #define PW_WPE 8  // waves per SIMD the wave kernel is compiled for: 64 registers (with
                   // one register more a SIMD holds a wave less, measured 30 % slower)
-#endif
 template <int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PW_WPE))) k_probe_wave(DevGraph g, const i32 *__restrict__ list,
                                                     const GraphStats *__restrict__ st, i32 *t, i64 *K4,
@@ -778,7 +752,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PW_WPE
         // the next item's row bounds and the one after's id load while this one runs
         const PMeta nxt = p_meta<MODE>(g, tc, un);
         un = it + 2 * waves < cnt ? list[it + 2 * waves] : -1;
-        probe_item<WAVE, MODE, PW_QP, PW_MP, CAP, PW_MAPSCAN>(g, cur, tid, M, HC, PITCH, t, K4, tau, nullptr, nullptr, tc,
+        probe_item<WAVE, MODE, PW_QP, PW_MP, CAP>(g, cur, tid, M, HC, PITCH, t, K4, tau, nullptr, nullptr, tc,
                                              &s_st[w], counters);
         cur = nxt;
     }
@@ -787,9 +761,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PW_WPE
 // Sixteen lanes per vertex, |N+(u)| <= TRI_GROUP_CAP (16 items per 256-thread block):
 // for items with little work, which would leave most of a wave idle.
 #define PG_NT 16
-#ifndef PG_QP
 #define PG_QP 4
-#endif
 template <int MODE>
 __global__ void __launch_bounds__(256) k_probe_group(DevGraph g, const i32 *__restrict__ list,
                                                      const GraphStats *__restrict__ st, i32 *t, i64 *K4,
@@ -826,9 +798,7 @@ __global__ void __launch_bounds__(256) k_probe_group(DevGraph g, const i32 *__re
 }
 
 // One PB_NT-thread workgroup per vertex, 64 < |N+(u)| <= TRI_BLOCK_CAP.
-#ifndef PB_NT
 #define PB_NT 512
-#endif
 template <int MODE>
 __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__restrict__ list,
                                                      const GraphStats *__restrict__ st, i32 *t, i64 *K4,
@@ -861,7 +831,7 @@ __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__
     for (; it < cnt; it += gridDim.x) {
         const PMeta nxt = p_meta<MODE>(g, tc, un);
         un = it + 2 * (i32)gridDim.x < cnt ? list[it + 2 * gridDim.x] : -1;
-        probe_item<PB_NT, MODE, PB_QP, PB_MP, CAP, PB_MAPSCAN>(g, cur, threadIdx.x, M, HC, PITCH, t, K4, tau, s_red, s_red32,
+        probe_item<PB_NT, MODE, PB_QP, PB_MP, CAP>(g, cur, threadIdx.x, M, HC, PITCH, t, K4, tau, s_red, s_red32,
                                                    tc, &s_st, counters);
         cur = nxt;
     }
@@ -1238,37 +1208,20 @@ struct QChunk {
     u32 *seg;    // segment byte of each wedge of a step (NT * max(QK, QS) bytes), or null
 };
 
-// How each 4-cycle kernel locates wedges (0 search, 1 q_segmap, 2 seg_map_scan): a
-// map costs LDS, and so occupancy, which the kernels win back by crediting middles
-// straight to Q instead of through per-segment sums in LDS.
-#ifndef QMAP_QLW
+// How each 4-cycle kernel locates wedges (0 a search per wedge, 2 a byte map built by
+// seg_map_scan), chosen per kernel by measurement: a map costs LDS, and so occupancy,
+// which the kernels win back by crediting middles straight to Q instead of through
+// per-segment sums in LDS.
 #define QMAP_QLW 2
-#endif
-#ifndef QMAP_QLB
 #define QMAP_QLB 2
-#endif
-#ifndef QMAP_QHW
 #define QMAP_QHW 2
-#endif
-#ifndef QMAP_QHB
 #define QMAP_QHB 0
-#endif
-#ifndef QMAP_QD
 #define QMAP_QD 2
-#endif
 // Which ones credit middles straight to Q (and so keep no per-segment sums in LDS).
-#ifndef QGMID_QHW
 #define QGMID_QHW 1
-#endif
-#ifndef QGMID_QHB
 #define QGMID_QHB 0
-#endif
-#ifndef QGMID_QLW
 #define QGMID_QLW 1
-#endif
-#ifndef QGMID_QLB
 #define QGMID_QLB 1
-#endif
 
 
 // Loads chunk [c0, c0+len) of the item's slots; returns its wedge count.
@@ -1372,7 +1325,7 @@ __device__ __forceinline__ QMeta q_meta(const DevGraph &g, i32 x) {
 // created a key's counter then credits C(c, 2) through cr, adds it to *local and
 // empties the counter, and the call returns true.  Otherwise (false) the counters
 // are left for the caller to harvest.
-// MAP: how wedges find their segments -- 0 a search each, 1 q_segmap, 2 seg_map_scan.
+// MAP: how wedges find their segments -- 0 a search each, otherwise seg_map_scan.
 // GMID: middles' credits go straight to Q (runs of lanes in one segment add once)
 // rather than through C.mid.
 template <int NT, int MODE, int QK = 0, int MAP = 0, bool GMID = false, typename Ctr, typename Credit>
@@ -1389,12 +1342,7 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                 int lo[QK];
                 i32 key[QK];
                 if constexpr (MAP > 0) {
-                    if constexpr (MAP == 1) {
-                        q_segmap<NT, QK>(C.off, ns, 0, total, tid, C.seg);
-                        item_sync<NT>();
-                    } else {
-                        seg_map_scan<NT, QK>(C.off, ns, 0, total, tid, C.seg, red32);
-                    }
+                    seg_map_scan<NT, QK>(C.off, ns, 0, total, tid, C.seg, red32);
 #pragma unroll
                     for (int j = 0; j < QK; j++) lo[j] = j < nj ? seg_at(C.seg, min(tid + j * NT, total - 1)) : 0;
                 } else {
@@ -1490,12 +1438,7 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                     const i32 mb = eb - eb % (NT * MQ);
                     if (mb == eb) {
                         item_sync<NT>();  // the previous block's map has been read
-                        if constexpr (MAP == 1) {
-                            q_segmap<NT, MQ>(C.off, len, eb, total, tid, C.seg);
-                            item_sync<NT>();
-                        } else {
-                            seg_map_scan<NT, MQ>(C.off, len, eb, total, tid, C.seg, red32);
-                        }
+                        seg_map_scan<NT, MQ>(C.off, len, eb, total, tid, C.seg, red32);
                     }
 #pragma unroll
                     for (int u = 0; u < QS; u++)
@@ -1589,9 +1532,7 @@ struct LightHash {
 };
 
 #define QLW_DC 64
-#ifndef QLW_QK
 #define QLW_QK 8
-#endif
 #define QLW_SEGB (QMAP_QLW ? WAVE * (QLW_QK > QS ? QLW_QK : QS) : 0)
 #define QLW_MIDB (QGMID_QLW ? 0 : 8 * QLW_DC)
 __host__ __device__ constexpr int qlw_wave_bytes(int hcw) {
@@ -1657,9 +1598,7 @@ __global__ void __launch_bounds__(256) k_q_wave(DevGraph g, const i32 *__restric
 // per item, at most hcb entries (dynamic LDS given with the launch).
 #define QLB_DC 256
 #define QLB_NT 256
-#ifndef QLB_QK
 #define QLB_QK 16
-#endif
 #define QLB_SEGB (QMAP_QLB ? QLB_NT * (QLB_QK > QS ? QLB_QK : QS) : 0)
 #define QLB_MIDB (QGMID_QLB ? 0 : 8 * QLB_DC)
 __host__ __device__ constexpr int qlb_bytes(int hcb) {
@@ -1823,15 +1762,9 @@ __device__ __forceinline__ void qh_item_packed(const DevGraph &g, const QMeta &m
 // One wave per item; the per-wave table size hcw (a power of two, at least twice
 // the class's wedge bound) comes with the launch, in dynamic LDS.
 #define QHW_DC 64
-#ifndef QHW_QK
 #define QHW_QK 8  // wedges per lane in registers: 512, the class's default bound
-#endif
-#ifndef QHW_WPE
 #define QHW_WPE 6  // waves per SIMD the heavy wave kernel is compiled for (80 registers)
-#endif
-#ifndef QHW_GRID
 #define QHW_GRID 6  // workgroups per CU (the class's grid is given per 4): all resident
-#endif
 #define QHW_SEGB (QMAP_QHW ? WAVE * (QHW_QK > QS ? QHW_QK : QS) : 0)
 #define QHW_MIDB (QGMID_QHW ? 0 : 8 * QHW_DC)
 __host__ __device__ constexpr int qhw_wave_bytes(int hcw) {
@@ -1869,19 +1802,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(QHW_WP
 
 #define QHB_HC QH_BLOCK_HC
 #define QHB_DC 256
-#ifndef QHB_QK
 #define QHB_QK 8  // wedges per thread kept in registers by the heavy workgroup kernel
                   // (2048, the class's default bound; 76 registers: six waves per SIMD)
-#endif
-#ifndef QHB_NT
 #define QHB_NT 256
-#endif
-#ifndef QHB_WPE
 #define QHB_WPE 1
-#endif
-#ifndef QHB_GRID
 #define QHB_GRID 6  // workgroups per CU (the class's grid is given per 4): all resident
-#endif
 // The table (hcb entries, a power of two at least twice the class's wedge bound)
 // comes with the launch in dynamic LDS.
 __global__ void __launch_bounds__(QHB_NT) __attribute__((amdgpu_waves_per_eu(QHB_WPE)))
@@ -1924,16 +1849,10 @@ __global__ void k_qh_reduce(const i64 *__restrict__ part, int rows, i32 K, i32 h
 }
 
 // Heavy largest vertices: dense 16-bit counters over [h0, n).
-#ifndef QD_NT
 #define QD_NT 1024  // 16 waves per workgroup, two workgroups per CU (LDS)
-#endif
-#ifndef QD_QK
 #define QD_QK 8  // wedges per thread kept in registers by the dense kernel
-#endif
 #define QD_DC 256
-#ifndef QD_WPE
 #define QD_WPE 8  // 64 registers: eight waves per SIMD
-#endif
 __global__ void __launch_bounds__(QD_NT) __attribute__((amdgpu_waves_per_eu(QD_WPE))) k_q_dense(DevGraph g, const i32 *__restrict__ list,
                                                    const GraphStats *__restrict__ st, i64 *Q, i64 *part, i32 Kp) {
     __shared__ u32 s_w[QH_DENSE_K / 2];

@@ -84,9 +84,7 @@ struct Thresholds {
 #define QL_BLOCK_HC 16384    // largest hash per workgroup, light 4-cycle items (sized per launch)
 #define QH_WAVE_HC 4096     // largest packed (key, count) table per wave (sized per launch)
 #define QH_BLOCK_HC 8192    // packed entries per workgroup
-#ifndef QH_PART_ROWS
 #define QH_PART_ROWS 64     // rows of heavy-key credits (8 per XCD)
-#endif
 #define QH_DENSE_K 32768    // size of the heavy key range (top-ranked vertices)
 #define QH_DENSE_DC 4096    // middles accumulated in LDS by the dense kernel (else global)
 
@@ -143,12 +141,8 @@ __global__ void k_sort_upper_large(const i32 *nrp, const i32 *nsplit, i32 *ncol,
 __global__ void k_mirror(i32 n, const u32 *ndeg, const i32 *nrp, const i32 *nsplit, const i32 *ncol,
                          const int4 *vmeta, i32 h0, i32 *mirror, i64 *wlight, i64 *wheavy, i64 *probes, float *feat);
 #define LSORT_CAP 16384
-#ifndef LSORT_NT
 #define LSORT_NT 512  // threads of the long-row sort
-#endif
-#ifndef LSORT_GRID
 #define LSORT_GRID 2  // its workgroups per CU (64 KiB of LDS each)
-#endif
 
 // count.hip
 hipError_t launch_classify(const DevGraph &g, const i64 *wl, const i64 *wh, const i64 *probes, const ListPtrs &lists,
