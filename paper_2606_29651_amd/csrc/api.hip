@@ -793,22 +793,20 @@ extern "C" niorca_status niorca_fvars(niorca_ctx *ctx, int32_t n, int64_t nnz, c
 }
 
 // Packed batch -> one disjoint union: column ids local to graph g become global by
-// adding vtx_off[g] (one wave per row; the graph of a row by binary search).  An id
-// outside [0, n_g) becomes -1, which the relabel pass refuses (bad_input).
-__global__ void k_localize(int32_t total_n, int32_t G, int64_t nnz, const int64_t *__restrict__ voff,
-                           const int64_t *__restrict__ rp, const int32_t *__restrict__ col,
-                           int32_t *__restrict__ colg) {
-    int waves = gridDim.x * (blockDim.x / WAVE);
-    int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
-    for (int32_t x = wid; x < total_n; x += waves) {
-        int lo = 0, hi = G;  // largest g with voff[g] <= x
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (voff[mid] <= x) lo = mid; else hi = mid;
-        }
-        const int32_t base = (int32_t)voff[lo], ng = (int32_t)(voff[lo + 1] - voff[lo]);
-        const int64_t b = rp[x], e = rp[x + 1];
-        if (b < 0 || e < b || e > nnz) continue;  // the degree pass refuses this row
+// adding vtx_off[g].  The slots of graph g are the contiguous range
+// [row_ptr[vtx_off[g]], row_ptr[vtx_off[g+1]]), so one wave per graph streams it
+// (coalesced, no per-row search).  An id outside [0, n_g) becomes -1, which the
+// relabel pass refuses (bad_input); a graph whose slot range leaves [0, nnz] is
+// skipped (the degree pass refuses its rows).
+__global__ void k_localize(int32_t G, int64_t nnz, const int64_t *__restrict__ voff, const int64_t *__restrict__ rp,
+                           const int32_t *__restrict__ col, int32_t *__restrict__ colg) {
+    const int waves = gridDim.x * (blockDim.x / WAVE);
+    const int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    for (int32_t g = wid; g < G; g += waves) {
+        const int64_t v0 = voff[g], v1 = voff[g + 1];
+        const int32_t base = (int32_t)v0, ng = (int32_t)(v1 - v0);
+        const int64_t b = rp[v0], e = rp[v1];
+        if (b < 0 || e < b || e > nnz) continue;
         for (int64_t s = b + lane_id(); s < e; s += WAVE) {
             const int32_t c = col[s];
             colg[s] = (c >= 0 && c < ng) ? c + base : -1;
@@ -873,8 +871,7 @@ extern "C" niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graph
     o.psi = out;
     const int cu = ctx->num_cu;
     if (!capture) {
-        hipLaunchKernelGGL(k_localize, dim3(cu * 8), dim3(256), 0, s, n, num_graphs, nnz, dvoff, row_ptr, col,
-                           colg);
+        hipLaunchKernelGGL(k_localize, dim3(cu * 8), dim3(256), 0, s, num_graphs, nnz, dvoff, row_ptr, col, colg);
         HIP_TRY(hipGetLastError());
         return run(ctx, n, nnz, row_ptr, colg, o, s, flags, &hb);
     }
@@ -893,8 +890,7 @@ extern "C" niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graph
             ctx->gexec = nullptr;
         }
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        hipLaunchKernelGGL(k_localize, dim3(cu * 8), dim3(256), 0, s, n, num_graphs, nnz, dvoff, row_ptr, col,
-                           colg);
+        hipLaunchKernelGGL(k_localize, dim3(cu * 8), dim3(256), 0, s, num_graphs, nnz, dvoff, row_ptr, col, colg);
         niorca_status rs = run(ctx, n, nnz, row_ptr, colg, o, s, flags & ~(uint32_t)NIORCA_GRAPH_CAPTURE, &hb);
         hipGraph_t graph = nullptr;
         hipError_t ce = hipStreamEndCapture(s, &graph);
