@@ -260,8 +260,56 @@ def stage1_work(c):
     return c[:, 0] + 4 * c[:, 1] + c[:, 2]
 
 
+def base_repeats(ni, ctx, rp, cl, out, k=5):
+    """ms of k single plain counts: the run-to-run spread the forms are compared against."""
+    import torch
+    res = []
+    for _ in range(k):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ni.count(rp, cl, out=out, ctx=ctx)
+        torch.cuda.synchronize()
+        res.append(1000.0 * (time.perf_counter() - t0))
+    return res
+
+
+def judge_binning(ni, ctx, g, rp, cl, model):
+    """Measured work of the Stage I/II items (shader-clock cycles per item, the
+    counters' last column) under the plain, degree-binned and MLP-binned forms on a
+    graph the model was not trained on: the model's error against log2(1 + cycles)
+    of the plain form, and per form the spread of the item cycles (p99 and maximum
+    over the mean: the load imbalance the binning is meant to reduce) and the total."""
+    import torch
+    out = {}
+    for name, flags in (("plain", 0), ("degree", ni.BIN_DEGREE), ("mlp", ni.BIN_MLP)):
+        ni.count(rp, cl, ctx=ctx, flags=flags | ni.COUNTERS)
+        c = ni.work_counters(g.n, ctx=ctx)
+        cyc = c[:, 6]
+        keep = cyc > 0
+        cy = cyc[keep].double()
+        mean = float(cy.mean())
+        rec = {"items": int(keep.sum()), "cycles_total": float(cy.sum()), "cycles_mean": mean,
+               "p99_over_mean": float(torch.quantile(cy[torch.randperm(cy.numel(), device=cy.device)[:1 << 20]],
+                                                     0.99)) / mean,
+               "max_over_mean": float(cy.max()) / mean}
+        if name == "plain":
+            X = ni.last_features(g.n, ctx=ctx)[keep].contiguous()
+            pred = ni.mlp_predict(model, X, ctx=ctx).double()
+            y = torch.log2(1.0 + cy)
+            err = pred - y
+            rec["model_mse_log2_cycles"] = float((err * err).mean())
+            rec["target_var_log2_cycles"] = float(torch.var(y))
+            rec["model_r2"] = 1.0 - rec["model_mse_log2_cycles"] / rec["target_var_log2_cycles"]
+            del X, pred, y, err
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rec.items()}
+        del c, cyc, cy
+    torch.cuda.empty_cache()
+    return out
+
+
 def train_work_model(ni, ctx, graphs):
-    """Counters of the plain form on the training graphs -> model of log2 work."""
+    """Counters of the plain form on the training graphs -> model of the measured work
+    of each Stage I/II item: log2(1 + its shader-clock cycles)."""
     import torch
     Xs, ys = [], []
     for g in graphs:
@@ -271,7 +319,7 @@ def train_work_model(ni, ctx, graphs):
         X = ni.last_features(g.n, ctx=ctx)
         keep = c[:, 6] > 0
         Xs.append(X[keep])
-        ys.append(torch.log2(1.0 + stage1_work(c[keep]).double()).float())
+        ys.append(torch.log2(1.0 + c[keep, 6].double()).float())
         del rp, cl
     X = torch.cat(Xs).contiguous()
     y = torch.cat(ys).contiguous()
@@ -346,7 +394,8 @@ def forms(args, ni, ctx, g, rp, cl, out, base_ms):
     mlp_ms, _, _ = time_count(ni, ctx, rp, cl, out, ni.BIN_MLP, 3, 1)
     same_mlp = bool(torch.equal(out, ref))
     res[args.workload] = {"plain": g.m / (base_ms * 1e-3), "degree": g.m / (deg_ms * 1e-3),
-                          "mlp": g.m / (mlp_ms * 1e-3), "identical": same_deg and same_mlp}
+                          "mlp": g.m / (mlp_ms * 1e-3), "identical": same_deg and same_mlp,
+                          "plain_ms_repeats": [round(x, 3) for x in base_repeats(ni, ctx, rp, cl, out)]}
     del ref
     # R-MAT scale 22: plain vs degree-binned vs MLP-binned
     t0 = time.time()
@@ -362,7 +411,9 @@ def forms(args, ni, ctx, g, rp, cl, out, base_ms):
     same = same and bool(torch.equal(rout, rref))
     res["rmat22"] = {"n": r.n, "m": r.m, "plain": r.m / (pl_ms * 1e-3), "degree": r.m / (dg_ms * 1e-3),
                      "mlp": r.m / (ml_ms * 1e-3), "identical": same,
-                     "plain_stage_ms": {k: round(v, 3) for k, v in pl_st.items()}}
+                     "plain_stage_ms": {k: round(v, 3) for k, v in pl_st.items()},
+                     "plain_ms_repeats": [round(x, 3) for x in base_repeats(ni, ctx, rrp, rcl, rout)],
+                     "measured_work": judge_binning(ni, ctx, r, rrp, rcl, model)}
     del rrp, rcl, rout, rref
     torch.cuda.empty_cache()
     # batched: 50,000 small graphs, tuned knobs, captured hipGraph
@@ -414,22 +465,43 @@ def forms(args, ni, ctx, g, rp, cl, out, base_ms):
     pctx = ni.Context(0)
     p_ms, _, _ = time_count(ni, pctx, d_brp, u_col, b_out, 0, reps, 1)
     same = same and bool(torch.equal(b_out, b_ref))
+    # the plain form graph by graph (one niorca_count per graph, as a caller without
+    # the batched entry would run it) on a seeded random subset, scaled to edges/s
+    pick = np.sort(np.random.default_rng(args.seed + 2).choice(len(graphs), 2000, replace=False))
+    sub = [graphs[i] for i in pick]
+    dev = [(torch.from_numpy(x.row_ptr).cuda(), torch.from_numpy(x.col).cuda(),
+            torch.empty((x.n, 15), dtype=torch.int64, device="cuda")) for x in sub]
+    for (a, b, o) in dev[:20]:
+        ni.count(a, b, out=o, ctx=pctx)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for (a, b, o) in dev:
+        ni.count(a, b, out=o, ctx=pctx)
+    torch.cuda.synchronize()
+    pg_s = time.perf_counter() - t1
+    pg_m = sum(x.m for x in sub)
     pctx.close()
+    del dev
     res["batch_mix"] = {"graphs": len(graphs), "n": int(vtx_off[-1]), "m": bm, "captured_ms": b_ms,
                         "value": bm / (b_ms * 1e-3), "uncaptured_ms": nb_ms, "plain_union_ms": p_ms,
-                        "plain_union_value": bm / (p_ms * 1e-3), "identical": same, "tuned": knobs}
+                        "plain_union_value": bm / (p_ms * 1e-3),
+                        "plain_per_graph_value": pg_m / pg_s,
+                        "plain_per_graph_sample": f"{len(sub)} seeded random graphs of the batch, {pg_m} edges, "
+                                                  f"one niorca_count each, in {pg_s * 1000:.1f} ms",
+                        "identical": same, "tuned": knobs}
     del d_brp, d_bcol, b_out, b_ref, u_col
     torch.cuda.empty_cache()
     return res
 
 
-def copy_bandwidth(mib=1024, reps=10):
+def copy_bandwidth(mib=1024, reps=10, convert=True):
     """GB/s of a plain device copy (4 B read and 4 B written per element), timed with
-    events on torch's stream."""
+    events on torch's stream: an int32 -> float32 conversion kernel (convert) or a
+    same-type device-to-device copy."""
     import torch
     n = mib * (1 << 20) // 4
     src = torch.arange(n, dtype=torch.int32, device="cuda")
-    dst = torch.empty(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty(n, dtype=torch.float32 if convert else torch.int32, device="cuda")
     dst.copy_(src)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
@@ -505,7 +577,7 @@ def main():
     log("[bench] stage ms " + json.dumps({k: round(v, 3) for k, v in stage_ms.items()}))
     log("[bench] kernel ms " + json.dumps({k: round(v, 3) for k, v in kernel_ms.items()}))
     dom, bytes_dom, ach = roofline_of(kernel_ms, stats)
-    cb = copy_bandwidth()
+    cb = max((copy_bandwidth(convert=c) for c in (True, False)), key=lambda r: r["GBps"])
     log(f"[bench] copy bandwidth {cb['GBps']:.0f} GB/s")
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic_for(args.workload, dom),
