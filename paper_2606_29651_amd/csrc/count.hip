@@ -237,13 +237,12 @@ __device__ __forceinline__ int seg_search(const i32 *off, int len, i32 e) {
 }
 
 // Segment of every element e in [eb, total), eb + NT*PER at most, of a run of
-// segments with prefix offsets off[0..len], less sbase, one byte each at byte e - eb
-// of map (the segments of the block lie in [sbase, sbase + 256)): thread t walks its
-// run of PER consecutive elements from eb + t*PER on after one search, where a
-// search per element would cost a logarithmic number of LDS reads for each.
+// segments with prefix offsets off[0..len], one byte each at byte e - eb of map (the
+// segments number at most 256): thread t walks its run of PER consecutive elements
+// from eb + t*PER on after one search, where a search per element would cost a
+// logarithmic number of LDS reads for each.
 template <int NT, int PER>
-__device__ __forceinline__ void q_segmap(const i32 *off, int len, i32 eb, i32 total, int tid, u32 *map,
-                                         int sbase = 0) {
+__device__ __forceinline__ void q_segmap(const i32 *off, int len, i32 eb, i32 total, int tid, u32 *map) {
     static_assert(PER % 4 == 0, "whole words per thread");
     const i32 e0 = eb + tid * PER;
     if (e0 >= total) return;
@@ -262,7 +261,7 @@ __device__ __forceinline__ void q_segmap(const i32 *off, int len, i32 eb, i32 to
                     nb = off[s + 1];
                 }
             }
-            w |= (u32)(s - sbase) << (8 * b);
+            w |= (u32)s << (8 * b);
         }
         map[tid * (PER / 4) + k4] = w;
     }
@@ -270,6 +269,37 @@ __device__ __forceinline__ void q_segmap(const i32 *off, int len, i32 eb, i32 to
 
 __device__ __forceinline__ int seg_at(const u32 *map, i32 i) {
     return ((const unsigned char *)map)[i];
+}
+
+// The same map with one 16-bit entry per element (the absolute segment index, for
+// items of up to 65536 segments): no block ever needs the search instead.
+template <int NT, int PER>
+__device__ __forceinline__ void q_segmap16(const i32 *off, int len, i32 eb, i32 total, int tid, u32 *map) {
+    static_assert(PER % 2 == 0, "whole words per thread");
+    const i32 e0 = eb + tid * PER;
+    if (e0 >= total) return;
+    int s = seg_search(off, len, e0);
+    i32 nb = off[s + 1];
+#pragma unroll
+    for (int k2 = 0; k2 < PER / 2; k2++) {
+        u32 w = 0;
+#pragma unroll
+        for (int b = 0; b < 2; b++) {
+            const i32 e = e0 + 2 * k2 + b;
+            if (e < total) {
+                while (nb <= e) {
+                    s++;
+                    nb = off[s + 1];
+                }
+            }
+            w |= (u32)s << (16 * b);
+        }
+        map[tid * (PER / 2) + k2] = w;
+    }
+}
+
+__device__ __forceinline__ int seg_at16(const u32 *map, i32 i) {
+    return ((const unsigned short *)map)[i];
 }
 
 // Wave-wide inclusive maximum of non-negative values, all 64 lanes active.
@@ -283,7 +313,7 @@ __device__ __forceinline__ int wave_incl_max(int v) {
     return v;
 }
 
-// The same byte map as q_segmap (sbase 0), built without a search per thread: every
+// The same byte map as q_segmap, built without a search per thread: every
 // nonempty segment starting in the block writes its index at its first element, and
 // a running maximum over the elements (within each thread's PER bytes, then across
 // the item's threads, from the segment of element eb on) fills in the rest.  The
@@ -291,7 +321,7 @@ __device__ __forceinline__ int wave_incl_max(int v) {
 // segment holding e.  NT is a multiple of the wave; red32 holds NT/WAVE entries.
 template <int NT, int PER>
 __device__ __forceinline__ void seg_map_scan(const i32 *off, int len, i32 eb, i32 total, int tid, u32 *map,
-                                             i32 *red32, int sbase = 0) {
+                                             i32 *red32) {
     static_assert(PER % 4 == 0 && NT % WAVE == 0, "whole words per thread, whole waves");
     constexpr int PW = PER / 4;
     u32 *mine = map + tid * PW;
@@ -301,7 +331,7 @@ __device__ __forceinline__ void seg_map_scan(const i32 *off, int len, i32 eb, i3
     const i32 eend = min(eb + NT * PER, total);
     for (int i = tid; i < len; i += NT) {
         const i32 o = off[i];
-        if (o >= eb && o < eend && o < off[i + 1]) ((unsigned char *)map)[o - eb] = (unsigned char)(i - sbase);
+        if (o >= eb && o < eend && o < off[i + 1]) ((unsigned char *)map)[o - eb] = (unsigned char)i;
     }
     item_sync<NT>();
     u32 w[PW];
@@ -327,7 +357,7 @@ __device__ __forceinline__ void seg_map_scan(const i32 *off, int len, i32 eb, i3
         for (int k = 0; k < NT / WAVE; k++)
             if (k < wv) c = max(c, red32[k]);
     }
-    if (eb > 0) c = max(c, seg_search(off, len, eb) - sbase);
+    if (eb > 0) c = max(c, seg_search(off, len, eb));
 #pragma unroll
     for (int k = 0; k < PW; k++) {
         u32 o = 0;
@@ -411,7 +441,7 @@ __device__ __forceinline__ PMeta p_meta(const DevGraph &g, const TriCache &tc, i
     return m;
 }
 
-template <int NT, int MODE, int QP, int MP = 0, int MAXDU = (1 << 30)>
+template <int NT, int MODE, int QP, int MP = 0, int MAXDU = (1 << 30), bool WIDE = false>
 __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, int tid, const ProbeMem &M, int hc,
                                            int pitch, i32 *__restrict__ t, i64 *__restrict__ K4,
                                            i64 *__restrict__ tau, i64 *red, i32 *red32, const TriCache &tc,
@@ -528,36 +558,34 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
     // probes are located through a segment map built every MP/QP rounds.
     static_assert(MP % QP == 0, "map blocks hold whole rounds");
     i32 mbase = 0;
-    int sfirst = 0;
-    bool mapped = true;
-    constexpr bool FEW = MAXDU <= 256;  // every item's segments fit a byte
     for (i32 eb = 0; eb < total; eb += NT * QP) {
         const int nj = min(QP, (total - eb + NT - 1) / NT);
         int lo[QP];
         i32 qq[QP], ww[QP];
-        if constexpr (MP > 0) {
+        if constexpr (MP > 0 && WIDE) {
             if (eb % (NT * MP) == 0) {
                 mbase = eb;
-                // a byte holds the segment relative to the block's first one; a
-                // block spanning 256 segments or more is searched instead
-                if (!FEW && du > 256) {
-                    sfirst = seg_search(M.off, du, eb);
-                    mapped = seg_search(M.off, du, min(eb + NT * MP, total) - 1) - sfirst < 256;
-                }
-                if (FEW || mapped) {
-                    item_sync<NT>();  // the previous block's map has been read
-                    q_segmap<NT, MP>(M.off, du, eb, total, tid, M.seg, FEW ? 0 : sfirst);
-                    item_sync<NT>();
-                }
+                item_sync<NT>();  // the previous block's map has been read
+                q_segmap16<NT, MP>(M.off, du, eb, total, tid, M.seg);
+                item_sync<NT>();
             }
-            if (FEW || mapped) {
 #pragma unroll
-                for (int j = 0; j < QP; j++) {
-                    const i32 e = eb + tid + j * NT;
-                    lo[j] = (j < nj && e < total) ? (FEW ? 0 : sfirst) + seg_at(M.seg, e - mbase) : 0;
-                }
-            } else {
-                q_locate<NT, QP>(M.off, du, eb + tid, nj, lo, total - 1);
+            for (int j = 0; j < QP; j++) {
+                const i32 e = eb + tid + j * NT;
+                lo[j] = (j < nj && e < total) ? seg_at16(M.seg, e - mbase) : 0;
+            }
+        } else if constexpr (MP > 0) {
+            static_assert(MAXDU <= 256, "a byte map holds the segment of items of at most 256 slots");
+            if (eb % (NT * MP) == 0) {
+                mbase = eb;
+                item_sync<NT>();  // the previous block's map has been read
+                q_segmap<NT, MP>(M.off, du, eb, total, tid, M.seg);
+                item_sync<NT>();
+            }
+#pragma unroll
+            for (int j = 0; j < QP; j++) {
+                const i32 e = eb + tid + j * NT;
+                lo[j] = (j < nj && e < total) ? seg_at(M.seg, e - mbase) : 0;
             }
         } else {
             q_locate<NT, QP>(M.off, du, eb + tid, nj, lo, total - 1);
@@ -812,7 +840,7 @@ __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__
     __shared__ i32 s_tcnt[CAP];
     __shared__ u32 s_A[CAP * PITCH];
     __shared__ i64 s_acc[CAP];
-    __shared__ u32 s_seg[PB_MP > 0 ? PB_NT * PB_MP / 4 : 1];
+    __shared__ u32 s_seg[PB_NT * PB_MP / 2];
     __shared__ i64 s_red[PB_NT / WAVE];
     __shared__ i32 s_red32[PB_NT / WAVE];
     __shared__ ItemState s_st;
@@ -831,8 +859,8 @@ __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__
     for (; it < cnt; it += gridDim.x) {
         const PMeta nxt = p_meta<MODE>(g, tc, un);
         un = it + 2 * (i32)gridDim.x < cnt ? list[it + 2 * gridDim.x] : -1;
-        probe_item<PB_NT, MODE, PB_QP, PB_MP, CAP>(g, cur, threadIdx.x, M, HC, PITCH, t, K4, tau, s_red, s_red32,
-                                                   tc, &s_st, counters);
+        probe_item<PB_NT, MODE, PB_QP, PB_MP, CAP, true>(g, cur, threadIdx.x, M, HC, PITCH, t, K4, tau, s_red,
+                                                         s_red32, tc, &s_st, counters);
         cur = nxt;
     }
 }
