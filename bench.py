@@ -145,6 +145,24 @@ def counter_summary(paths):
     return "\n".join(lines)
 
 
+def kernel_summary(path, top=24):
+    """Text table of a rocprofv3 --kernel-trace --stats run_kernel_stats.csv: calls,
+    average and total duration and share of each kernel, the top ones by total time."""
+    import csv
+    rows = []
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            name = r["Name"].replace("void ", "", 1)
+            name = name.split("(")[0] if "(" in name else name
+            rows.append((name, int(r["Calls"]), float(r["AverageNs"]) / 1000.0, float(r["TotalDurationNs"]) / 1e6,
+                         float(r["Percentage"])))
+    rows.sort(key=lambda x: -x[3])
+    lines = [f"{'kernel':<58}{'calls':>7}{'avg_us':>11}{'total_ms':>11}{'pct':>7}"]
+    for name, calls, avg, tot, pct in rows[:top]:
+        lines.append(f"{name[:57]:<58}{calls:>7}{avg:>11.1f}{tot:>11.3f}{pct:>7.2f}")
+    return "\n".join(lines)
+
+
 def traffic_for(workload, kernel):
     """HBM bytes per launch of kernel from profiles/traffic_<workload>.txt, or None when
     there is no such summary or the kernel sources changed since it was taken."""
@@ -539,6 +557,9 @@ def main():
                                                             "COPY_WRITE_CSV"),
                     help="print the per-kernel HBM traffic summary from rocprofv3 --pmc counter CSVs of the "
                          "bench (FETCH_SIZE, WRITE_SIZE) and of --copy-calibration 1024, then exit")
+    ap.add_argument("--kernel-summary", metavar="CSV",
+                    help="print the per-kernel duration table of a rocprofv3 --kernel-trace --stats "
+                         "run_kernel_stats.csv, then exit")
     ap.add_argument("--counter-summary", nargs="+", metavar="CSV",
                     help="print shader-sequencer counters per dispatch of each timed kernel from rocprofv3 "
                          "--pmc counter CSVs of the bench, then exit")
@@ -551,6 +572,9 @@ def main():
         return
     if args.counter_summary:
         print(counter_summary(args.counter_summary))
+        return
+    if args.kernel_summary:
+        print(kernel_summary(args.kernel_summary))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU path is not built",
