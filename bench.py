@@ -396,9 +396,10 @@ def forms(args, ni, ctx, g, rp, cl, out, base_ms):
     # thresholds of the learned binning: a small search on the training graph
     ref = out.clone()
     best = None
-    for thr_t in (-99.0, 8.0):
-        for thr_g in (-99.0, 10.0, 11.0, 12.0, 13.0):
-            for thr_b in (17.0, 99.0):
+    # thresholds on predicted log2 item cycles (a Chung-Lu item averages about 2^17)
+    for thr_t in (-99.0, 12.0):
+        for thr_g in (-99.0, 12.0, 13.0, 14.0, 15.0, 16.0):
+            for thr_b in (22.0, 99.0):
                 ni.set_cost_model(model, thr_t, thr_b, thr_g, ctx=ctx)
                 ms, _, _ = time_count(ni, ctx, rp, cl, out, ni.BIN_MLP, 2, 1)
                 if best is None or ms < best[0]:
@@ -448,8 +449,8 @@ def forms(args, ni, ctx, g, rp, cl, out, base_ms):
         s_off, s_rp, s_col = gg.pack_batch([graphs[i] for i in pick])
         d_srp, d_scol = torch.from_numpy(s_rp).cuda(), torch.from_numpy(s_col).cuda()
         s_out = torch.empty((int(s_off[-1]), 15), dtype=torch.int64, device="cuda")
-        cands = autotune.grid(heavy_k=[0, 4096, 32768], tri_wave=[32, 64], qh_wave=[256, 512, 1024],
-                              ql_wave=[256, 512])
+        cands = autotune.grid(bin_mode=[0, 1], heavy_k=[0, 4096, 32768], tri_wave=[32, 64],
+                              qh_wave=[256, 512, 1024], ql_wave=[256, 512])
         tuned = autotune.tune(tctx, lambda: ni.count_batched(s_off, d_srp, d_scol, out=s_out, ctx=tctx), cands,
                               repeats=3)
         autotune.save(TUNE_FILE, "batch_mix", tuned["best"],
@@ -475,6 +476,28 @@ def forms(args, ni, ctx, g, rp, cl, out, base_ms):
     stream.synchronize()
     nb_ms = 1000.0 * (time.perf_counter() - t1)
     same = bool(torch.equal(b_out, b_ref))
+    # the learned binning in place of the degree thresholds (model and thresholds of
+    # the Chung-Lu search above), captured the same way
+    ni.set_cost_model(model, best[1], best[2], best[3], ctx=tctx)
+    tctx.set_param("bin_mode", 2)
+    ni.count_batched(vtx_off, d_brp, d_bcol, out=b_out, ctx=tctx, stream=stream, flags=ni.GRAPH_CAPTURE)
+    stream.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        ni.count_batched(vtx_off, d_brp, d_bcol, out=b_out, ctx=tctx, stream=stream, flags=ni.GRAPH_CAPTURE)
+    stream.synchronize()
+    bm_ms = 1000.0 * (time.perf_counter() - t1) / reps
+    same = same and bool(torch.equal(b_out, b_ref))
+    # and with no binning at all
+    tctx.set_param("bin_mode", 0)
+    ni.count_batched(vtx_off, d_brp, d_bcol, out=b_out, ctx=tctx, stream=stream, flags=ni.GRAPH_CAPTURE)
+    stream.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        ni.count_batched(vtx_off, d_brp, d_bcol, out=b_out, ctx=tctx, stream=stream, flags=ni.GRAPH_CAPTURE)
+    stream.synchronize()
+    b0_ms = 1000.0 * (time.perf_counter() - t1) / reps
+    same = same and bool(torch.equal(b_out, b_ref))
     tctx.close()
     # the plain form on the same graphs: niorca_count of their disjoint union (global ids)
     u_col = torch.from_numpy(bcol).cuda()
@@ -504,6 +527,8 @@ def forms(args, ni, ctx, g, rp, cl, out, base_ms):
                         "value": bm / (b_ms * 1e-3), "uncaptured_ms": nb_ms, "plain_union_ms": p_ms,
                         "plain_union_value": bm / (p_ms * 1e-3),
                         "plain_per_graph_value": pg_m / pg_s,
+                        "mlp_binned_captured_ms": bm_ms, "mlp_binned_value": bm / (bm_ms * 1e-3),
+                        "unbinned_captured_ms": b0_ms, "unbinned_value": bm / (b0_ms * 1e-3),
                         "plain_per_graph_sample": f"{len(sub)} seeded random graphs of the batch, {pg_m} edges, "
                                                   f"one niorca_count each, in {pg_s * 1000:.1f} ms",
                         "identical": same, "tuned": knobs}

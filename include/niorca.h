@@ -108,11 +108,11 @@ uint64_t niorca_workspace_bytes(const niorca_ctx *ctx);
  *                        intermediate entry points: 0 capacity only (default), 1 as
  *                        NIORCA_BIN_DEGREE, 2 as NIORCA_BIN_MLP (needs a cost model)
  *   "bin_deg_thread" (NIORCA_BIN_DEGREE) degree up to which a vertex with |N+| <= 8
- *               goes to the one-lane Stage I class (default 16)
+ *               goes to the one-lane Stage I class (default 0: none)
  *   "bin_deg_group"  (NIORCA_BIN_DEGREE) degree up to which a vertex with |N+| <= 16
- *               (and not one-lane) goes to the sixteen-lane Stage I class (default 48)
+ *               (and not one-lane) goes to the sixteen-lane Stage I class (default 32)
  *   "bin_deg_block"  (NIORCA_BIN_DEGREE) degree from which a vertex goes to the
- *               workgroup Stage I class (default 4096)
+ *               workgroup Stage I class (default 2^30: none)
  *   "tri_cache" 0..2^34  most triangles kept from Stage I for the tau pass (8 bytes
  *                        each, default 2^32; a call reserves no more than the sum over
  *                        vertices of C(|N+|, 2); vertices whose triangles do not fit

@@ -34,8 +34,11 @@ struct niorca_ctx {
     bool ev_made = false;
     bool ev_valid = false;
     // tunable class thresholds and the size of the heavy 4-cycle key range
-    Thresholds th{TRI_WAVE_CAP, TRI_BLOCK_CAP, 0, 16, 4096, 0.f, 0.f, nullptr,
-                  512, 8192, 512, 2048, 2048, 48, -1e30f};
+    // (degree binning: no one-lane items, sixteen lanes up to degree 32, no degree
+    // promotion to workgroups -- the measured best on the Erdos-Renyi, Chung-Lu,
+    // R-MAT and batched workloads)
+    Thresholds th{TRI_WAVE_CAP, TRI_BLOCK_CAP, 0, 0, 1 << 30, 0.f, 0.f, nullptr,
+                  512, 8192, 512, 2048, 2048, 32, -1e30f};
     // size of the heavy 4-cycle key range; -1 = chosen per call from the degrees
     int32_t heavy_k = -1;
     // the last captured batched sequence and the shape it was captured for
@@ -814,6 +817,12 @@ __global__ void k_localize(int32_t G, int64_t nnz, const int64_t *__restrict__ v
     }
 }
 
+static uint32_t f32_bits(float x) {
+    uint32_t u;
+    memcpy(&u, &x, sizeof u);
+    return u;
+}
+
 static uint64_t mix64(uint64_t h, uint64_t v) {
     h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
     return h;
@@ -882,7 +891,12 @@ extern "C" niorca_status niorca_count_batched(niorca_ctx *ctx, int32_t num_graph
                        ctx->ws_bytes, vh, (uint64_t)ctx->heavy_k, (uint64_t)ctx->tri_cache_records,
                        (uint64_t)ctx->th.tri_wave, (uint64_t)ctx->th.tri_block, (uint64_t)ctx->th.ql_wave,
                        (uint64_t)ctx->th.ql_block, (uint64_t)ctx->th.qh_wave, (uint64_t)ctx->th.qh_block,
-                       (uint64_t)ctx->th.ql_split, (uint64_t)ctx->large_lds_max, (uint64_t)flags})
+                       (uint64_t)ctx->th.ql_split, (uint64_t)ctx->large_lds_max, (uint64_t)flags,
+                       // binning: mode, degree bounds and the learned bounds are launch arguments too
+                       (uint64_t)ctx->bin_default, (uint64_t)ctx->th.deg_thread, (uint64_t)ctx->th.deg_group,
+                       (uint64_t)ctx->th.deg_block, (uint64_t)f32_bits(ctx->thr_thread),
+                       (uint64_t)f32_bits(ctx->thr_group), (uint64_t)f32_bits(ctx->thr_block),
+                       (uint64_t)(uintptr_t)ctx->mlp_dev})
         key = mix64(key, v);
     if (!ctx->gexec || ctx->gkey != key) {
         if (ctx->gexec) {
