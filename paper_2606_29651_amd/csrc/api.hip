@@ -360,6 +360,7 @@ static niorca_status check_graph_args(niorca_ctx *ctx, int32_t n, int64_t nnz, c
 // Workspace layout of one count.
 struct Layout {
     uint64_t st, deg, val, k2, v2, hist, scan, perm, nrp, nsplit, hstart, lng, ncol, mirror, t, wl, wh, vmeta;
+    uint64_t hseg, lbeg;  // per-slot 4-cycle wedge runs (heavy: int2 bounds; light: start)
     uint64_t lists[WC_COUNT];
     uint64_t acc, tcoff, tccnt, tcbump, tcrec, probes, feat, pred, counters, ek4;
     uint64_t base_end;  // everything above needs no graph statistics
@@ -381,6 +382,7 @@ static void layout_base(Layout &L, const niorca_ctx *ctx, int32_t n, int64_t nnz
     L.hstart = A.take<i32>(n); L.lng = A.take<i32>(n + 1);
     // slot arrays carry a pad so that a one-past-the-row read never leaves the buffer
     L.ncol = A.take<i32>(nnz + 64); L.mirror = A.take<i32>(nnz + 64); L.t = A.take<i32>(nnz + 64);
+    L.hseg = A.take<int2>(nnz + 64); L.lbeg = A.take<i32>(nnz + 64);
     L.wl = A.take<i64>(n); L.wh = A.take<i64>(n);
     L.vmeta = A.take<int4>(n);
     for (int c = 0; c < WC_COUNT; c++) L.lists[c] = A.take<i32>(n);
@@ -535,6 +537,8 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     i32 *perm = (i32 *)(W + L.perm), *nrp = (i32 *)(W + L.nrp), *nsplit = (i32 *)(W + L.nsplit);
     i32 *hstart = (i32 *)(W + L.hstart), *longlist = (i32 *)(W + L.lng);
     i32 *ncol = (i32 *)(W + L.ncol), *mirror = (i32 *)(W + L.mirror), *t = (i32 *)(W + L.t);
+    int2 *hseg = (int2 *)(W + L.hseg);
+    i32 *lbeg = (i32 *)(W + L.lbeg);
     i64 *wl = (i64 *)(W + L.wl), *wh = (i64 *)(W + L.wh);
     int4 *vmeta = (int4 *)(W + L.vmeta);
     ListPtrs lists;
@@ -609,7 +613,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     float *feat = L.feat ? (float *)(W + L.feat) : nullptr;
     float *pred = L.pred ? (float *)(W + L.pred) : nullptr;
     i64 *counters = L.counters ? (i64 *)(W + L.counters) : nullptr;
-    hipLaunchKernelGGL(k_mirror, dim3(cu * 8), dim3(nthr), 0, s, n, deg, nrp, nsplit, ncol, vmeta, h0, mirror, wl,
+    hipLaunchKernelGGL(k_mirror, dim3(cu * 8), dim3(nthr), 0, s, n, deg, nrp, nsplit, ncol, vmeta, h0, mirror, hseg, lbeg, wl,
                        wh, probes, feat);
     HIP_TRY(hipGetLastError());
     Thresholds th = ctx->th;
@@ -621,7 +625,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
         th.thr_group = ctx->thr_group;
         th.thr_block = ctx->thr_block;
     }
-    DevGraph g{n, (i32)nnz, h0, nrp, nsplit, ncol, mirror, hstart, deg, val, wl, wh, vmeta};
+    DevGraph g{n, (i32)nnz, h0, nrp, nsplit, ncol, mirror, hstart, deg, val, wl, wh, vmeta, hseg, lbeg};
     HIP_TRY(launch_classify(g, wl, wh, probes, lists, dst, th, s));
     if (counters) {
         HIP_TRY(fill32(counters, (i64)sizeof(i64) * NUM_COUNTERS * n, 0u, s));

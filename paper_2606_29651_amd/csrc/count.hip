@@ -1217,14 +1217,16 @@ enum { Q_LIGHT = 0, Q_HEAVY = 1 };
 // Segment (wedge run) of slot s of item x.
 template <int MODE>
 __device__ __forceinline__ void q_segment(const DevGraph &g, i32 x, i32 s, i32 sp, i32 &v, i32 &beg, i32 &end) {
+    // the run bounds were written per slot next to the mirror slots, so that they
+    // load alongside the neighbour rather than after it
     v = g.ncol[s];
     if (MODE == Q_LIGHT) {
-        beg = vmeta_at(g, v, VM_BEGIN);
+        beg = g.lbeg[s];
         end = g.mirror[s];
     } else {
-        end = vmeta_at(g, v, VM_END);
-        // (the clamp only matters for an asymmetric input, whose mirror may be the row end)
-        beg = (x >= g.h0 && s < sp) ? min(g.mirror[s] + 1, end) : vmeta_at(g, v, VM_HSTART);
+        const int2 h = g.hseg[s];
+        beg = h.x;
+        end = h.y;
     }
 }
 

@@ -114,6 +114,10 @@ struct DevGraph {
     const i64 *wheavy;      // int64[n]: 4-cycle wedges with y opposite a heavy largest vertex
     const int4 *vmeta;      // int4[n]: {nrp[y], nsplit[y], nrp[y+1], hstart[y]}, one line
                             // for kernels that visit y as some other vertex's neighbour
+    const int2 *hseg;       // int2[nnz]: slot s of y (neighbour b) -> first and end slot of
+                            // the heavy 4-cycle tops u > y in N+(b) (wedges y-b-u)
+    const i32 *lbeg;        // int32[nnz]: lower slot s of y (neighbour b) -> row start of b
+                            // (light wedges y-b-w, w < y, end at mirror[s])
 };
 
 enum { VM_BEGIN = 0, VM_NSPLIT = 1, VM_END = 2, VM_HSTART = 3 };
@@ -139,7 +143,8 @@ __global__ void k_sort_upper_small(i32 n, const u32 *ndeg, const i32 *nrp, const
 __global__ void k_sort_upper_large(const i32 *nrp, const i32 *nsplit, i32 *ncol, i32 *hstart, int4 *vmeta, i32 h0,
                                    const i32 *longlist, const i32 *longcount);
 __global__ void k_mirror(i32 n, const u32 *ndeg, const i32 *nrp, const i32 *nsplit, const i32 *ncol,
-                         const int4 *vmeta, i32 h0, i32 *mirror, i64 *wlight, i64 *wheavy, i64 *probes, float *feat);
+                         const int4 *vmeta, i32 h0, i32 *mirror, int2 *hseg, i32 *lbeg, i64 *wlight, i64 *wheavy,
+                         i64 *probes, float *feat);
 #define LSORT_CAP 16384
 #define LSORT_NT 512  // threads of the long-row sort
 #define LSORT_GRID 2  // its workgroups per CU (64 KiB of LDS each)

@@ -479,6 +479,7 @@ template <int W>
 __device__ __forceinline__ void mirror_row(i32 y, bool active, int l, const i32 *__restrict__ nrp,
                                            const i32 *__restrict__ nsplit, const i32 *__restrict__ ncol,
                                            const int4 *__restrict__ vmeta, i32 h0, i32 *__restrict__ mirror,
+                                           int2 *__restrict__ hseg, i32 *__restrict__ lbeg,
                                            i64 *__restrict__ wlight, i64 *__restrict__ wheavy,
                                            i64 *__restrict__ probes, float *__restrict__ feat) {
     i32 b0 = 0, sp = 0, e0 = 0;
@@ -497,10 +498,13 @@ __device__ __forceinline__ void mirror_row(i32 y, bool active, int l, const i32 
         if (s < sp) {
             i32 m = lower_bound_i32(ncol, vb.y, bend, y);
             mirror[s] = m;
+            lbeg[s] = bb;
             wl += m - bb;
             i32 st = (y >= h0) ? min(m + 1, bend) : vb.w;  // (m = bend only for asymmetric input)
+            hseg[s] = make_int2(st, bend);
             wh += bend - st;
         } else {
+            hseg[s] = make_int2(vb.w, bend);
             wh += bend - vb.w;
             i32 dpb = bend - vb.y;
             pr += dpb;
@@ -534,17 +538,18 @@ __device__ __forceinline__ void mirror_row(i32 y, bool active, int l, const i32 
 __global__ void k_mirror(i32 n, const u32 *__restrict__ ndeg, const i32 *__restrict__ nrp,
                          const i32 *__restrict__ nsplit, const i32 *__restrict__ ncol,
                          const int4 *__restrict__ vmeta, i32 h0, i32 *__restrict__ mirror,
-                         i64 *__restrict__ wlight, i64 *__restrict__ wheavy, i64 *__restrict__ probes,
-                         float *__restrict__ feat) {
+                         int2 *__restrict__ hseg, i32 *__restrict__ lbeg, i64 *__restrict__ wlight,
+                         i64 *__restrict__ wheavy, i64 *__restrict__ probes, float *__restrict__ feat) {
     const int waves = gridDim.x * (blockDim.x / WAVE);
     const int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const i32 cut = first_above(ndeg, n, SG_MAXDEG);
     constexpr int GPW = WAVE / SG;
     for (i32 yb = wid * GPW; yb < cut; yb += waves * GPW) {
         const i32 y = yb + lane_id() / SG;
-        mirror_row<SG>(y, y < cut, lane_id() % SG, nrp, nsplit, ncol, vmeta, h0, mirror, wlight, wheavy, probes,
-                       feat);
+        mirror_row<SG>(y, y < cut, lane_id() % SG, nrp, nsplit, ncol, vmeta, h0, mirror, hseg, lbeg, wlight, wheavy,
+                       probes, feat);
     }
     for (i32 y = n - 1 - wid; y >= cut; y -= waves)
-        mirror_row<WAVE>(y, true, lane_id(), nrp, nsplit, ncol, vmeta, h0, mirror, wlight, wheavy, probes, feat);
+        mirror_row<WAVE>(y, true, lane_id(), nrp, nsplit, ncol, vmeta, h0, mirror, hseg, lbeg, wlight, wheavy, probes,
+                         feat);
 }
