@@ -1046,9 +1046,8 @@ __device__ __forceinline__ void sums_vertex(const DevGraph &g, const i32 *__rest
     }
     i64 St = 0, Stt = 0, Std = 0, Sd = 0, Sdd = 0;
     for (i32 s = b0 + l; s < e0; s += W) {
-        i32 a = g.ncol[s];
         i64 ta = (s < sp) ? t[g.mirror[s]] : t[s];
-        i64 da = g.ndeg[a];
+        i64 da = g.dslot[s];
         St += ta;
         Stt += ta * ta;
         Std += ta * da;

@@ -118,6 +118,8 @@ struct DevGraph {
                             // the heavy 4-cycle tops u > y in N+(b) (wedges y-b-u)
     const i32 *lbeg;        // int32[nnz]: lower slot s of y (neighbour b) -> row start of b
                             // (light wedges y-b-w, w < y, end at mirror[s])
+    const i32 *dslot;       // int32[nnz]: slot s -> degree of its neighbour, so that the
+                            // neighbour sums stream it instead of gathering it
 };
 
 enum { VM_BEGIN = 0, VM_NSPLIT = 1, VM_END = 2, VM_HSTART = 3 };
@@ -143,8 +145,8 @@ __global__ void k_sort_upper_small(i32 n, const u32 *ndeg, const i32 *nrp, const
 __global__ void k_sort_upper_large(const i32 *nrp, const i32 *nsplit, i32 *ncol, i32 *hstart, int4 *vmeta, i32 h0,
                                    const i32 *longlist, const i32 *longcount);
 __global__ void k_mirror(i32 n, const u32 *ndeg, const i32 *nrp, const i32 *nsplit, const i32 *ncol,
-                         const int4 *vmeta, i32 h0, i32 *mirror, int2 *hseg, i32 *lbeg, i64 *wlight, i64 *wheavy,
-                         i64 *probes, float *feat);
+                         const int4 *vmeta, i32 h0, i32 *mirror, int2 *hseg, i32 *lbeg, i32 *dslot, i64 *wlight,
+                         i64 *wheavy, i64 *probes, float *feat);
 #define LSORT_CAP 16384
 #define LSORT_NT 512  // threads of the long-row sort
 #define LSORT_GRID 2  // its workgroups per CU (64 KiB of LDS each)

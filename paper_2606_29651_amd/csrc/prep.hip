@@ -462,55 +462,12 @@ __global__ void __launch_bounds__(LSORT_NT) k_sort_upper_large(const i32 *__rest
     }
 }
 
-// ---------------------------------------------------------------------------
-// Mirror slots and per-vertex work of the 4-cycle passes, one wave per row y (or
-// one 16-lane group for rows of degree <= SG_MAXDEG):
-//   lower slot s (neighbour b < y): mirror[s] = slot of y inside N+(b);
-//   wlight[y] = sum over lower slots of (mirror[s] - row start of b): the wedges
-//               with y as the largest vertex;
-//   wheavy[y] = sum over all slots of the heavy suffix lengths of N+(b) above
-//               max(h0, y+1): the wedges with y opposite a heavy largest vertex;
-//   probes[y] = sum of |N+(b)| over b in N+(y): the Stage I probes made from y.
-// With feat != nullptr it also writes six cheap per-vertex features for the work
-// model: log2(1 + x) of degree, |N+|, |N-|, neighbour-degree sum, probes and the
-// largest |N+(b)| over b in N+(y).
-// ---------------------------------------------------------------------------
+// Per-row sums of the mirror pass (over the row's W lanes) and their writes.
 template <int W>
-__device__ __forceinline__ void mirror_row(i32 y, bool active, int l, const i32 *__restrict__ nrp,
-                                           const i32 *__restrict__ nsplit, const i32 *__restrict__ ncol,
-                                           const int4 *__restrict__ vmeta, i32 h0, i32 *__restrict__ mirror,
-                                           int2 *__restrict__ hseg, i32 *__restrict__ lbeg,
-                                           i64 *__restrict__ wlight, i64 *__restrict__ wheavy,
-                                           i64 *__restrict__ probes, float *__restrict__ feat) {
-    i32 b0 = 0, sp = 0, e0 = 0;
-    if (active) {
-        b0 = nrp[y];
-        sp = nsplit[y];
-        e0 = nrp[y + 1];
-    }
-    i64 wl = 0, wh = 0, pr = 0, nds = 0;
-    int mx = 0;
-    for (i32 s = b0 + l; s < e0; s += W) {
-        i32 b = ncol[s];
-        const int4 vb = vmeta[b];  // row start, N+ start, row end, heavy start of b
-        i32 bb = vb.x, bend = vb.z;
-        nds += bend - bb;
-        if (s < sp) {
-            i32 m = lower_bound_i32(ncol, vb.y, bend, y);
-            mirror[s] = m;
-            lbeg[s] = bb;
-            wl += m - bb;
-            i32 st = (y >= h0) ? min(m + 1, bend) : vb.w;  // (m = bend only for asymmetric input)
-            hseg[s] = make_int2(st, bend);
-            wh += bend - st;
-        } else {
-            hseg[s] = make_int2(vb.w, bend);
-            wh += bend - vb.w;
-            i32 dpb = bend - vb.y;
-            pr += dpb;
-            mx = max(mx, dpb);
-        }
-    }
+__device__ __forceinline__ void mirror_row_tail(i32 y, bool active, int l, i32 b0, i32 sp, i32 e0, i32 h0, i64 wl,
+                                                i64 wh, i64 pr, i64 nds, int mx, i64 *__restrict__ wlight,
+                                                i64 *__restrict__ wheavy, i64 *__restrict__ probes,
+                                                float *__restrict__ feat) {
     wl = group_sum64<W>(wl);
     wh = group_sum64<W>(wh);
     pr = group_sum64<W>(pr);
@@ -532,24 +489,78 @@ __device__ __forceinline__ void mirror_row(i32 y, bool active, int l, const i32 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Mirror slots and per-vertex work of the 4-cycle passes, one wave per row y (or
+// one 16-lane group for rows of degree <= SG_MAXDEG):
+//   lower slot s (neighbour b < y): mirror[s] = slot of y inside N+(b);
+//   wlight[y] = sum over lower slots of (mirror[s] - row start of b): the wedges
+//               with y as the largest vertex;
+//   wheavy[y] = sum over all slots of the heavy suffix lengths of N+(b) above
+//               max(h0, y+1): the wedges with y opposite a heavy largest vertex;
+//   probes[y] = sum of |N+(b)| over b in N+(y): the Stage I probes made from y.
+// With feat != nullptr it also writes six cheap per-vertex features for the work
+// model: log2(1 + x) of degree, |N+|, |N-|, neighbour-degree sum, probes and the
+// largest |N+(b)| over b in N+(y).
+// ---------------------------------------------------------------------------
+template <int W>
+__device__ __forceinline__ void mirror_row(i32 y, bool active, int l, const i32 *__restrict__ nrp,
+                                           const i32 *__restrict__ nsplit, const i32 *__restrict__ ncol,
+                                           const int4 *__restrict__ vmeta, i32 h0, i32 *__restrict__ mirror,
+                                           int2 *__restrict__ hseg, i32 *__restrict__ lbeg, i32 *__restrict__ dslot,
+                                           i64 *__restrict__ wlight, i64 *__restrict__ wheavy,
+                                           i64 *__restrict__ probes, float *__restrict__ feat) {
+    i32 b0 = 0, sp = 0, e0 = 0;
+    if (active) {
+        b0 = nrp[y];
+        sp = nsplit[y];
+        e0 = nrp[y + 1];
+    }
+    i64 wl = 0, wh = 0, pr = 0, nds = 0;
+    int mx = 0;
+    for (i32 s = b0 + l; s < e0; s += W) {
+        i32 b = ncol[s];
+        const int4 vb = vmeta[b];  // row start, N+ start, row end, heavy start of b
+        i32 bb = vb.x, bend = vb.z;
+        nds += bend - bb;
+        dslot[s] = bend - bb;
+        if (s < sp) {
+            i32 m = lower_bound_i32(ncol, vb.y, bend, y);
+            mirror[s] = m;
+            lbeg[s] = bb;
+            wl += m - bb;
+            i32 st = (y >= h0) ? min(m + 1, bend) : vb.w;  // (m = bend only for asymmetric input)
+            hseg[s] = make_int2(st, bend);
+            wh += bend - st;
+        } else {
+            hseg[s] = make_int2(vb.w, bend);
+            wh += bend - vb.w;
+            i32 dpb = bend - vb.y;
+            pr += dpb;
+            mx = max(mx, dpb);
+        }
+    }
+    mirror_row_tail<W>(y, active, l, b0, sp, e0, h0, wl, wh, pr, nds, mx, wlight, wheavy, probes, feat);
+}
+
 // Mirror slots (for each N- slot, the N+ slot of the reverse edge), the per-vertex
 // work of the later passes (4-cycle wedges light and heavy, Stage I probes) and the
 // work-model features.
 __global__ void k_mirror(i32 n, const u32 *__restrict__ ndeg, const i32 *__restrict__ nrp,
                          const i32 *__restrict__ nsplit, const i32 *__restrict__ ncol,
                          const int4 *__restrict__ vmeta, i32 h0, i32 *__restrict__ mirror,
-                         int2 *__restrict__ hseg, i32 *__restrict__ lbeg, i64 *__restrict__ wlight,
-                         i64 *__restrict__ wheavy, i64 *__restrict__ probes, float *__restrict__ feat) {
+                         int2 *__restrict__ hseg, i32 *__restrict__ lbeg, i32 *__restrict__ dslot,
+                         i64 *__restrict__ wlight, i64 *__restrict__ wheavy, i64 *__restrict__ probes,
+                         float *__restrict__ feat) {
     const int waves = gridDim.x * (blockDim.x / WAVE);
     const int wid = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     const i32 cut = first_above(ndeg, n, SG_MAXDEG);
     constexpr int GPW = WAVE / SG;
     for (i32 yb = wid * GPW; yb < cut; yb += waves * GPW) {
         const i32 y = yb + lane_id() / SG;
-        mirror_row<SG>(y, y < cut, lane_id() % SG, nrp, nsplit, ncol, vmeta, h0, mirror, hseg, lbeg, wlight, wheavy,
-                       probes, feat);
+        mirror_row<SG>(y, y < cut, lane_id() % SG, nrp, nsplit, ncol, vmeta, h0, mirror, hseg, lbeg, dslot, wlight,
+                       wheavy, probes, feat);
     }
     for (i32 y = n - 1 - wid; y >= cut; y -= waves)
-        mirror_row<WAVE>(y, true, lane_id(), nrp, nsplit, ncol, vmeta, h0, mirror, hseg, lbeg, wlight, wheavy, probes,
-                         feat);
+        mirror_row<WAVE>(y, true, lane_id(), nrp, nsplit, ncol, vmeta, h0, mirror, hseg, lbeg, dslot, wlight, wheavy,
+                         probes, feat);
 }
