@@ -1238,14 +1238,16 @@ struct QChunk {
 };
 
 // How each 4-cycle kernel locates wedges (0 a search per wedge, 2 a byte map built by
-// seg_map_scan), chosen per kernel by measurement: a map costs LDS, and so occupancy,
-// which the kernels win back by crediting middles straight to Q instead of through
-// per-segment sums in LDS.
+// seg_map_scan, 3 the same map built by q_segmap: one search per thread, then a walk),
+// chosen per kernel by measurement: a map costs LDS, and so occupancy, which the
+// kernels win back by crediting middles straight to Q instead of through per-segment
+// sums in LDS; the walk suits the heavy workgroup kernels, whose long segments make
+// it short, the scan the light ones.
 #define QMAP_QLW 2
 #define QMAP_QLB 2
 #define QMAP_QHW 2
-#define QMAP_QHB 0
-#define QMAP_QD 2
+#define QMAP_QHB 3
+#define QMAP_QD 3
 // Which ones credit middles straight to Q (and so keep no per-segment sums in LDS).
 #define QGMID_QHW 1
 #define QGMID_QHB 0
@@ -1354,7 +1356,7 @@ __device__ __forceinline__ QMeta q_meta(const DevGraph &g, i32 x) {
 // created a key's counter then credits C(c, 2) through cr, adds it to *local and
 // empties the counter, and the call returns true.  Otherwise (false) the counters
 // are left for the caller to harvest.
-// MAP: how wedges find their segments -- 0 a search each, otherwise seg_map_scan.
+// MAP: how wedges find their segments -- 0 a search each, 2 seg_map_scan, 3 q_segmap.
 // GMID: middles' credits go straight to Q (runs of lanes in one segment add once)
 // rather than through C.mid.
 template <int NT, int MODE, int QK = 0, int MAP = 0, bool GMID = false, typename Ctr, typename Credit>
@@ -1371,7 +1373,12 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                 int lo[QK];
                 i32 key[QK];
                 if constexpr (MAP > 0) {
-                    seg_map_scan<NT, QK>(C.off, ns, 0, total, tid, C.seg, red32);
+                    if constexpr (MAP == 3) {
+                        q_segmap<NT, QK>(C.off, ns, 0, total, tid, C.seg);
+                        item_sync<NT>();
+                    } else {
+                        seg_map_scan<NT, QK>(C.off, ns, 0, total, tid, C.seg, red32);
+                    }
 #pragma unroll
                     for (int j = 0; j < QK; j++) lo[j] = j < nj ? seg_at(C.seg, min(tid + j * NT, total - 1)) : 0;
                 } else {
@@ -1467,7 +1474,12 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
                     const i32 mb = eb - eb % (NT * MQ);
                     if (mb == eb) {
                         item_sync<NT>();  // the previous block's map has been read
-                        seg_map_scan<NT, MQ>(C.off, len, eb, total, tid, C.seg, red32);
+                        if constexpr (MAP == 3) {
+                            q_segmap<NT, MQ>(C.off, len, eb, total, tid, C.seg);
+                            item_sync<NT>();
+                        } else {
+                            seg_map_scan<NT, MQ>(C.off, len, eb, total, tid, C.seg, red32);
+                        }
                     }
 #pragma unroll
                     for (int u = 0; u < QS; u++)
