@@ -1456,7 +1456,9 @@ __device__ __forceinline__ bool q_sweeps(const DevGraph &g, const QMeta &mt, con
         for (i32 c0 = 0; c0 < ns; c0 += dc) {
             i32 len = min(dc, ns - c0);
             i32 total;
-            if (pass == 0 || !single) {
+            // a single chunk stays loaded from the register-path check (loading it
+            // again would race with waves still reading its total) and across passes
+            if (!single || (pass == 0 && QK == 0)) {
                 total = q_load_chunk<NT, MODE>(g, x, s0, sp, c0, len, C, tid, red32);
             } else {
                 total = C.off[len];
