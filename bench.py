@@ -201,19 +201,25 @@ def kernel_bytes(kernel, stats):
     return 4 * work + 16 * slots
 
 
-def time_count(ni, ctx, rp, cl, out, flags, steps, warmup):
+def time_count(ni, ctx, rp, cl, out, flags, steps, warmup, timing_steps=3):
+    """Milliseconds per count over `steps` counts as a caller runs them (no event
+    between stages), then stage and kernel times from `timing_steps` further counts
+    with per-stage and per-kernel events."""
     import torch
     for _ in range(warmup):
         ni.count(rp, cl, out=out, ctx=ctx, flags=flags)
     torch.cuda.synchronize()
-    stages, kernels = [], []
     t0 = time.perf_counter()
     for _ in range(steps):
+        ni.count(rp, cl, out=out, ctx=ctx, flags=flags)
+    torch.cuda.synchronize()
+    ms = 1000.0 * (time.perf_counter() - t0) / steps
+    stages, kernels = [], []
+    for _ in range(max(1, min(steps, timing_steps))):
         ni.count(rp, cl, out=out, ctx=ctx, flags=flags | ni.TIMING)
         stages.append(ctx.stage_times())
         kernels.append(ctx.kernel_times())
     torch.cuda.synchronize()
-    ms = 1000.0 * (time.perf_counter() - t0) / steps
     avg_s = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
     avg_k = {k: float(np.mean([s[k] for s in kernels])) for k in kernels[0]}
     return ms, avg_s, avg_k
