@@ -441,6 +441,68 @@ __device__ __forceinline__ PMeta p_meta(const DevGraph &g, const TriCache &tc, i
     return m;
 }
 
+#define PL_NT 1024  // threads of a large Stage I item
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+typedef int v16i32 __attribute__((ext_vector_type(16)));
+
+// Sixteen bits of a bitset row as sixteen 0/1 bytes (bit q -> byte q): each nibble
+// spread by one multiply whose shifted copies (0, 7, 14, 21) never overlap.
+__device__ __forceinline__ v4i32 bits16_to_bytes(u32 w) {
+    v4i32 r;
+    r[0] = (int)(((w & 0xfu) * 0x204081u) & 0x01010101u);
+    r[1] = (int)((((w >> 4) & 0xfu) * 0x204081u) & 0x01010101u);
+    r[2] = (int)((((w >> 8) & 0xfu) * 0x204081u) & 0x01010101u);
+    r[3] = (int)((((w >> 12) & 0xfu) * 0x204081u) & 0x01010101u);
+    return r;
+}
+
+// The 4-clique pass of a large item as a dense contraction: with A the 0/1
+// adjacency of H_u (the bitset, rows of `pitch` words), C = A*A counts the common
+// neighbours of every pair, and sk[j] = sum over i of A[j][i] C[j][i] is twice the
+// number of triangles of H_u through j (the per-slot sums the record pass builds).
+// Each wave takes 32x32 tiles (J, I) with J <= I (C and A are symmetric, so an
+// off-diagonal tile also serves its transpose) and runs one int8 MFMA
+// (32x32x32, 0/1 bytes expanded from sixteen bits per lane) per 32 columns of A:
+// lane l supplies row (or column) l % 32 and the bits (l / 32) * 16 .. + 16 of the
+// word, and accumulator q holds row (q / 4) * 8 + (l / 32) * 4 + q % 4 of column
+// l % 32 (the layout of the 32x32 MFMA forms).  Rows and columns past du read zero.
+template <int NT>
+__device__ __forceinline__ i64 dense_k4_sums(const u32 *A, int pitch, int du, int nw, i32 *sk, int tid) {
+    const int wv = tid / WAVE, l = lane_id();
+    const int nb = (du + 31) >> 5;
+    const int ntiles = nb * (nb + 1) / 2;
+    const int sh = (l >> 5) << 4;
+    i64 words = 0;
+    for (int tix = wv; tix < ntiles; tix += NT / WAVE) {
+        int J = 0, rem = tix;
+        while (rem >= nb - J) {
+            rem -= nb - J;
+            J++;
+        }
+        const int I = J + rem;
+        const int ra = J * 32 + (l & 31), rb = I * 32 + (l & 31);
+        const bool va = ra < du, vb = rb < du;
+        v16i32 acc = {};
+        for (int kw = 0; kw < nw; kw++) {
+            const u32 wa = va ? A[ra * pitch + kw] : 0u;
+            const u32 wb = vb ? A[rb * pitch + kw] : 0u;
+            acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(bits16_to_bytes((wa >> sh) & 0xffffu),
+                                                         bits16_to_bytes((wb >> sh) & 0xffffu), acc, 0, 0, 0);
+        }
+        words += 2 * nw;
+        const int i = I * 32 + (l & 31);
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int j = J * 32 + (q >> 2) * 8 + (l >> 5) * 4 + (q & 3);
+            if (j < du && i < du && acc[q] && ((A[j * pitch + (i >> 5)] >> (i & 31)) & 1u)) {
+                atomicAdd(&sk[j], acc[q]);
+                if (J < I) atomicAdd(&sk[i], acc[q]);
+            }
+        }
+    }
+    return words;
+}
+
 template <int NT, int MODE, int QP, int MP = 0, int MAXDU = (1 << 30), bool WIDE = false>
 __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, int tid, const ProbeMem &M, int hc,
                                            int pitch, i32 *__restrict__ t, i64 *__restrict__ K4,
@@ -552,6 +614,10 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
     item_sync<NT>();
     const bool keep = TRI && S->item_ok;
     const i64 item_base = keep ? S->item_base : 0;
+    // a bitset the 4-clique pass reads from an LDS copy is rebuilt there from the
+    // item's triangle records (each an edge of H_u) after the probes, rather than
+    // built in global memory with two device-scope atomics per hit
+    const bool rebuild = keep && M.A_k4 != M.A;
     i64 tau_local = 0;
     // rounds of NT*QP probes: each thread locates its QP probes together, then
     // issues all their loads before the first hash lookup.  With MP > 0 the
@@ -617,8 +683,10 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
                 atomicAdd(&M.tcnt[i], 1);
                 atomicAdd(&M.tcnt[p], 1);
                 atomicAdd(&t[q], 1);
-                atomicOr(&M.A[i * pitch + (p >> 5)], 1u << (p & 31));
-                atomicOr(&M.A[p * pitch + (i >> 5)], 1u << (i & 31));
+                if (!rebuild) {
+                    atomicOr(&M.A[i * pitch + (p >> 5)], 1u << (p & 31));
+                    atomicOr(&M.A[p * pitch + (i >> 5)], 1u << (i & 31));
+                }
                 if (keep) {
                     i32 r = atomicAdd(&S->item_cnt, 1);
                     tc.rec[item_base + r] = ((u64)(u32)q << 32) | ((u64)p << 16) | (u64)i;
@@ -650,10 +718,36 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
         const u32 *A = M.A_k4;
         if (A != M.A) {
             item_sync<NT>();
-            for (int i = tid; i < du * pitch; i += NT) M.A_k4[i] = M.A[i];
+            if (rebuild) {
+                for (int i = tid; i < du * pitch; i += NT) M.A_k4[i] = 0u;
+                item_sync<NT>();
+                const i64 r1 = item_base + S->item_cnt;
+                for (i64 r = item_base + tid; r < r1; r += NT) {
+                    const u64 rec = tc.rec[r];
+                    const int i = (int)(rec & 0xffffu), p = (int)((rec >> 16) & 0xffffu);
+                    atomicOr(&M.A_k4[i * pitch + (p >> 5)], 1u << (p & 31));
+                    atomicOr(&M.A_k4[p * pitch + (i >> 5)], 1u << (i & 31));
+                }
+            } else {
+                for (int i = tid; i < du * pitch; i += NT) M.A_k4[i] = M.A[i];
+            }
             item_sync<NT>();
         }
-        if (M.k4s && keep) {
+        if (NT == PL_NT && MODE == PROBE_TRI) {
+            // large items: the dense contraction (H_u of such items is dense enough
+            // that A*A on the matrix cores beats an intersection per edge)
+            i32 *sk = M.k4s;
+            item_sync<NT>();
+            for (int j = tid; j < du; j += NT) sk[j] = 0;
+            item_sync<NT>();
+            words_scanned += dense_k4_sums<NT>(A, pitch, du, nw, sk, tid);
+            item_sync<NT>();
+            for (int j = tid; j < du; j += NT) {
+                const i64 sj = sk[j];
+                if (sj) atomic_add_i64(&K4[M.nb ? M.nb[j] : g.ncol[base + j]], sj >> 1);
+                s_local += sj;
+            }
+        } else if (M.k4s && keep) {
             // every edge (i, p) of H_u once, from this item's triangle records: the
             // common neighbours of i and p in H_u close triangles of H_u through both,
             // summed per slot in k4s (which may share the spent tcnt)
@@ -968,7 +1062,6 @@ __global__ void __launch_bounds__(256) k_probe_thread(DevGraph g, const i32 *__r
 // bitset of H_u built in the global slice and copied into the same LDS (over the
 // hash) for the 4-clique pass; 1 -- as 2 but the 4-clique pass reads the global
 // bitset; 0 -- everything but the reductions in the global slice.
-#define PL_NT 1024
 __host__ __device__ inline i64 probe_large_lds_bytes(int cap, int hc) {
     return (i64)sizeof(i32) * (2 * (i64)hc + 4 * (i64)cap + 1);
 }
