@@ -396,6 +396,8 @@ struct ProbeMem {
                  // (nb may be null too: then neighbours are read from the row again)
     i32 *k4s;    // [cap] per-slot sums of the 4-clique pass over triangle records, or
                  // null for the scan over bitset rows
+    i64 *acc_rec;  // [cap] per-slot sums of the tau pass over cached triangle records: acc
+                   // itself, or LDS over the hash that this pass does not use
 };
 
 // Triangle records kept by Stage I for the tau pass: one u64 per triangle found at
@@ -514,10 +516,11 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
     if (MODE == PROBE_TAU && pm.tcnt == 0) return;  // no triangle at u: nothing to add
     if (MODE == PROBE_TAU && pm.tcnt >= 0) {
         // cached triangles: tau from the records and the final t values
+        i64 *const acc = M.acc_rec;
         for (int i = tid; i < du; i += NT) {
             M.nb[i] = g.ncol[base + i];
             M.tcnt[i] = t[base + i];
-            M.acc[i] = 0;
+            acc[i] = 0;
         }
         item_sync<NT>();
         const i64 r0 = pm.toff, r1 = r0 + pm.tcnt;
@@ -539,14 +542,14 @@ __device__ __forceinline__ void probe_item(const DevGraph &g, const PMeta &pm, i
                 const bool ok = rec[k] != ~0ull;
                 const int i = ok ? (int)(rec[k] & 0xffffu) : 0, p = ok ? (int)((rec[k] >> 16) & 0xffffu) : 0;
                 tau_local += tq[k];
-                if constexpr (NT >= WAVE) wave_run_add(M.acc, i, ok ? M.tcnt[p] : 0);
-                else if (ok) atomicAdd((unsigned long long *)&M.acc[i], (unsigned long long)M.tcnt[p]);
-                if (ok) atomicAdd((unsigned long long *)&M.acc[p], (unsigned long long)M.tcnt[i]);
+                if constexpr (NT >= WAVE) wave_run_add(acc, i, ok ? M.tcnt[p] : 0);
+                else if (ok) atomicAdd((unsigned long long *)&acc[i], (unsigned long long)M.tcnt[p]);
+                if (ok) atomicAdd((unsigned long long *)&acc[p], (unsigned long long)M.tcnt[i]);
             }
         }
         item_sync<NT>();
         for (int j = tid; j < du; j += NT) {
-            i64 a = M.acc[j];
+            i64 a = acc[j];
             if (a) atomic_add_i64(&tau[M.nb[j]], a);
         }
         i64 s = item_sum<NT>(tau_local, red, tid);
@@ -859,7 +862,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PW_WPE
     __shared__ u32 s_seg[4][PW_MP > 0 ? WAVE * PW_MP / 4 : 1];
     __shared__ ItemState s_st[4];
     const int w = threadIdx.x / WAVE, tid = lane_id();
-    ProbeMem M{s_hkey[w], s_hpos[w], s_off[w], s_nb[w], s_beg[w], s_tcnt[w], s_A[w], s_acc[w], s_A[w], s_seg[w]};
+    ProbeMem M{s_hkey[w], s_hpos[w], s_off[w], s_nb[w], s_beg[w], s_tcnt[w], s_A[w], s_acc[w], s_A[w], s_seg[w], nullptr,
+               s_acc[w]};
     if (tid == 0) {
         s_st[w].chunk_cur = s_st[w].chunk_end = 0;
         s_st[w].full = 0;
@@ -899,7 +903,8 @@ __global__ void __launch_bounds__(256) k_probe_group(DevGraph g, const i32 *__re
     __shared__ i64 s_acc[NG][CAP];
     __shared__ ItemState s_st[NG];
     const int gr = threadIdx.x / PG_NT, tid = threadIdx.x % PG_NT;
-    ProbeMem M{s_hkey[gr], s_hpos[gr], s_off[gr], s_nb[gr], s_beg[gr], s_tcnt[gr], s_A[gr], s_acc[gr], s_A[gr]};
+    ProbeMem M{s_hkey[gr], s_hpos[gr], s_off[gr], s_nb[gr], s_beg[gr], s_tcnt[gr], s_A[gr], s_acc[gr], s_A[gr],
+               nullptr, nullptr, s_acc[gr]};
     if (tid == 0) {
         s_st[gr].chunk_cur = s_st[gr].chunk_end = 0;
         s_st[gr].full = 0;
@@ -940,7 +945,7 @@ __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__
     __shared__ ItemState s_st;
     // the triangle pass reads neighbours from the row again (its LDS is full)
     ProbeMem M{s_hkey, s_hpos, s_off, MODE != PROBE_TAU ? nullptr : s_nb, s_beg, s_tcnt, s_A, s_acc, s_A, s_seg,
-               s_tcnt};
+               s_tcnt, s_acc};
     if (threadIdx.x == 0) {
         s_st.chunk_cur = s_st.chunk_end = 0;
         s_st.full = 0;
@@ -1108,6 +1113,9 @@ __global__ void __launch_bounds__(PL_NT) k_probe_large(DevGraph g, const i32 *__
         M.tcnt = (i32 *)q;
         M.k4s = M.tcnt;
     }
+    // the tau pass over cached records keeps its sums in LDS over hkey and hpos (8 hc >= 16 cap
+    // bytes, the start rounded up to 8 bytes), which that pass leaves unused
+    M.acc_rec = LAY == 0 ? M.acc : (i64 *)(s_dyn + (LAY == 2 ? (sizeof(i32) * (i64)cap + 7) & ~7ll : 0));
     __shared__ ItemState s_st;
     if (threadIdx.x == 0) {
         s_st.chunk_cur = s_st.chunk_end = 0;
