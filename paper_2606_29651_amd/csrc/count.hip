@@ -2046,7 +2046,7 @@ __global__ void __launch_bounds__(QD_NT) __attribute__((amdgpu_waves_per_eu(QD_W
 
 // Light largest vertices whose wedges overflow the LDS hash: int32 counters over
 // [0, n) in per-workgroup global scratch, touched keys listed for clearing.
-#define QG_NT 256
+#define QG_NT 1024  // one workgroup per CU (a counter slice each): sixteen waves to hide the atomics' latency
 #define QG_DC 1024
 template <int MODE>
 __global__ void __launch_bounds__(QG_NT) k_q_global(DevGraph g, const i32 *__restrict__ list,
