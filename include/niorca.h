@@ -90,7 +90,8 @@ uint64_t niorca_workspace_bytes(const niorca_ctx *ctx);
 /* Tuning knobs of the work classes (they change which kernel shape handles a vertex,
  * never a count).  Names and ranges:
  *   "tri_wave"  1..64    vertices with |N+| up to this use one wave (Stage I/II, tau)
- *   "tri_block" 1..512   ... up to this one workgroup with LDS; above, global scratch
+ *   "tri_block" 1..480   ... up to this one workgroup with LDS; above, one 1024-thread
+ *                        workgroup per vertex (LDS where it fits, else global scratch)
  *   "ql_wave"   0..2048  4-cycle wedges (largest vertex light) up to this: wave hash
  *                        (default 512; the per-wave table is sized from it)
  *   "ql_block"  0..8192  ... up to this: workgroup hash (default 8192, table sized

@@ -15,7 +15,7 @@ import os
 import time
 from typing import Callable, Dict, Iterable, List
 
-DEFAULTS = {"tri_wave": 64, "tri_block": 512, "ql_wave": 512, "ql_block": 8192, "ql_split": 2048,
+DEFAULTS = {"tri_wave": 64, "tri_block": 480, "ql_wave": 512, "ql_block": 8192, "ql_split": 2048,
             "qh_wave": 512, "qh_block": 2048, "heavy_k": -1, "bin_mode": 0, "bin_deg_thread": 0,
             "bin_deg_group": 32, "bin_deg_block": 1 << 30}
 

@@ -661,7 +661,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
         i64 *ek4 = (i64 *)(W + L.ek4);
         HIP_TRY(fill32(ek4, sizeof(i64) * nnz, 0u, s));
         HIP_TRY(launch_probe(2, g, lh, dst, t, acc.K4, ek4, tca, large_scratch, L.large_slice, L.large_cap,
-                             L.large_hc, L.large_blocks, ctx->large_lds_max, cu * 8, cu * 2, nullptr, nokev, s));
+                             L.large_hc, L.large_blocks, ctx->large_lds_max, cu * 8, cu * PB_GRID, nullptr, nokev, s));
         hipLaunchKernelGGL(k_slot_to_input<i64>, dim3(cu * 8), dim3(nthr), 0, s, n, rp, col, perm, g,
                            (const i64 *)ek4, o.ek4);
         HIP_TRY(hipGetLastError());
@@ -669,7 +669,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
         return NIORCA_OK;
     }
     HIP_TRY(launch_probe(0, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, L.large_slice, L.large_cap,
-                         L.large_hc, L.large_blocks, ctx->large_lds_max, cu * 8, cu * 2, counters, kev, s));
+                         L.large_hc, L.large_blocks, ctx->large_lds_max, cu * 8, cu * PB_GRID, counters, kev, s));
     STAGE_MARK(5);
     if (o.tri) {
         hipLaunchKernelGGL(k_slot_to_input<i32>, dim3(cu * 8), dim3(nthr), 0, s, n, rp, col, perm, g,
@@ -690,7 +690,7 @@ static niorca_status run(niorca_ctx *ctx, int32_t n, int64_t nnz, const int64_t 
     HIP_TRY(launch_sums(g, t, acc, cu * 8, s));
     STAGE_MARK(6);
     HIP_TRY(launch_probe(1, g, lh, dst, t, acc.K4, acc.tau, tca, large_scratch, L.large_slice, L.large_cap,
-                         L.large_hc, L.large_blocks, ctx->large_lds_max, cu * 8, cu * 2, nullptr, nokev, s));
+                         L.large_hc, L.large_blocks, ctx->large_lds_max, cu * 8, cu * PB_GRID_TAU, nullptr, nokev, s));
     STAGE_MARK(7);
     if (n - h0 > 0) HIP_TRY(fill32(qpart, (i64)sizeof(i64) * L.part_rows * (n - h0), 0u, s));
     HIP_TRY(launch_q(g, lh, dst, acc.Q, gscratch, L.gslice, L.gblocks, cu * 4, cu * 4, cu * 2, qpart, L.part_rows,

@@ -930,7 +930,8 @@ template <int MODE>
 __global__ void __launch_bounds__(PB_NT) k_probe_block(DevGraph g, const i32 *__restrict__ list,
                                                      const GraphStats *__restrict__ st, i32 *t, i64 *K4,
                                                      i64 *tau, TriCache tc, i64 *counters) {
-    constexpr int CAP = TRI_BLOCK_CAP, HC = 2 * CAP, PITCH = bit_pitch(CAP);
+    constexpr int CAP = TRI_BLOCK_CAP, HC = 1024, PITCH = bit_pitch(CAP);
+    static_assert(HC >= 2 * CAP && (HC & (HC - 1)) == 0, "the hash: a power of two, at most half full");
     __shared__ i32 s_hkey[HC];
     __shared__ i32 s_hpos[HC];
     __shared__ i32 s_off[CAP + 1];

@@ -78,7 +78,9 @@ struct Thresholds {
 // Class capacities (shared by classification and kernels).
 #define TRI_WAVE_CAP 64
 #define TRI_GROUP_CAP 16
-#define TRI_BLOCK_CAP 512
+#define TRI_BLOCK_CAP 480  // 51 KB of LDS per workgroup item, so three share a CU's 160 KB
+#define PB_GRID 3          // workgroups per CU of the Stage I/II workgroup kernel
+#define PB_GRID_TAU 2      // ... and of its tau pass (more per CU measured no faster)
 #define QL_WAVE_HC 4096     // largest hash per wave, light 4-cycle items (sized per launch)
 #define QL_WAVE_DC 64       // segment (row slot) capacity per wave item
 #define QL_BLOCK_HC 16384    // largest hash per workgroup, light 4-cycle items (sized per launch)

@@ -174,7 +174,7 @@ def test_edge_k4_matches_oracle(ni, ora, name, mode):
 
 @pytest.mark.parametrize("n,large_lds", [(600, None), (600, 0), (1100, None)])
 def test_edge_k4_complete_closed_form(ni, n, large_lds):
-    """K_n: every edge lies in C(n-2, 2) 4-cliques; |N+| reaches n-1 > 512, the
+    """K_n: every edge lies in C(n-2, 2) 4-cliques; |N+| reaches n-1 > 480, the
     global-scratch Stage I class (large_lds = 0: everything in global memory)."""
     import torch
     g = gg.complete(n)

@@ -73,7 +73,7 @@ def _dev(g):
 
 def bipartite_matched(a):
     """K_{a,a} plus a perfect matching on the right side and one left-left edge:
-    left vertex 0 then has a+1 > 512 neighbours that all rank above it (the
+    left vertex 0 then has a+1 > 480 neighbours that all rank above it (the
     global-scratch Stage I class), with triangles and a few 4-cliques."""
     left = np.repeat(np.arange(a), a)
     right = a + np.tile(np.arange(a), a)
@@ -207,7 +207,7 @@ def kn_row(n):
 @pytest.mark.parametrize("n,large_lds", [(600, None), (1500, None), (600, 30000), (600, 0)])
 def test_complete_graph_closed_form(ni, n, large_lds):
     """K_n: every vertex has the same 15 counts, derived by counting (no oracle).
-    |N+| reaches n-1 > 512, so the top vertices use the large class; large_lds picks
+    |N+| reaches n-1 > 480, so the top vertices use the large class; large_lds picks
     its layout (default: bitset copied to LDS for the 4-clique pass; 30000: hash in
     LDS, bitset in global memory; 0: all in global memory)."""
     g = gg.complete(n)
