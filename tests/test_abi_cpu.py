@@ -61,3 +61,15 @@ def test_committed_tuning_file_parses():
     path = os.path.join(ROOT, "paper_2606_29651_amd", "tuning.txt")
     got = autotune.load(path, "batch_mix")
     assert got and set(got) <= set(autotune.DEFAULTS)
+
+
+def test_documented_class_bounds_match_the_kernels():
+    """The header's ranges for the Stage I class knobs and the autotuner's defaults
+    are the class capacities the kernels are compiled for."""
+    caps = dict(re.findall(r"#define (TRI_WAVE_CAP|TRI_BLOCK_CAP) (\d+)",
+                           open(os.path.join(ROOT, "paper_2606_29651_amd", "csrc", "kernels.hpp")).read()))
+    doc = dict(re.findall(r'"(tri_wave|tri_block)"\s+1\.\.(\d+)', open(HEADER).read()))
+    assert doc == {"tri_wave": caps["TRI_WAVE_CAP"], "tri_block": caps["TRI_BLOCK_CAP"]}
+    from paper_2606_29651_amd.autotune import DEFAULTS
+    assert DEFAULTS["tri_wave"] == int(caps["TRI_WAVE_CAP"])
+    assert DEFAULTS["tri_block"] == int(caps["TRI_BLOCK_CAP"])
